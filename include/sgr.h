@@ -1,0 +1,226 @@
+/*
+ * sgr.h -- C ABI of the MI355X semantic Gaussian rasterizer and view scorer.
+ *
+ * The operations follow "Understanding while Exploring: Semantics-driven
+ * Active Mapping" (arXiv 2506.00225):
+ *   - Sec. 3.1 "Gaussian Mapping": Gaussians are transformed into camera
+ *     space, sorted front to back, projected and alpha-composited (Eq. 1)
+ *     into colour C, depth D and silhouette S;
+ *   - Sec. 3.1 "Sparse Semantic Representation" / "Semantic Rendering":
+ *     each Gaussian carries k (class index, probability) pairs whose values
+ *     are composited into a full C-class map (Eq. 3);
+ *   - Sec. 3.1: the renderer is differentiable; the semantic loss reaches
+ *     only the semantic attributes;
+ *   - Sec. 3.2: candidate views are scored by the number of pixels with
+ *     zero silhouette (Eq. 5) and by the summed per-pixel entropy (Eq. 4,
+ *     Eq. 6) of the clipped, renormalised semantic map.
+ *
+ * Conventions (all calls):
+ *   - Every array pointer is a DEVICE pointer owned by the caller, unless
+ *     it is documented as a host pointer.  `cams` and every struct passed
+ *     by pointer are HOST memory, read during the call only.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ *     the default stream).  Errors found on the host are returned before
+ *     anything is enqueued.  Errors found on the device (key capacity) are
+ *     recorded in a status word inside the workspace; read it with
+ *     sgr_read_status (which synchronises the stream).
+ *   - The library allocates no device memory.  All scratch lives in the
+ *     caller's workspace, whose size is sgr_workspace_size(...).  Its
+ *     layout is a pure function of (n, cams' sizes, num_views, cfg,
+ *     key_capacity): the calls of one frame must receive the same values.
+ *   - Calls on one workspace must be ordered on one stream; two frames in
+ *     flight need two workspaces.
+ *   - Gaussian parameters are post-activation: scales are linear metres,
+ *     opacity in (0,1), quaternions (w,x,y,z) need not be normalised
+ *     (they are normalised inside sgr_project and the gradient includes
+ *     the normalisation).
+ *   - Camera: R is world->camera, row-major; camera x right, y down, z
+ *     forward; pixel (col,row) has its centre at (col+0.5, row+0.5).
+ *   - Images are channel-last, row-major: rgb [H][W][3], depth/sil/t_final/
+ *     n_contrib [H][W], sem [H][W][C].
+ */
+#ifndef SGR_H
+#define SGR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SGR_OK = 0,
+    SGR_EINVAL = 1,       /* invalid argument, detected on the host */
+    SGR_ECAPACITY = 2,    /* more tile keys than key_capacity (device-side) */
+    SGR_EHIP = 3,         /* a HIP runtime call failed */
+    SGR_EUNSUPPORTED = 4  /* valid but unsupported (e.g. tile size) */
+} sgr_status;
+
+typedef struct {
+    float R[9];        /* world -> camera rotation, row-major */
+    float t[3];        /* world -> camera translation */
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} sgr_camera;
+
+typedef struct {
+    float alpha_min;   /* skip a Gaussian whose alpha is below this (1/255) */
+    float alpha_max;   /* opacity clamp (0.99) */
+    float t_min;       /* stop before transmittance would drop below this (1e-4) */
+    float z_near;      /* cull Gaussians whose camera-space z is <= this (0.2 m) */
+    float lowpass;     /* screen-space low-pass added to the 2D covariance (0.3 px^2) */
+    int32_t num_classes;          /* C, 1..256 */
+    int32_t top_k;                /* k, 1..32 */
+    int32_t sem_grad_to_geometry; /* 0: semantic channels do not reach alpha (Sec. 3.1) */
+    int32_t tile_w, tile_h;       /* 0 or 16 (the only supported tile) */
+} sgr_config;
+
+typedef struct {
+    int64_t n;
+    const float *means;    /* [n][3] */
+    const float *scales;   /* [n][3] */
+    const float *quats;    /* [n][4] (w,x,y,z) */
+    const float *opacity;  /* [n] */
+    const float *rgb;      /* [n][3] */
+    const float *sem_val;  /* [n][k] */
+    const uint8_t *sem_idx;/* [n][k] class indices < C */
+} sgr_gaussians;
+
+/* Per-view output maps of sgr_render_forward.  Any pointer may be NULL to
+ * skip that output (t_final and n_contrib are still kept internally for the
+ * backward pass). */
+typedef struct {
+    float *rgb, *depth, *sil, *sem, *t_final;
+    int32_t *n_contrib;
+} sgr_maps;
+
+/* Per-view incoming gradients dL/d(map) for sgr_render_backward.  A NULL
+ * pointer means a zero gradient for that map. */
+typedef struct {
+    const float *rgb, *depth, *sil, *sem;
+} sgr_map_grads;
+
+/* Gradient outputs (same layouts as sgr_gaussians), overwritten, summed over
+ * views.  A NULL pointer skips that output. */
+typedef struct {
+    float *means, *scales, *quats, *opacity, *rgb, *sem_val;
+} sgr_grads;
+
+/* Byte offsets of named arrays inside the workspace (for inspection and
+ * tests).  Counts are element capacities. */
+typedef struct {
+    size_t total_bytes;
+    size_t counters;        /* uint32: [0] status, [1] visible, [2] keys, ... */
+    size_t views;           /* per-view device table */
+    size_t proj_count;      /* uint32 [V*n]: tiles touched per (view, Gaussian); 0 = culled */
+    size_t proj_zbits;      /* uint32 [V*n]: bits of fp32 camera-space z */
+    size_t proj_rec;        /* 3 x float4 [V*n]: projected record */
+    size_t order;           /* uint32 [V*n]: (view*n + id) of each visible pair, front to back */
+    size_t sorted_keys;     /* uint32 [key_capacity]: global tile id, sorted */
+    size_t sorted_vals;     /* uint32 [key_capacity]: emission index of each sorted key */
+    size_t sorted_gauss;    /* uint32 [key_capacity]: front-to-back index of each sorted key */
+    size_t ranges;          /* uint32 [num_tiles][2]: [start, end) per global tile */
+    size_t tile_offsets;    /* uint32 [V*n]: first emission index of each visible pair */
+    int64_t num_tiles;      /* sum over views of tiles_x * tiles_y */
+    int64_t num_pixels;     /* sum over views of W * H */
+    int64_t vn;             /* V * n */
+} sgr_layout;
+
+/* Workspace size in bytes for a frame; 0 if the arguments are invalid. */
+size_t sgr_workspace_size(int64_t n, const sgr_camera *cams, int32_t num_views, const sgr_config *cfg,
+                          int64_t key_capacity);
+
+/* Fills `out` with the workspace layout for these arguments. */
+sgr_status sgr_workspace_layout(int64_t n, const sgr_camera *cams, int32_t num_views, const sgr_config *cfg,
+                                int64_t key_capacity, sgr_layout *out);
+
+/*
+ * sgr_project -- Sec. 3.1 (camera transform, EWA projection to a 2D conic,
+ * front-to-back depth order).  For every (view, Gaussian): camera-space
+ * p = R mu + t; culled when p.z <= z_near, det(Sigma2) <= 0, opacity <
+ * alpha_min or an empty pixel rectangle; Sigma2 = J R Sigma3 R^T J^T +
+ * lowpass*I, Sigma3 = Rq diag(s^2) Rq^T; the pixel rectangle is the exact
+ * axis-aligned box of {o exp(-Q/2) >= alpha_min}, Q = d^T Sigma2^-1 d,
+ * computed in double precision.  Visible pairs are then sorted by (fp32 z
+ * bits, Gaussian id) per view and their records gathered in that order.
+ */
+sgr_status sgr_project(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views, const sgr_config *cfg,
+                       int64_t key_capacity, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * sgr_bin -- tile binning (Sec. 3.1: Gaussians are composited in depth
+ * order, nearest first, here per tile).  Emits one key per (visible pair, 16x16 tile its pixel rectangle
+ * touches), sorts the keys by (view, tile) with a stable on-device radix
+ * sort so each tile's list stays front to back, and builds [start, end) per
+ * tile.  If d_num_keys is not NULL the key count K is written there
+ * (device int64).  K > key_capacity sets SGR_ECAPACITY in the status word
+ * and the later calls of the frame do no work.
+ */
+sgr_status sgr_bin(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views, const sgr_config *cfg,
+                   int64_t key_capacity, int64_t *d_num_keys, void *workspace, size_t workspace_bytes,
+                   void *stream);
+
+/*
+ * sgr_render_forward -- Eq. 1 (colour, depth, silhouette) and Eq. 3
+ * (semantics) per pixel, front to back: alpha = min(alpha_max, o G); skip
+ * when alpha < alpha_min; stop, without blending, when T (1 - alpha) <
+ * t_min; otherwise add z alpha T and set T <- T (1 - alpha).  `out` is an
+ * array of num_views sgr_maps.  n_contrib counts blended Gaussians and
+ * t_final is the final transmittance.
+ */
+sgr_status sgr_render_forward(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views,
+                              const sgr_config *cfg, int64_t key_capacity, const sgr_maps *out,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * sgr_render_backward -- gradient of sum_views sum_p <dL[v](p), maps[v](p)>
+ * with respect to means, scales, quats, opacity, rgb and sem_val, walking
+ * each pixel's blended list back to front from the saved final
+ * transmittance.  With sem_grad_to_geometry = 0 the semantic maps reach
+ * only sem_val (Sec. 3.1).  Must follow sgr_render_forward on the same
+ * workspace.  `dL` is an array of num_views sgr_map_grads.  Gradients of
+ * each tile are reduced inside the tile and summed per Gaussian in a fixed
+ * order: the result is bitwise reproducible.
+ */
+sgr_status sgr_render_backward(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views,
+                               const sgr_config *cfg, int64_t key_capacity, const sgr_map_grads *dL,
+                               const sgr_grads *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * sgr_score_views -- Sec. 3.2, Eq. 4-6: for each of num_views candidate
+ * views (sizes may differ), render the silhouette and semantics without
+ * writing maps and reduce per view: n_empty[v] = number of pixels where no
+ * Gaussian is blended (S = 0), entropy_sum[v] = sum over pixels of
+ * H = -sum_m q_m ln q_m with q = clip(P, 0.001, 1) renormalised over all C
+ * classes.  Runs sgr_project and sgr_bin itself; the compositing of every
+ * (view, tile) runs in one persistent launch.  n_empty, entropy_sum are
+ * device arrays [num_views].
+ */
+sgr_status sgr_score_views(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views,
+                           const sgr_config *cfg, int64_t key_capacity, uint32_t *n_empty, double *entropy_sum,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * sgr_score_maps -- the same per-view reduction as sgr_score_views from an
+ * already rendered dense map of one view (sem [H][W][C], n_contrib [H][W]);
+ * writes n_empty[0] and entropy_sum[0] (device).  Used by the plain
+ * one-view-per-launch path.  The workspace (sgr_score_maps_workspace_size
+ * bytes, 256-byte aligned) holds per-block partial sums.
+ */
+size_t sgr_score_maps_workspace_size(int32_t width, int32_t height);
+sgr_status sgr_score_maps(const float *sem, const int32_t *n_contrib, int32_t width, int32_t height,
+                          int32_t num_classes, uint32_t *n_empty, double *entropy_sum, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* Synchronises `stream` and reads the status word, the visible-pair count
+ * and the key count of the workspace (host outputs; any may be NULL). */
+sgr_status sgr_read_status(const void *workspace, void *stream, int64_t *num_visible, int64_t *num_keys);
+
+const char *sgr_status_string(sgr_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGR_H */

@@ -1,0 +1,13 @@
+"""MI355X-native semantic Gaussian rasterizer and candidate-view scorer.
+
+The hot path (projection, tile binning with an on-device radix sort,
+front-to-back compositing of colour / depth / silhouette / sparse top-k
+semantics, its backward pass, and batched view scoring) runs in the HIP
+library libsgr.so behind the C ABI of include/sgr.h; this package only
+marshals arguments and takes device memory and streams from PyTorch.
+"""
+from . import _lib
+from ._lib import SgrError
+from .rasterizer import Frame, Gaussians, camera_array, make_config, render, score_maps
+
+__all__ = ["Frame", "Gaussians", "SgrError", "camera_array", "make_config", "render", "score_maps", "_lib"]

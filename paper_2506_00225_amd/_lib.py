@@ -1,0 +1,173 @@
+"""ctypes binding of libsgr.so (include/sgr.h), argument marshalling only.
+
+Every function here has the name and argument order of the C entry point it
+wraps.  There is no fallback: if the library is missing or does not load,
+`lib()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsgr.so")
+
+c_float_p = ctypes.POINTER(ctypes.c_float)
+P = ctypes.c_void_p
+
+SGR_OK, SGR_EINVAL, SGR_ECAPACITY, SGR_EHIP, SGR_EUNSUPPORTED = 0, 1, 2, 3, 4
+
+
+class sgr_camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class sgr_config(ctypes.Structure):
+    _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
+                ("z_near", ctypes.c_float), ("lowpass", ctypes.c_float), ("num_classes", ctypes.c_int32),
+                ("top_k", ctypes.c_int32), ("sem_grad_to_geometry", ctypes.c_int32), ("tile_w", ctypes.c_int32),
+                ("tile_h", ctypes.c_int32)]
+
+
+class sgr_gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("means", P), ("scales", P), ("quats", P), ("opacity", P), ("rgb", P),
+                ("sem_val", P), ("sem_idx", P)]
+
+
+class sgr_maps(ctypes.Structure):
+    _fields_ = [("rgb", P), ("depth", P), ("sil", P), ("sem", P), ("t_final", P), ("n_contrib", P)]
+
+
+class sgr_map_grads(ctypes.Structure):
+    _fields_ = [("rgb", P), ("depth", P), ("sil", P), ("sem", P)]
+
+
+class sgr_grads(ctypes.Structure):
+    _fields_ = [("means", P), ("scales", P), ("quats", P), ("opacity", P), ("rgb", P), ("sem_val", P)]
+
+
+class sgr_layout(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_size_t) for name in (
+        "total_bytes", "counters", "views", "proj_count", "proj_zbits", "proj_rec", "order", "sorted_keys",
+        "sorted_vals", "sorted_gauss", "ranges", "tile_offsets")] + [
+        ("num_tiles", ctypes.c_int64), ("num_pixels", ctypes.c_int64), ("vn", ctypes.c_int64)]
+
+
+EXPORTS = (
+    "sgr_workspace_size", "sgr_workspace_layout", "sgr_project", "sgr_bin", "sgr_render_forward",
+    "sgr_render_backward", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
+    "sgr_read_status", "sgr_status_string",
+)
+
+_lib = None
+
+
+def lib():
+    """Loads libsgr.so; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libsgr.so not found at {LIB_PATH}: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    cam_p, cfg_p = ctypes.POINTER(sgr_camera), ctypes.POINTER(sgr_config)
+    g_p = ctypes.POINTER(sgr_gaussians)
+    L.sgr_workspace_size.argtypes = [i64, cam_p, i32, cfg_p, i64]
+    L.sgr_workspace_size.restype = sz
+    L.sgr_workspace_layout.argtypes = [i64, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_layout)]
+    L.sgr_workspace_layout.restype = i32
+    L.sgr_project.argtypes = [g_p, cam_p, i32, cfg_p, i64, P, sz, P]
+    L.sgr_project.restype = i32
+    L.sgr_bin.argtypes = [g_p, cam_p, i32, cfg_p, i64, P, P, sz, P]
+    L.sgr_bin.restype = i32
+    L.sgr_render_forward.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_maps), P, sz, P]
+    L.sgr_render_forward.restype = i32
+    L.sgr_render_backward.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_map_grads),
+                                      ctypes.POINTER(sgr_grads), P, sz, P]
+    L.sgr_render_backward.restype = i32
+    L.sgr_score_views.argtypes = [g_p, cam_p, i32, cfg_p, i64, P, P, P, sz, P]
+    L.sgr_score_views.restype = i32
+    L.sgr_score_maps_workspace_size.argtypes = [i32, i32]
+    L.sgr_score_maps_workspace_size.restype = sz
+    L.sgr_score_maps.argtypes = [P, P, i32, i32, i32, P, P, P, sz, P]
+    L.sgr_score_maps.restype = i32
+    L.sgr_read_status.argtypes = [P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.sgr_read_status.restype = i32
+    L.sgr_status_string.argtypes = [i32]
+    L.sgr_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+class SgrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        msg = lib().sgr_status_string(int(status)).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+def check(status: int, where: str) -> None:
+    if status != SGR_OK:
+        raise SgrError(status, where)
+
+
+# ---------------------------------------------------------------- same-name wrappers
+
+def sgr_workspace_size(n, cams, num_views, cfg, key_capacity):
+    return lib().sgr_workspace_size(n, cams, num_views, ctypes.byref(cfg), key_capacity)
+
+
+def sgr_workspace_layout(n, cams, num_views, cfg, key_capacity):
+    out = sgr_layout()
+    check(lib().sgr_workspace_layout(n, cams, num_views, ctypes.byref(cfg), key_capacity, ctypes.byref(out)),
+          "sgr_workspace_layout")
+    return out
+
+
+def sgr_project(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, stream):
+    return lib().sgr_project(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, workspace,
+                             workspace_bytes, stream)
+
+
+def sgr_bin(g, cams, num_views, cfg, key_capacity, d_num_keys, workspace, workspace_bytes, stream):
+    return lib().sgr_bin(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, d_num_keys, workspace,
+                         workspace_bytes, stream)
+
+
+def sgr_render_forward(g, cams, num_views, cfg, key_capacity, maps, workspace, workspace_bytes, stream):
+    return lib().sgr_render_forward(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, maps,
+                                    workspace, workspace_bytes, stream)
+
+
+def sgr_render_backward(g, cams, num_views, cfg, key_capacity, dl, grads, workspace, workspace_bytes, stream):
+    return lib().sgr_render_backward(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, dl,
+                                     ctypes.byref(grads), workspace, workspace_bytes, stream)
+
+
+def sgr_score_views(g, cams, num_views, cfg, key_capacity, n_empty, entropy_sum, workspace, workspace_bytes, stream):
+    return lib().sgr_score_views(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, n_empty,
+                                 entropy_sum, workspace, workspace_bytes, stream)
+
+
+def sgr_score_maps_workspace_size(width, height):
+    return lib().sgr_score_maps_workspace_size(width, height)
+
+
+def sgr_score_maps(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, workspace, workspace_bytes,
+                   stream):
+    return lib().sgr_score_maps(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, workspace,
+                                workspace_bytes, stream)
+
+
+def sgr_read_status(workspace, stream):
+    nv, nk = ctypes.c_int64(0), ctypes.c_int64(0)
+    st = lib().sgr_read_status(workspace, stream, ctypes.byref(nv), ctypes.byref(nk))
+    return st, nv.value, nk.value
+
+
+def sgr_status_string(status):
+    return lib().sgr_status_string(int(status)).decode()

@@ -1,0 +1,326 @@
+// C ABI: argument validation (host only, before any HIP call), workspace
+// planning and dispatch.
+#include <cmath>
+#include <mutex>
+
+#include "pipeline.h"
+#include "render_common.h"
+#include "sort.h"
+
+namespace sgr {
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static bool finite_cam(const sgr_camera& c) {
+    for (int i = 0; i < 9; i++)
+        if (!std::isfinite(c.R[i])) return false;
+    for (int i = 0; i < 3; i++)
+        if (!std::isfinite(c.t[i])) return false;
+    return std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) && std::isfinite(c.cy) && c.fx != 0.f &&
+           c.fy != 0.f;
+}
+
+sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_config* cfg, int64_t cap, Plan* P) {
+    if (!cams || !cfg || !P || n < 0 || V < 1 || cap < 1) return SGR_EINVAL;
+    if (cfg->num_classes < 1 || cfg->num_classes > kMaxC || cfg->top_k < 1 || cfg->top_k > kMaxK) return SGR_EINVAL;
+    if (!(cfg->alpha_min > 0.f) || !(cfg->alpha_max > cfg->alpha_min) || !(cfg->alpha_max < 1.f) ||
+        !(cfg->t_min > 0.f) || !(cfg->t_min < 1.f) || !(cfg->z_near > 0.f) || !std::isfinite(cfg->z_near) ||
+        !(cfg->lowpass >= 0.f) || !std::isfinite(cfg->lowpass))
+        return SGR_EINVAL;
+    if ((cfg->tile_w != 0 && cfg->tile_w != kTile) || (cfg->tile_h != 0 && cfg->tile_h != kTile))
+        return SGR_EUNSUPPORTED;
+    const int64_t vn = n * (int64_t)V;
+    if (vn >= (int64_t)1 << 31 || cap >= (int64_t)1 << 31) return SGR_EINVAL;
+    P->n = n;
+    P->V = V;
+    P->vn = vn;
+    P->cap = cap;
+    P->k = cfg->top_k;
+    P->kpad = (cfg->top_k + 3) & ~3;
+    P->C = cfg->num_classes;
+    P->cfg = *cfg;
+    P->view_table.assign(V, ViewDev{});
+    int64_t tiles = 0, pixels = 0;
+    for (int v = 0; v < V; v++) {
+        const sgr_camera& c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 32767 || c.height > 32767 || !finite_cam(c)) return SGR_EINVAL;
+        ViewDev& d = P->view_table[v];
+        memcpy(d.R, c.R, sizeof(d.R));
+        memcpy(d.t, c.t, sizeof(d.t));
+        d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+        d.width = c.width;
+        d.height = c.height;
+        d.tiles_x = (int32_t)div_up(c.width, kTile);
+        d.tiles_y = (int32_t)div_up(c.height, kTile);
+        d.tile_off = (int32_t)tiles;
+        d.pix_off = pixels;
+        tiles += (int64_t)d.tiles_x * d.tiles_y;
+        pixels += (int64_t)c.width * c.height;
+        if (tiles >= (int64_t)1 << 30 || pixels >= (int64_t)1 << 40) return SGR_EINVAL;
+    }
+    P->num_tiles = tiles;
+    P->num_pixels = pixels;
+    int bits = 1;
+    while (((int64_t)1 << bits) < tiles) bits++;
+    P->tile_bits = bits;
+    P->tile_passes = (bits + 7) / 8;
+
+    const int NV = 10 + P->k;
+    const size_t vns = (size_t)vn, caps = (size_t)cap;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + std::max<size_t>(bytes, 1), 256);
+        return at;
+    };
+    P->counters = take(sizeof(uint32_t) * kNumCounters);
+    P->views = take(sizeof(ViewDev) * V);
+    P->map_table = take(sizeof(MapPtrs) * V);
+    P->grad_table = take(sizeof(GradPtrs) * V);
+    P->count = take(4 * vns);
+    P->zbits = take(4 * vns);
+    P->gp_of_lin = take(4 * vns);
+    P->rec = take(sizeof(Proj) * vns);
+    P->vis_k0 = take(4 * vns);
+    P->vis_v0 = take(4 * vns);
+    P->vis_k1 = take(4 * vns);
+    P->vis_v1 = take(4 * vns);
+    P->order = P->vis_v0;  // the 4-pass depth sort ends in the *0 buffers
+    P->srec = take(sizeof(Proj) * vns);
+    P->scol = take(16 * vns);
+    P->ssv = take(4 * (size_t)P->k * vns);
+    P->ssi = take((size_t)P->kpad * vns);
+    P->tcount = take(4 * vns);
+    P->toff = take(4 * vns);
+    P->keys0 = take(4 * caps);
+    P->vals0 = take(4 * caps);
+    P->keys1 = take(4 * caps);
+    P->vals1 = take(4 * caps);
+    P->owner = take(4 * caps);
+    P->sgp = take(4 * caps);
+    P->ranges = take(8 * (size_t)tiles);
+    const uint32_t big = (uint32_t)std::max<int64_t>(vn, cap);
+    const size_t hist_words = radix_hist_words(big);
+    P->hist = take(4 * hist_words);
+    P->partial = take(4 * scan_partial_words(std::max<size_t>(big, hist_words)));
+    P->pix_T = take(4 * (size_t)pixels);
+    P->pix_last = take(4 * (size_t)pixels);
+    P->slots = take(4 * (size_t)NV * caps);
+    P->touched = take(caps);
+    P->g2d = take(4 * (size_t)NV * vns);
+    P->tile_part = take((sizeof(double) + sizeof(uint32_t)) * (size_t)tiles);
+    P->total = o;
+    const bool odd = (P->tile_passes & 1) != 0;
+    P->sorted_keys = odd ? P->keys1 : P->keys0;
+    P->sorted_vals = odd ? P->vals1 : P->vals0;
+    return SGR_OK;
+}
+
+// ------------------------------------------------------------------ small device helpers
+
+struct BytePayload {
+    uint32_t words[480];
+    uint32_t nwords;
+};
+
+__global__ void copy_payload(BytePayload p, uint32_t* dst) {
+    for (uint32_t i = threadIdx.x; i < p.nwords; i += blockDim.x) dst[i] = p.words[i];
+}
+
+// Host -> device copy carried in kernel arguments (no host staging buffer,
+// safe to capture in a graph).  bytes must be a multiple of 4.
+void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    const uint32_t* s = (const uint32_t*)src;
+    uint32_t* d = (uint32_t*)dst;
+    size_t words = bytes / 4;
+    for (size_t off = 0; off < words; off += 480) {
+        BytePayload p;
+        p.nwords = (uint32_t)std::min<size_t>(480, words - off);
+        memcpy(p.words, s + off, 4 * p.nwords);
+        copy_payload<<<1, 256, 0, st>>>(p, d + off);
+    }
+}
+
+__global__ void zero_u32(uint32_t* p) { *p = 0u; }
+
+static std::mutex g_dev_mu;
+static int g_cu[64];
+static size_t g_lds[64];
+
+static int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    return dev;
+}
+
+int device_cu_count() {
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_cu[dev]) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+        g_cu[dev] = cu;
+    }
+    return g_cu[dev];
+}
+
+size_t device_max_lds() {
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_lds[dev]) {
+        int b = 0;
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || b <= 0)
+            b = 65536;
+        g_lds[dev] = std::min<size_t>((size_t)b, kMaxLds);
+    }
+    return g_lds[dev];
+}
+
+size_t score_maps_scratch_bytes(int W, int H) {
+    const size_t grid = (size_t)div_up((int64_t)W * H, kBlock);
+    return align_up((sizeof(double) + sizeof(uint32_t)) * grid + sizeof(uint32_t), 256);
+}
+
+}  // namespace sgr
+
+using namespace sgr;
+
+static bool gaussians_ok(const sgr_gaussians* g) {
+    if (!g || g->n < 0) return false;
+    if (g->n == 0) return true;
+    return g->means && g->scales && g->quats && g->opacity && g->rgb && g->sem_val && g->sem_idx;
+}
+
+static sgr_status prepare(const sgr_gaussians* g, const sgr_camera* cams, int32_t V, const sgr_config* cfg,
+                          int64_t cap, void* ws, size_t ws_bytes, Plan* P) {
+    if (!gaussians_ok(g)) return SGR_EINVAL;
+    const sgr_status s = make_plan(g->n, cams, V, cfg, cap, P);
+    if (s != SGR_OK) return s;
+    if (!ws || ws_bytes < P->total || ((uintptr_t)ws & 255u)) return SGR_EINVAL;
+    return SGR_OK;
+}
+
+extern "C" {
+
+size_t sgr_workspace_size(int64_t n, const sgr_camera* cams, int32_t num_views, const sgr_config* cfg,
+                          int64_t key_capacity) {
+    Plan P;
+    if (make_plan(n, cams, num_views, cfg, key_capacity, &P) != SGR_OK) return 0;
+    return P.total;
+}
+
+sgr_status sgr_workspace_layout(int64_t n, const sgr_camera* cams, int32_t num_views, const sgr_config* cfg,
+                                int64_t key_capacity, sgr_layout* out) {
+    if (!out) return SGR_EINVAL;
+    Plan P;
+    const sgr_status s = make_plan(n, cams, num_views, cfg, key_capacity, &P);
+    if (s != SGR_OK) return s;
+    out->total_bytes = P.total;
+    out->counters = P.counters;
+    out->views = P.views;
+    out->proj_count = P.count;
+    out->proj_zbits = P.zbits;
+    out->proj_rec = P.rec;
+    out->order = P.order;
+    out->sorted_keys = P.sorted_keys;
+    out->sorted_vals = P.sorted_vals;
+    out->sorted_gauss = P.sgp;
+    out->ranges = P.ranges;
+    out->tile_offsets = P.toff;
+    out->num_tiles = P.num_tiles;
+    out->num_pixels = P.num_pixels;
+    out->vn = P.vn;
+    return SGR_OK;
+}
+
+sgr_status sgr_project(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views, const sgr_config* cfg,
+                       int64_t key_capacity, void* workspace, size_t workspace_bytes, void* stream) {
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    return launch_project(P, g, (char*)workspace, (hipStream_t)stream);
+}
+
+sgr_status sgr_bin(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views, const sgr_config* cfg,
+                   int64_t key_capacity, int64_t* d_num_keys, void* workspace, size_t workspace_bytes,
+                   void* stream) {
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    return launch_bin(P, (char*)workspace, d_num_keys, (hipStream_t)stream);
+}
+
+sgr_status sgr_render_forward(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
+                              const sgr_config* cfg, int64_t key_capacity, const sgr_maps* out, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+    if (!out) return SGR_EINVAL;
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    return launch_forward(P, out, (char*)workspace, (hipStream_t)stream);
+}
+
+sgr_status sgr_render_backward(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
+                               const sgr_config* cfg, int64_t key_capacity, const sgr_map_grads* dL,
+                               const sgr_grads* out, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!dL || !out) return SGR_EINVAL;
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    return launch_backward(P, g, dL, out, (char*)workspace, (hipStream_t)stream);
+}
+
+sgr_status sgr_score_views(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
+                           const sgr_config* cfg, int64_t key_capacity, uint32_t* n_empty, double* entropy_sum,
+                           void* workspace, size_t workspace_bytes, void* stream) {
+    if (!n_empty || !entropy_sum) return SGR_EINVAL;
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = launch_project(P, g, (char*)workspace, st)) != SGR_OK) return s;
+    if ((s = launch_bin(P, (char*)workspace, nullptr, st)) != SGR_OK) return s;
+    return launch_score(P, n_empty, entropy_sum, (char*)workspace, st);
+}
+
+size_t sgr_score_maps_workspace_size(int32_t width, int32_t height) {
+    if (width < 1 || height < 1) return 0;
+    return score_maps_scratch_bytes(width, height);
+}
+
+sgr_status sgr_score_maps(const float* sem, const int32_t* n_contrib, int32_t width, int32_t height,
+                          int32_t num_classes, uint32_t* n_empty, double* entropy_sum, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+    if (!sem || !n_contrib || !n_empty || !entropy_sum || width < 1 || height < 1 || num_classes < 1 ||
+        num_classes > kMaxC)
+        return SGR_EINVAL;
+    if (!workspace || workspace_bytes < score_maps_scratch_bytes(width, height) || ((uintptr_t)workspace & 255u))
+        return SGR_EINVAL;
+    return launch_score_maps(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, (char*)workspace,
+                             (hipStream_t)stream);
+}
+
+sgr_status sgr_read_status(const void* workspace, void* stream, int64_t* num_visible, int64_t* num_keys) {
+    if (!workspace) return SGR_EINVAL;
+    uint32_t c[kNumCounters];
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SGR_EHIP;
+    if (hipMemcpy(c, workspace, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return SGR_EHIP;
+    if (num_visible) *num_visible = c[kNumVisible];
+    if (num_keys) *num_keys = c[kKeysLo];
+    if (c[kStatus] & SGR_ECAPACITY) return SGR_ECAPACITY;
+    if (c[kStatus] & Plan::kBadIndex) return SGR_EINVAL;
+    return SGR_OK;
+}
+
+const char* sgr_status_string(sgr_status s) {
+    switch (s) {
+        case SGR_OK: return "ok";
+        case SGR_EINVAL: return "invalid argument";
+        case SGR_ECAPACITY: return "tile key capacity exceeded";
+        case SGR_EHIP: return "HIP runtime error";
+        case SGR_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,344 @@
+// Projection (EWA splat), visibility compaction, depth-ordered gather,
+// per-tile key emission and tile ranges.
+#include "pipeline.h"
+#include "sort.h"
+
+namespace sgr {
+
+// --------------------------------------------------------------- views
+
+struct ViewChunk {
+    ViewDev v[kViewChunk];
+    int32_t first, count;
+};
+
+// Camera tables travel as kernel arguments (graph-capturable, no host copy).
+__global__ void upload_views(ViewChunk chunk, ViewDev* views) {
+    const int j = threadIdx.x;
+    if (j < chunk.count) views[chunk.first + j] = chunk.v[j];
+}
+
+__global__ void init_frame(uint32_t* counters, uint2* ranges, int64_t num_tiles) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < kNumCounters) counters[i] = 0;
+    if (i < num_tiles) ranges[i] = make_uint2(0u, 0u);
+}
+
+__global__ void publish_num_keys(const uint32_t* counters, int64_t* d_num_keys) {
+    d_num_keys[0] = (int64_t)counters[kKeysLo];
+}
+
+// --------------------------------------------------------------- projection
+
+// One thread per (view, Gaussian).  Everything that decides binning (the
+// camera-space point, the 2D covariance, the pixel rectangle, the depth
+// key) is evaluated in double precision with the same operation order as
+// the FP64 reference and no contraction into FMA, so the tile keys agree
+// bit for bit; the compositing record is then rounded to fp32.
+__global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
+#pragma clang fp contract(off)
+    const int64_t lin = blockIdx.x * 256ll + threadIdx.x;
+    if (lin >= a.vn) return;
+    const int v = (int)(lin / a.n);
+    const int64_t i = lin - (int64_t)v * a.n;
+    const ViewDev& vw = a.views[v];
+    a.gp_of_lin[lin] = kInvalid;
+    uint32_t count = 0;
+    const double m0 = a.means[3 * i], m1 = a.means[3 * i + 1], m2 = a.means[3 * i + 2];
+    double p[3];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+        p[r] = (double)vw.R[3 * r] * m0 + (double)vw.R[3 * r + 1] * m1 + (double)vw.R[3 * r + 2] * m2 +
+               (double)vw.t[r];
+    const float zf = (float)p[2];
+    a.zbits[lin] = __float_as_uint(zf);
+    Proj rec;
+    bool vis = p[2] > (double)a.z_near;
+    if (vis) {
+        const double q0 = a.quats[4 * i], q1 = a.quats[4 * i + 1], q2 = a.quats[4 * i + 2], q3 = a.quats[4 * i + 3];
+        const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+        double Rq[9];
+        Rq[0] = 1 - 2 * (y * y + z * z); Rq[1] = 2 * (x * y - w * z);     Rq[2] = 2 * (x * z + w * y);
+        Rq[3] = 2 * (x * y + w * z);     Rq[4] = 1 - 2 * (x * x + z * z); Rq[5] = 2 * (y * z - w * x);
+        Rq[6] = 2 * (x * z - w * y);     Rq[7] = 2 * (y * z + w * x);     Rq[8] = 1 - 2 * (x * x + y * y);
+        const double s[3] = {(double)a.scales[3 * i], (double)a.scales[3 * i + 1], (double)a.scales[3 * i + 2]};
+        double S3[9];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                double acc = 0;
+#pragma unroll
+                for (int e = 0; e < 3; e++) acc += Rq[3 * r + e] * s[e] * s[e] * Rq[3 * c + e];
+                S3[3 * r + c] = acc;
+            }
+        const double fx = vw.fx, fy = vw.fy, zz = p[2];
+        const double J[6] = {fx / zz, 0, -fx * p[0] / (zz * zz), 0, fy / zz, -fy * p[1] / (zz * zz)};
+        double T[6];
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                double acc = 0;
+#pragma unroll
+                for (int e = 0; e < 3; e++) acc += J[3 * r + e] * (double)vw.R[3 * e + c];
+                T[3 * r + c] = acc;
+            }
+        double S2[4];
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                double acc = 0;
+#pragma unroll
+                for (int e = 0; e < 3; e++)
+#pragma unroll
+                    for (int f = 0; f < 3; f++) acc += T[3 * r + e] * S3[3 * e + f] * T[3 * c + f];
+                S2[2 * r + c] = acc;
+            }
+        const double lp = a.lowpass;
+        S2[0] += lp;
+        S2[3] += lp;
+        const double sxx = S2[0], sxy = 0.5 * (S2[1] + S2[2]), syy = S2[3];
+        const double det = sxx * syy - sxy * sxy;
+        const double o = a.opacity[i];
+        vis = det > 0 && o >= (double)a.alpha_min;
+        if (vis) {
+            const double mx = fx * p[0] / zz + (double)vw.cx, my = fy * p[1] / zz + (double)vw.cy;
+            const double qmax = 2.0 * log(o / (double)a.alpha_min);
+            const double ex = sqrt(qmax * sxx), ey = sqrt(qmax * syy);
+            double clo = ceil(mx - ex - 0.5), chi = floor(mx + ex - 0.5);
+            double rlo = ceil(my - ey - 0.5), rhi = floor(my + ey - 0.5);
+            if (clo < 0) clo = 0;
+            if (chi > vw.width - 1) chi = vw.width - 1;
+            if (rlo < 0) rlo = 0;
+            if (rhi > vw.height - 1) rhi = vw.height - 1;
+            // |mean| beyond 2^30 px cannot be represented in the record; such a
+            // Gaussian would need an astronomically large footprint to reach the
+            // image and is treated as culled on both sides of the parity check.
+            vis = clo <= chi && rlo <= rhi && fabs(mx) < 1073741824.0 && fabs(my) < 1073741824.0;
+            if (vis) {
+                const int c0 = (int)clo, c1 = (int)chi, r0 = (int)rlo, r1 = (int)rhi;
+                count = (uint32_t)((c1 / kTile - c0 / kTile + 1) * (r1 / kTile - r0 / kTile + 1));
+                const double ixd = floor(mx), iyd = floor(my);
+                const double a_ = syy / det;  // conic entries
+                const double kInv2Ln2 = 0.72134752044448170368;  // 1 / (2 ln 2)
+                rec.r0 = make_float4(__int_as_float((int)ixd), __int_as_float((int)iyd), (float)(mx - ixd),
+                                     (float)(my - iyd));
+                rec.r1 = make_float4((float)(a_ * kInv2Ln2), (float)(-sxy / syy), (float)(kInv2Ln2 / syy), (float)o);
+                rec.r2 = make_float4(__uint_as_float((uint32_t)c0 | ((uint32_t)c1 << 16)),
+                                     __uint_as_float((uint32_t)r0 | ((uint32_t)r1 << 16)), zf, __int_as_float(v));
+                a.rec[lin] = rec;
+            }
+        }
+    }
+    a.count[lin] = count;
+}
+
+// --------------------------------------------------------------- compaction
+
+// Writes (depth key, view*n + id) of every visible pair in index order.
+__global__ __launch_bounds__(256) void compact_visible(const uint32_t* __restrict__ count,
+                                                       const uint32_t* __restrict__ zbits, int64_t vn,
+                                                       const uint32_t* __restrict__ partial,
+                                                       uint32_t* __restrict__ out_key, uint32_t* __restrict__ out_val) {
+    __shared__ uint32_t wsum[4];
+    const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanItems;
+    uint32_t f[kScanItems], s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; r++) {
+        const int64_t i = base + r;
+        f[r] = (i < vn && count[i] != 0u) ? 1u : 0u;
+        s += f[r];
+    }
+    // block exclusive scan
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t pre = partial[blockIdx.x] + x - s;
+    for (int j = 0; j < w; j++) pre += wsum[j];
+#pragma unroll
+    for (int r = 0; r < kScanItems; r++) {
+        if (f[r]) {
+            const int64_t i = base + r;
+            out_key[pre] = zbits[i];
+            out_val[pre] = (uint32_t)i;
+            pre++;
+        }
+    }
+}
+
+// --------------------------------------------------------------- gather
+
+// Gathers the records of visible pairs in front-to-back order g.
+__global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t nv = a.counters[kNumVisible];
+    if (g >= nv) return;
+    const uint32_t lin = a.order[g];
+    const int64_t i = (int64_t)(lin % (uint64_t)a.n);
+    const Proj p = a.rec[lin];
+    a.srec[g] = p;
+    a.scol[g] = make_float4(a.rgb[3 * i], a.rgb[3 * i + 1], a.rgb[3 * i + 2], p.r2.z);
+    const int k = a.k;
+    for (int m = 0; m < k; m++) a.ssv[(size_t)g * k + m] = a.sem_val[i * k + m];
+    uint8_t* di = a.ssi + (size_t)g * a.kpad;
+    bool bad = false;
+    for (int m = 0; m < a.kpad; m++) {
+        uint8_t c = m < k ? a.sem_idx[i * k + m] : (uint8_t)0;
+        if ((int)c >= a.C) {  // never index past the class accumulators
+            bad = true;
+            c = 0;
+        }
+        di[m] = c;
+    }
+    if (bad) atomicOr(&a.counters[kStatus], Plan::kBadIndex);
+    a.tcount[g] = a.count[lin];
+    a.gp_of_lin[lin] = g;
+}
+
+// --------------------------------------------------------------- keys
+
+// Block b emits the keys of visible pairs [256 b, 256 b + 256): the block's
+// keys are spread evenly over its threads, each finding its owner by binary
+// search over the block's offsets in LDS.
+__global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
+    __shared__ uint32_t off[257];
+    __shared__ int32_t info[256][3];  // first global tile of the rect, rect width in tiles, view width in tiles
+    const uint32_t nv = a.counters[kNumVisible];
+    const uint32_t g0 = blockIdx.x * 256u;
+    if (g0 >= nv) return;
+    const uint32_t cnt = min(256u, nv - g0);
+    const uint32_t g = g0 + threadIdx.x;
+    if (threadIdx.x < cnt) {
+        off[threadIdx.x] = a.toff[g];
+        const float4 r2 = a.srec[g].r2;
+        const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
+        const int v = __float_as_int(r2.w);
+        const int tx0 = (int)(rx & 0xffffu) / kTile, tx1 = (int)(rx >> 16) / kTile;
+        const int ty0 = (int)(ry & 0xffffu) / kTile;
+        const ViewDev& vw = a.views[v];
+        info[threadIdx.x][0] = vw.tile_off + ty0 * vw.tiles_x + tx0;
+        info[threadIdx.x][1] = tx1 - tx0 + 1;
+        info[threadIdx.x][2] = vw.tiles_x;
+        if (threadIdx.x == cnt - 1) off[cnt] = a.toff[g] + a.tcount[g];
+    }
+    __syncthreads();
+    const uint32_t base = off[0];
+    const uint32_t total = off[cnt] - base;
+    const uint32_t cap = (uint32_t)a.cap;
+    for (uint32_t p = threadIdx.x; p < total; p += 256) {
+        const uint32_t e = base + p;
+        // owner: last j with off[j] <= e
+        int lo = 0, hi = (int)cnt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t local = e - off[lo];
+        const uint32_t wdt = (uint32_t)info[lo][1];
+        const uint32_t gt = (uint32_t)info[lo][0] + (local / wdt) * (uint32_t)info[lo][2] + local % wdt;
+        if (e < cap) {
+            a.keys[e] = gt;
+            a.owner[e] = g0 + lo;
+        }
+    }
+}
+
+// [start, end) of every non-empty tile, and the front-to-back index of each
+// sorted key.
+__global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ skeys,
+                                                   const uint32_t* __restrict__ svals,
+                                                   const uint32_t* __restrict__ owner, uint32_t* __restrict__ sgp,
+                                                   uint2* __restrict__ ranges, const uint32_t* __restrict__ counters,
+                                                   uint32_t cap) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t K = min(counters[kKeysLo], cap);
+    if (counters[kStatus] & SGR_ECAPACITY) return;
+    if (s >= K) return;
+    const uint32_t key = skeys[s];
+    sgp[s] = owner[svals[s]];
+    if (s == 0 || skeys[s - 1] != key) ranges[key].x = s;
+    if (s == K - 1 || skeys[s + 1] != key) ranges[key].y = s + 1;
+}
+
+// --------------------------------------------------------------- launchers
+
+sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st) {
+    ViewDev* views = (ViewDev*)(ws + P.views);
+    uint32_t* counters = (uint32_t*)(ws + P.counters);
+    // camera table, as kernel arguments
+    for (int first = 0; first < P.V; first += kViewChunk) {
+        ViewChunk ch;
+        memset(&ch, 0, sizeof(ch));
+        ch.first = first;
+        ch.count = std::min(kViewChunk, P.V - first);
+        for (int j = 0; j < ch.count; j++) ch.v[j] = P.view_table[first + j];
+        upload_views<<<1, kViewChunk, 0, st>>>(ch, views);
+    }
+    {
+        const int64_t nthreads = std::max<int64_t>(P.num_tiles, kNumCounters);
+        init_frame<<<(unsigned)div_up(nthreads, 256), 256, 0, st>>>(counters, (uint2*)(ws + P.ranges), P.num_tiles);
+    }
+    ProjectArgs pa;
+    pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opacity = g->opacity;
+    pa.views = views; pa.n = P.n; pa.vn = P.vn;
+    pa.alpha_min = P.cfg.alpha_min; pa.z_near = P.cfg.z_near; pa.lowpass = P.cfg.lowpass;
+    pa.count = (uint32_t*)(ws + P.count); pa.zbits = (uint32_t*)(ws + P.zbits);
+    pa.rec = (Proj*)(ws + P.rec); pa.gp_of_lin = (uint32_t*)(ws + P.gp_of_lin);
+    if (P.vn == 0) return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+    project_kernel<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(pa);
+    // compaction of visible pairs, then the depth sort
+    uint32_t* partial = (uint32_t*)(ws + P.partial);
+    {
+        const uint32_t nblk = (uint32_t)div_up(P.vn, kScanTile);
+        scan_flag_partials(pa.count, (uint32_t)P.vn, partial, counters + kNumVisible, st);
+        compact_visible<<<nblk, 256, 0, st>>>(pa.count, pa.zbits, P.vn, partial, (uint32_t*)(ws + P.vis_k0),
+                                              (uint32_t*)(ws + P.vis_v0));
+    }
+    const int passes = radix_sort((uint32_t*)(ws + P.vis_k0), (uint32_t*)(ws + P.vis_v0), (uint32_t*)(ws + P.vis_k1),
+                                  (uint32_t*)(ws + P.vis_v1), false, device_count(counters + kNumVisible, 0),
+                                  (uint32_t)P.vn, 32, (uint32_t*)(ws + P.hist), partial, st);
+    (void)passes;  // 4 passes: the result is back in the *0 buffers (P.order)
+    GatherArgs ga;
+    ga.order = (const uint32_t*)(ws + P.order); ga.rec = pa.rec; ga.count = pa.count;
+    ga.rgb = g->rgb; ga.sem_val = g->sem_val; ga.sem_idx = g->sem_idx;
+    ga.n = P.n; ga.k = P.k; ga.kpad = P.kpad; ga.C = P.C; ga.counters = counters;
+    ga.srec = (Proj*)(ws + P.srec); ga.scol = (float4*)(ws + P.scol); ga.ssv = (float*)(ws + P.ssv);
+    ga.ssi = (uint8_t*)(ws + P.ssi); ga.tcount = (uint32_t*)(ws + P.tcount); ga.gp_of_lin = pa.gp_of_lin;
+    gather_sorted<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(ga);
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t st) {
+    uint32_t* counters = (uint32_t*)(ws + P.counters);
+    uint32_t* partial = (uint32_t*)(ws + P.partial);
+    uint32_t* tcount = (uint32_t*)(ws + P.tcount);
+    uint32_t* toff = (uint32_t*)(ws + P.toff);
+    // per-pair key offsets; the total is the key count K
+    scan_exclusive(tcount, toff, device_count(counters + kNumVisible, 0), (uint32_t)P.vn, partial,
+                   counters + kKeysLo, (uint32_t)P.cap, counters + kStatus, st);
+    KeyArgs ka;
+    ka.toff = toff; ka.tcount = tcount; ka.srec = (const Proj*)(ws + P.srec); ka.views = (const ViewDev*)(ws + P.views);
+    ka.counters = counters; ka.cap = P.cap;
+    ka.keys = (uint32_t*)(ws + P.keys0); ka.owner = (uint32_t*)(ws + P.owner);
+    if (P.vn > 0) emit_keys<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(ka);
+    const int passes = radix_sort((uint32_t*)(ws + P.keys0), (uint32_t*)(ws + P.vals0), (uint32_t*)(ws + P.keys1),
+                                  (uint32_t*)(ws + P.vals1), true, device_count(counters + kKeysLo, (uint32_t)P.cap),
+                                  (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st);
+    if (passes != P.tile_passes) return SGR_EUNSUPPORTED;
+    tile_ranges<<<(unsigned)div_up(P.cap, 256), 256, 0, st>>>(
+        (const uint32_t*)(ws + P.sorted_keys), (const uint32_t*)(ws + P.sorted_vals), (const uint32_t*)(ws + P.owner),
+        (uint32_t*)(ws + P.sgp), (uint2*)(ws + P.ranges), counters, (uint32_t)P.cap);
+    if (d_num_keys) publish_num_keys<<<1, 1, 0, st>>>(counters, d_num_keys);
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+}  // namespace sgr

@@ -1,0 +1,84 @@
+// Workspace plan, kernel argument blocks and launchers of the pipeline.
+#pragma once
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "sgr_internal.h"
+
+namespace sgr {
+
+constexpr int kViewChunk = 16;  // cameras per upload launch (kernel-argument payload)
+
+// Workspace layout of one frame: a pure function of the call arguments.
+struct Plan {
+    int64_t n = 0, vn = 0, cap = 0, num_tiles = 0, num_pixels = 0;
+    int V = 0, k = 0, kpad = 0, C = 0, nv_slot = 0;
+    int tile_bits = 0, tile_passes = 0;
+    // status bit set on the device when a semantic index is >= C
+    static constexpr uint32_t kBadIndex = 8u;
+    sgr_config cfg{};
+    std::vector<ViewDev> view_table;
+    // byte offsets
+    size_t counters = 0, views = 0;
+    size_t count = 0, zbits = 0, rec = 0, gp_of_lin = 0;
+    size_t vis_k0 = 0, vis_v0 = 0, vis_k1 = 0, vis_v1 = 0, order = 0;
+    size_t srec = 0, scol = 0, ssv = 0, ssi = 0, tcount = 0, toff = 0;
+    size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, sgp = 0, ranges = 0;
+    size_t sorted_keys = 0, sorted_vals = 0;
+    size_t hist = 0, partial = 0;
+    size_t pix_T = 0, pix_last = 0;
+    size_t slots = 0, touched = 0, g2d = 0;
+    size_t tile_part = 0;
+    size_t map_table = 0, grad_table = 0;
+    size_t total = 0;
+};
+
+sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_config* cfg, int64_t cap, Plan* P);
+
+struct ProjectArgs {
+    const float *means, *scales, *quats, *opacity;
+    const ViewDev* views;
+    int64_t n, vn;
+    float alpha_min, z_near, lowpass;
+    uint32_t *count, *zbits, *gp_of_lin;
+    Proj* rec;
+};
+
+struct GatherArgs {
+    const uint32_t* order;
+    const Proj* rec;
+    const uint32_t* count;
+    const float *rgb, *sem_val;
+    const uint8_t* sem_idx;
+    int64_t n;
+    int k, kpad, C;
+    uint32_t* counters;
+    Proj* srec;
+    float4* scol;
+    float* ssv;
+    uint8_t* ssi;
+    uint32_t *tcount, *gp_of_lin;
+};
+
+struct KeyArgs {
+    const uint32_t *toff, *tcount;
+    const Proj* srec;
+    const ViewDev* views;
+    const uint32_t* counters;
+    int64_t cap;
+    uint32_t *keys, *owner;
+};
+
+sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st);
+sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t st);
+sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStream_t st);
+sgr_status launch_backward(const Plan& P, const sgr_gaussians* g, const sgr_map_grads* dL, const sgr_grads* out,
+                           char* ws, hipStream_t st);
+sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, char* ws, hipStream_t st);
+sgr_status launch_score_maps(const float* sem, const int32_t* n_contrib, int W, int H, int C, uint32_t* n_empty,
+                             double* entropy_sum, char* scratch, hipStream_t st);
+size_t score_maps_scratch_bytes(int W, int H);
+
+}  // namespace sgr

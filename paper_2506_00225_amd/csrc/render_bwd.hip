@@ -1,0 +1,460 @@
+// Backward pass: reverse compositing per tile with an atomic-free per-tile
+// reduction into one gradient slot per (tile, Gaussian) key, a fixed-order
+// sum of each Gaussian's slots, and the chain rule to 3D parameters.
+#include "pipeline.h"
+#include "render_common.h"
+
+namespace sgr {
+
+constexpr int kBwdBatch = 32;
+
+// Sum over the 64 lanes of a wave; the total lands in lane 63.  Row-wise
+// inclusive scan with row_shr (zero fill), then row_bcast:15 / row_bcast:31
+// carry the row totals upward.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWMASK, 0xf, true));
+}
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+    x += dpp_f<0x111, 0xf>(x);  // row_shr:1
+    x += dpp_f<0x112, 0xf>(x);  // row_shr:2
+    x += dpp_f<0x114, 0xf>(x);  // row_shr:4
+    x += dpp_f<0x118, 0xf>(x);  // row_shr:8
+    x += dpp_f<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_f<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+struct BwdArgs {
+    TileArgs t;
+    const GradPtrs* grads;     // [V]
+    float* slots;              // [cap][nvals]
+    uint8_t* touched;          // [cap]
+    const uint32_t* svals;     // sorted emission index of each key
+    int nvals;                 // 10 + k
+    int semgeo;
+    int sem_in_lds;
+};
+
+// Per-key value layout: 0,1 mean2d; 2,3,4 conic (a, b, c); 5 opacity;
+// 6,7,8 rgb; 9 depth; 10.. semantic values.
+template <int KT>
+__global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
+    extern __shared__ float smem[];
+    const TileArgs& a = b.t;
+    const int gt = xcd_remap(blockIdx.x, gridDim.x);
+    if (gt >= a.num_tiles) return;
+    if (a.counters[kStatus] & SGR_ECAPACITY) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int k = KT > 0 ? KT : a.k;
+    const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
+    const int C = a.C;
+    constexpr int NVMAX = 10 + (KT > 0 ? KT : kMaxK);
+    const int NV = 10 + k;
+
+    float* gp = smem;  // [C][257] dL/dsem of the tile's pixels (when staged)
+    float* base = smem + (b.sem_in_lds ? acc_floats(C) : 0);
+    float4* s_r0 = (float4*)base;
+    float4* s_r1 = s_r0 + kBwdBatch;
+    float4* s_r2 = s_r1 + kBwdBatch;
+    float4* s_col = s_r2 + kBwdBatch;
+    float* s_sv = (float*)(s_col + kBwdBatch);
+    uint32_t* s_si = (uint32_t*)(s_sv + kBwdBatch * k);
+    float* part = (float*)(s_si + kBwdBatch * kw);           // [4][kBwdBatch][NV]
+    uint32_t* flag = (uint32_t*)(part + 4 * kBwdBatch * NV);   // [4][kBwdBatch]
+    __shared__ uint32_t s_maxlast;
+
+    const int v = view_of_tile(a.views, a.V, gt);
+    const ViewDev& vw = a.views[v];
+    const int local = gt - vw.tile_off;
+    const int tx = local % vw.tiles_x, ty = local / vw.tiles_x;
+    const int px = tx * kTile + (tid & (kTile - 1)), py = ty * kTile + (tid >> 4);
+    const bool inside = px < vw.width && py < vw.height;
+    const uint2 rg = a.ranges[gt];
+    const uint32_t start = rg.x, end = rg.y;
+    const GradPtrs gr = b.grads[v];
+    const int64_t pix = (int64_t)py * vw.width + px;
+
+    float T = 1.f;
+    uint32_t last = start;
+    float gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gS = 0.f;
+    if (inside) {
+        T = a.pix_T[vw.pix_off + pix];
+        last = a.pix_last[vw.pix_off + pix];
+        if (gr.rgb) { gC0 = gr.rgb[3 * pix]; gC1 = gr.rgb[3 * pix + 1]; gC2 = gr.rgb[3 * pix + 2]; }
+        if (gr.depth) gD = gr.depth[pix];
+        if (gr.sil) gS = gr.sil[pix];
+    }
+    if (tid == 0) s_maxlast = start;
+    // stage dL/dsem for the tile, class-major
+    if (b.sem_in_lds) {
+        const int x0 = tx * kTile, y0 = ty * kTile;
+        const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
+        const int row_elems = kTile * C;
+        const int dl = kBlock / C, dc = kBlock % C;
+        for (int row = 0; row < kTile; row++) {
+            const float* src = gr.sem ? gr.sem + ((int64_t)(y0 + row) * vw.width + x0) * C : nullptr;
+            int lx = tid / C, c = tid % C;
+            for (int e = tid; e < row_elems; e += kBlock) {
+                float val = 0.f;
+                if (src && row < hrows && lx < wcols) val = src[e];
+                gp[c * kAccStride + row * kTile + lx] = val;
+                lx += dl;
+                c += dc;
+                if (c >= C) { c -= C; lx++; }
+            }
+        }
+    }
+    __syncthreads();
+    if (inside && last > start) atomicMax(&s_maxlast, last);
+    __syncthreads();
+    const uint32_t maxlast = s_maxlast;
+    const float amin = a.alpha_min, amax = a.alpha_max;
+    const float k2ln2 = 1.38629436111989061883f;  // 2 ln 2
+    float R = 0.f;
+
+    for (int64_t bend = maxlast; bend > (int64_t)start; bend -= kBwdBatch) {
+        const uint32_t b0 = (uint32_t)max((int64_t)start, bend - kBwdBatch);
+        const int nb = (int)(bend - b0);
+        if (tid < nb) {
+            const uint32_t g = a.sgp[b0 + tid];
+            const Proj p = a.srec[g];
+            s_r0[tid] = p.r0;
+            s_r1[tid] = p.r1;
+            s_r2[tid] = p.r2;
+            s_col[tid] = a.scol[g];
+        } else if (tid >= 128 && tid - 128 < nb) {
+            const int j = tid - 128;
+            const uint32_t g = a.sgp[b0 + j];
+            const float* sv = a.ssv + (size_t)g * k;
+            for (int m = 0; m < k; m++) s_sv[j * k + m] = sv[m];
+            const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
+            for (int m = 0; m < kw; m++) s_si[j * kw + m] = si[m];
+        }
+        __syncthreads();
+        for (int j = nb - 1; j >= 0; j--) {
+            const uint32_t s = b0 + j;
+            float val[NVMAX];
+#pragma unroll
+            for (int q = 0; q < NVMAX; q++) val[q] = 0.f;
+            bool act = false;
+            if (s < last) {
+                const float4 q2 = s_r2[j];
+                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+                if (px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) && py >= (int)(ry & 0xffffu) &&
+                    py <= (int)(ry >> 16)) {
+                    const float4 q0 = s_r0[j], q1 = s_r1[j];
+                    float G, dx, dy;
+                    const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
+                    if (alpha >= amin) {
+                        act = true;
+                        const float om = 1.f - alpha;
+                        T = T / om;  // transmittance in front of this Gaussian
+                        const float w = alpha * T;
+                        const float4 col = s_col[j];
+                        val[6] = w * gC0;
+                        val[7] = w * gC1;
+                        val[8] = w * gC2;
+                        val[9] = w * gD;
+                        float e = col.x * gC0 + col.y * gC1 + col.z * gC2 + col.w * gD + gS;
+                        float es = 0.f;
+                        if (b.sem_in_lds) {
+                            const float* sv = s_sv + j * k;
+                            const uint32_t* si = s_si + j * kw;
+#pragma unroll
+                            for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
+                                if (KT == 0 && mw >= kw) break;
+                                const uint32_t word = si[mw];
+#pragma unroll
+                                for (int bb = 0; bb < 4; bb++) {
+                                    const int m = mw * 4 + bb;
+                                    if (m < k) {
+                                        const float g = gp[((word >> (8 * bb)) & 0xffu) * kAccStride + tid];
+                                        val[10 + m] = w * g;
+                                        es += sv[m] * g;
+                                    }
+                                }
+                            }
+                        }
+                        if (b.semgeo) e += es;
+                        const float dalpha = T * e - R / om;
+                        R += e * w;
+                        if (q1.w * G < amax) {
+                            val[5] = dalpha * G;
+                            const float dQ = dalpha * (-0.5f * alpha);
+                            const float ca = q1.x * k2ln2;
+                            const float cb = q1.y * ca;
+                            const float cc = q1.z * k2ln2 + q1.y * cb;
+                            val[2] = dQ * dx * dx;
+                            val[3] = dQ * 2.f * dx * dy;
+                            val[4] = dQ * dy * dy;
+                            val[0] = -2.f * dQ * (ca * dx + cb * dy);
+                            val[1] = -2.f * dQ * (cb * dx + cc * dy);
+                        }
+                    }
+                }
+            }
+            const uint64_t any = __ballot(act);
+            if (any) {
+#pragma unroll
+                for (int q = 0; q < NVMAX; q++) {
+                    if (q < NV) {
+                        const float sum = wave_sum_lane63(val[q]);
+                        if (lane == 63) part[(wv * kBwdBatch + j) * NV + q] = sum;
+                    }
+                }
+            }
+            if (lane == 0) flag[wv * kBwdBatch + j] = any ? 1u : 0u;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < nb * NV; idx += kBlock) {
+            const int j = idx / NV, q = idx - j * NV;
+            const uint32_t f0 = flag[j], f1 = flag[kBwdBatch + j], f2 = flag[2 * kBwdBatch + j],
+                           f3 = flag[3 * kBwdBatch + j];
+            const uint32_t e = b.svals[b0 + j];
+            const bool t = (f0 | f1 | f2 | f3) != 0u;
+            if (t) {
+                float sum = 0.f;
+                if (f0) sum += part[(0 * kBwdBatch + j) * NV + q];
+                if (f1) sum += part[(1 * kBwdBatch + j) * NV + q];
+                if (f2) sum += part[(2 * kBwdBatch + j) * NV + q];
+                if (f3) sum += part[(3 * kBwdBatch + j) * NV + q];
+                b.slots[(size_t)e * NV + q] = sum;
+            }
+            if (q == 0) b.touched[e] = t ? 1 : 0;
+        }
+        __syncthreads();
+    }
+    for (uint32_t s = maxlast + tid; s < end; s += kBlock) b.touched[b.svals[s]] = 0;
+}
+
+// Sum of each visible pair's key slots, in emission order.
+template <int KT>
+__global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ slots,
+                                                    const uint8_t* __restrict__ touched,
+                                                    const uint32_t* __restrict__ toff,
+                                                    const uint32_t* __restrict__ tcount,
+                                                    const uint32_t* __restrict__ counters, int nv_rt,
+                                                    float* __restrict__ g2d) {
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    if (g >= counters[kNumVisible]) return;
+    constexpr int NVMAX = 10 + (KT > 0 ? KT : kMaxK);
+    const int NV = KT > 0 ? 10 + KT : nv_rt;
+    float acc[NVMAX];
+#pragma unroll
+    for (int q = 0; q < NVMAX; q++) acc[q] = 0.f;
+    if (!(counters[kStatus] & SGR_ECAPACITY)) {
+        const uint32_t e0 = toff[g], e1 = e0 + tcount[g];
+        for (uint32_t e = e0; e < e1; e++) {
+            if (!touched[e]) continue;
+            const float* sl = slots + (size_t)e * NV;
+#pragma unroll
+            for (int q = 0; q < NVMAX; q++)
+                if (q < NV) acc[q] += sl[q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NVMAX; q++)
+        if (q < NV) g2d[(size_t)g * NV + q] = acc[q];
+}
+
+struct ProjBwdArgs {
+    const float *means, *scales, *quats, *opacity;
+    const ViewDev* views;
+    int64_t n;
+    int V, k, NV;
+    float lowpass;
+    const uint32_t* gp_of_lin;
+    const float* g2d;
+    const uint32_t* counters;
+    float *d_means, *d_scales, *d_quats, *d_opacity, *d_rgb, *d_sem;
+};
+
+// Chain rule from each (view, Gaussian) pair's 2D gradient to the 3D
+// parameters, in double precision, summed over views in view order.
+template <int KT>
+__global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
+    const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+    if (i >= a.n) return;
+    const bool ok = !(a.counters[kStatus] & SGR_ECAPACITY);
+    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
+    float go = 0.f, grgb[3] = {0.f, 0.f, 0.f};
+    constexpr int KM = KT > 0 ? KT : kMaxK;
+    const int k = KT > 0 ? KT : a.k;
+    float gsem[KM];
+#pragma unroll
+    for (int m = 0; m < KM; m++) gsem[m] = 0.f;
+    const double m0 = a.means[3 * i], m1 = a.means[3 * i + 1], m2 = a.means[3 * i + 2];
+    const double q0 = a.quats[4 * i], q1 = a.quats[4 * i + 1], q2 = a.quats[4 * i + 2], q3 = a.quats[4 * i + 3];
+    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const double qw = q0 / qn, qx = q1 / qn, qy = q2 / qn, qz = q3 / qn;
+    double Rq[9];
+    Rq[0] = 1 - 2 * (qy * qy + qz * qz); Rq[1] = 2 * (qx * qy - qw * qz);     Rq[2] = 2 * (qx * qz + qw * qy);
+    Rq[3] = 2 * (qx * qy + qw * qz);     Rq[4] = 1 - 2 * (qx * qx + qz * qz); Rq[5] = 2 * (qy * qz - qw * qx);
+    Rq[6] = 2 * (qx * qz - qw * qy);     Rq[7] = 2 * (qy * qz + qw * qx);     Rq[8] = 1 - 2 * (qx * qx + qy * qy);
+    const double s[3] = {(double)a.scales[3 * i], (double)a.scales[3 * i + 1], (double)a.scales[3 * i + 2]};
+    double M[9], S3[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) M[3 * r + c] = Rq[3 * r + c] * s[c];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) S3[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+    double dS3[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int v = 0; v < a.V && ok; v++) {
+        const uint32_t g = a.gp_of_lin[(int64_t)v * a.n + i];
+        if (g == kInvalid) continue;
+        const float* d2 = a.g2d + (size_t)g * a.NV;
+        const ViewDev& vw = a.views[v];
+        double W[9];
+        for (int r = 0; r < 9; r++) W[r] = vw.R[r];
+        double p[3];
+        for (int r = 0; r < 3; r++) p[r] = W[3 * r] * m0 + W[3 * r + 1] * m1 + W[3 * r + 2] * m2 + (double)vw.t[r];
+        const double fx = vw.fx, fy = vw.fy, x = p[0], y = p[1], z = p[2];
+        const double J[6] = {fx / z, 0, -fx * x / (z * z), 0, fy / z, -fy * y / (z * z)};
+        double T[6];
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 3; c++) T[3 * r + c] = J[3 * r] * W[c] + J[3 * r + 1] * W[3 + c] + J[3 * r + 2] * W[6 + c];
+        double TS3[6];
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 3; c++)
+                TS3[3 * r + c] = T[3 * r] * S3[c] + T[3 * r + 1] * S3[3 + c] + T[3 * r + 2] * S3[6 + c];
+        double S2[4];
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 2; c++)
+                S2[2 * r + c] = TS3[3 * r] * T[3 * c] + TS3[3 * r + 1] * T[3 * c + 1] + TS3[3 * r + 2] * T[3 * c + 2];
+        const double sxx = S2[0] + a.lowpass, sxy = 0.5 * (S2[1] + S2[2]), syy = S2[3] + a.lowpass;
+        const double det = sxx * syy - sxy * sxy;
+        const double A[4] = {syy / det, -sxy / det, -sxy / det, sxx / det};
+        const double dA[4] = {d2[2], 0.5 * d2[3], 0.5 * d2[3], d2[4]};
+        double tmp[4], dS2[4];
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 2; c++) tmp[2 * r + c] = A[2 * r] * dA[c] + A[2 * r + 1] * dA[2 + c];
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 2; c++) dS2[2 * r + c] = -(tmp[2 * r] * A[c] + tmp[2 * r + 1] * A[2 + c]);
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 3; c++)
+                dS3[3 * r + c] += T[r] * (dS2[0] * T[c] + dS2[1] * T[3 + c]) + T[3 + r] * (dS2[2] * T[c] + dS2[3] * T[3 + c]);
+        double dT[6];
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 3; c++) dT[3 * r + c] = 2.0 * (dS2[2 * r] * TS3[c] + dS2[2 * r + 1] * TS3[3 + c]);
+        double dJ[6];
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 3; c++) dJ[3 * r + c] = dT[3 * r] * W[3 * c] + dT[3 * r + 1] * W[3 * c + 1] + dT[3 * r + 2] * W[3 * c + 2];
+        const double z2 = z * z, z3 = z2 * z;
+        double dp[3];
+        dp[0] = dJ[2] * (-fx / z2);
+        dp[1] = dJ[5] * (-fy / z2);
+        dp[2] = dJ[0] * (-fx / z2) + dJ[2] * (2.0 * fx * x / z3) + dJ[4] * (-fy / z2) + dJ[5] * (2.0 * fy * y / z3);
+        const double gmx = d2[0], gmy = d2[1];
+        dp[0] += gmx * fx / z;
+        dp[1] += gmy * fy / z;
+        dp[2] += -gmx * fx * x / z2 - gmy * fy * y / z2 + (double)d2[9];
+        for (int c = 0; c < 3; c++) gm[c] += W[c] * dp[0] + W[3 + c] * dp[1] + W[6 + c] * dp[2];
+        go += d2[5];
+        grgb[0] += d2[6];
+        grgb[1] += d2[7];
+        grgb[2] += d2[8];
+#pragma unroll
+        for (int m = 0; m < KM; m++)
+            if (m < k) gsem[m] += d2[10 + m];
+    }
+    // Sigma3 = M M^T, M = Rq diag(s): dM = 2 dS3 M
+    double dM[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) dM[3 * r + c] = 2.0 * (dS3[3 * r] * M[c] + dS3[3 * r + 1] * M[3 + c] + dS3[3 * r + 2] * M[6 + c]);
+    for (int c = 0; c < 3; c++) gs[c] = dM[c] * Rq[c] + dM[3 + c] * Rq[3 + c] + dM[6 + c] * Rq[6 + c];
+    double dR[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) dR[3 * r + c] = dM[3 * r + c] * s[c];
+    double dq[4];
+    dq[0] = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+    dq[1] = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] + qw * dR[7] - 2.0 * qx * dR[8]);
+    dq[2] = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] + qz * dR[7] - 2.0 * qy * dR[8]);
+    dq[3] = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] + qy * dR[5] + qx * dR[6] + qy * dR[7]);
+    const double dot = dq[0] * qw + dq[1] * qx + dq[2] * qy + dq[3] * qz;
+    const double qh[4] = {qw, qx, qy, qz};
+    for (int c = 0; c < 4; c++) gq[c] = (dq[c] - qh[c] * dot) / qn;
+    if (a.d_means) for (int c = 0; c < 3; c++) a.d_means[3 * i + c] = (float)gm[c];
+    if (a.d_scales) for (int c = 0; c < 3; c++) a.d_scales[3 * i + c] = (float)gs[c];
+    if (a.d_quats) for (int c = 0; c < 4; c++) a.d_quats[4 * i + c] = (float)gq[c];
+    if (a.d_opacity) a.d_opacity[i] = go;
+    if (a.d_rgb) for (int c = 0; c < 3; c++) a.d_rgb[3 * i + c] = grgb[c];
+    if (a.d_sem) {
+#pragma unroll
+        for (int m = 0; m < KM; m++)
+            if (m < k) a.d_sem[i * k + m] = gsem[m];
+    }
+}
+
+// ------------------------------------------------------------------ launcher
+
+static size_t bwd_lds_bytes(int C, int k, int kpad, bool sem_lds) {
+    size_t b = (size_t)kBwdBatch * (4 * sizeof(float4) + k * sizeof(float) + kpad);
+    b += (size_t)4 * kBwdBatch * (10 + k) * sizeof(float) + 4 * kBwdBatch * sizeof(uint32_t);
+    if (sem_lds) b += (size_t)acc_floats(C) * sizeof(float);
+    return b;
+}
+
+template <typename K>
+static void set_lds_b(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+sgr_status launch_backward(const Plan& P, const sgr_gaussians* g, const sgr_map_grads* dL, const sgr_grads* out,
+                           char* ws, hipStream_t st) {
+    BwdArgs b;
+    memset(&b, 0, sizeof(b));
+    b.t = make_tile_args(P, ws);
+    std::vector<GradPtrs> gpt(P.V);
+    for (int v = 0; v < P.V; v++) gpt[v] = GradPtrs{dL[v].rgb, dL[v].depth, dL[v].sil, dL[v].sem};
+    upload_bytes(ws + P.grad_table, gpt.data(), sizeof(GradPtrs) * P.V, st);
+    b.grads = (const GradPtrs*)(ws + P.grad_table);
+    b.slots = (float*)(ws + P.slots);
+    b.touched = (uint8_t*)(ws + P.touched);
+    b.svals = (const uint32_t*)(ws + P.sorted_vals);
+    b.nvals = 10 + P.k;
+    b.semgeo = P.cfg.sem_grad_to_geometry;
+    size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad, true);
+    b.sem_in_lds = 1;
+    if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
+    const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
+    if (P.k == 16) {
+        set_lds_b(render_bwd_kernel<16>, lds);
+        render_bwd_kernel<16><<<grid, kBlock, lds, st>>>(b);
+    } else if (P.k == 3) {
+        set_lds_b(render_bwd_kernel<3>, lds);
+        render_bwd_kernel<3><<<grid, kBlock, lds, st>>>(b);
+    } else {
+        set_lds_b(render_bwd_kernel<0>, lds);
+        render_bwd_kernel<0><<<grid, kBlock, lds, st>>>(b);
+    }
+    const uint32_t* counters = (const uint32_t*)(ws + P.counters);
+    const unsigned ggrid = (unsigned)div_up(P.vn, 256);
+    if (ggrid > 0) {
+        const uint32_t* toff = (const uint32_t*)(ws + P.toff);
+        const uint32_t* tcount = (const uint32_t*)(ws + P.tcount);
+        float* g2d = (float*)(ws + P.g2d);
+        if (P.k == 16) gather_slots<16><<<ggrid, 256, 0, st>>>(b.slots, b.touched, toff, tcount, counters, b.nvals, g2d);
+        else if (P.k == 3) gather_slots<3><<<ggrid, 256, 0, st>>>(b.slots, b.touched, toff, tcount, counters, b.nvals, g2d);
+        else gather_slots<0><<<ggrid, 256, 0, st>>>(b.slots, b.touched, toff, tcount, counters, b.nvals, g2d);
+    }
+    ProjBwdArgs pa;
+    pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opacity = g->opacity;
+    pa.views = (const ViewDev*)(ws + P.views);
+    pa.n = P.n; pa.V = P.V; pa.k = P.k; pa.NV = b.nvals;
+    pa.lowpass = P.cfg.lowpass;
+    pa.gp_of_lin = (const uint32_t*)(ws + P.gp_of_lin);
+    pa.g2d = (const float*)(ws + P.g2d);
+    pa.counters = counters;
+    pa.d_means = out->means; pa.d_scales = out->scales; pa.d_quats = out->quats;
+    pa.d_opacity = out->opacity; pa.d_rgb = out->rgb; pa.d_sem = out->sem_val;
+    const unsigned pgrid = (unsigned)div_up(P.n, 256);
+    if (pgrid > 0) {
+        if (P.k == 16) project_backward_kernel<16><<<pgrid, 256, 0, st>>>(pa);
+        else if (P.k == 3) project_backward_kernel<3><<<pgrid, 256, 0, st>>>(pa);
+        else project_backward_kernel<0><<<pgrid, 256, 0, st>>>(pa);
+    }
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+}  // namespace sgr

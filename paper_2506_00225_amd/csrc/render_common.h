@@ -1,0 +1,93 @@
+// Shared pieces of the compositing kernels.
+#pragma once
+
+#include "pipeline.h"
+
+namespace sgr {
+
+constexpr int kFwdBatch = 128;     // Gaussians staged per forward batch
+constexpr size_t kMaxLds = 160 * 1024;
+
+// LDS floats of a class-major accumulator tile, rounded up so that what
+// follows it stays 16-byte aligned.
+__host__ __device__ inline int acc_floats(int C) { return (C * kAccStride + 3) & ~3; }
+
+struct MapPtrs {
+    float *rgb, *depth, *sil, *sem, *t_final;
+    int32_t* n_contrib;
+};
+
+struct GradPtrs {
+    const float *rgb, *depth, *sil, *sem;
+};
+
+struct TileArgs {
+    const ViewDev* views;
+    int V;
+    int64_t num_tiles;
+    int k, kpad, C;
+    const uint2* ranges;
+    const uint32_t* sgp;
+    const Proj* srec;
+    const float4* scol;
+    const float* ssv;
+    const uint8_t* ssi;
+    uint32_t* counters;
+    float* pix_T;
+    uint32_t* pix_last;
+    float alpha_min, alpha_max, t_min;
+    const MapPtrs* maps;
+};
+
+struct TileResult {
+    float T;
+    int ncon;
+    bool inside;
+    int v, px, py, tx, ty;
+    uint32_t last;
+    float c[3];
+    float d, s;
+};
+
+struct ScoreOut {
+    double* tile_h;
+    uint32_t* tile_e;
+    uint32_t* n_empty;
+    double* entropy_sum;
+};
+
+__device__ inline int view_of_tile(const ViewDev* views, int V, int gt) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= gt) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// alpha = min(alpha_max, o G) at the centre of pixel (px, py).  The offset
+// from the mean is formed from the record's integer and fractional parts
+// (exact up to one rounding), and log2 G = -(ca u^2 + cc dy^2) with
+// u = dx + cb dy has no cancellation.  dx, dy are pixel centre minus mean.
+__device__ __forceinline__ float eval_alpha(const float4& q0, const float4& q1, int px, int py, float amax,
+                                            float* G, float* dx, float* dy) {
+    const float ddx = (float)(px - __float_as_int(q0.x)) + (0.5f - q0.z);
+    const float ddy = (float)(py - __float_as_int(q0.y)) + (0.5f - q0.w);
+    const float u = fmaf(q1.y, ddy, ddx);
+    const float e = fmaf(q1.x * u, u, q1.z * ddy * ddy);
+    const float g = exp2f(-e);
+    *G = g;
+    *dx = ddx;
+    *dy = ddy;
+    return fminf(amax, q1.w * g);
+}
+
+TileArgs make_tile_args(const Plan& P, char* ws);
+size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode);
+int device_cu_count();
+size_t device_max_lds();
+void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t st);
+
+__global__ void zero_u32(uint32_t* p);
+
+}  // namespace sgr

@@ -1,0 +1,413 @@
+// Front-to-back compositing (Eq. 1, Eq. 3) per 16x16 tile, and the
+// persistent candidate-view scorer (Eq. 4-6) built on the same tile body.
+#include "pipeline.h"
+#include "render_common.h"
+
+namespace sgr {
+
+// Per-tile compositing.  One thread per pixel (256 = 4 wave64).  Batches of
+// the tile's front-to-back list are staged in LDS; every lane reads the
+// same record (an LDS broadcast).  Semantic accumulators live in LDS,
+// class-major with a 257-float stride: the 64 lanes of a wave update 64
+// consecutive floats of one class row, which is conflict-free.
+template <int KT, int SEM>
+__device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float* smem, TileResult& res) {
+    const int tid = threadIdx.x;
+    const int k = KT > 0 ? KT : a.k;
+    const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;  // index words per Gaussian
+    const int C = a.C;
+    float* acc = smem;                                   // [C][257] when SEM == 1
+    float* bat = smem + (SEM == 1 ? acc_floats(C) : 0);
+    float4* s_r0 = (float4*)bat;
+    float4* s_r1 = s_r0 + kFwdBatch;
+    float4* s_r2 = s_r1 + kFwdBatch;
+    float4* s_col = s_r2 + kFwdBatch;
+    float* s_sv = (float*)(s_col + kFwdBatch);
+    uint32_t* s_si = (uint32_t*)(s_sv + kFwdBatch * k);
+
+    const int v = view_of_tile(a.views, a.V, gt);
+    const ViewDev& vw = a.views[v];
+    const int local = gt - vw.tile_off;
+    const int tx = local % vw.tiles_x, ty = local / vw.tiles_x;
+    const int px = tx * kTile + (tid & (kTile - 1)), py = ty * kTile + (tid >> 4);
+    const bool inside = px < vw.width && py < vw.height;
+    const uint2 rg = a.ranges[gt];
+    const uint32_t start = rg.x, end = rg.y;
+
+    if (SEM == 1)
+        for (int i = tid; i < C * kAccStride; i += kBlock) acc[i] = 0.f;
+    float* gacc = nullptr;  // SEM == 2: the thread's own row of the output map
+    if (SEM == 2 && inside && a.maps[v].sem) {
+        gacc = a.maps[v].sem + ((int64_t)py * vw.width + px) * C;
+        for (int c = 0; c < C; c++) gacc[c] = 0.f;
+    }
+
+    float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f, ss = 0.f;
+    int ncon = 0;
+    uint32_t last = start;
+    bool done = !inside;
+    const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min;
+
+    for (uint32_t b0 = start; b0 < end; b0 += kFwdBatch) {
+        if (__syncthreads_count(done) == kBlock) break;
+        const int nb = (int)min((uint32_t)kFwdBatch, end - b0);
+        if (tid < kFwdBatch) {
+            if (tid < nb) {
+                const uint32_t g = a.sgp[b0 + tid];
+                const Proj p = a.srec[g];
+                s_r0[tid] = p.r0;
+                s_r1[tid] = p.r1;
+                s_r2[tid] = p.r2;
+                s_col[tid] = a.scol[g];
+            }
+        } else if (SEM != 0) {
+            const int j = tid - kFwdBatch;
+            if (j < nb) {
+                const uint32_t g = a.sgp[b0 + j];
+                const float* sv = a.ssv + (size_t)g * k;
+                for (int m = 0; m < k; m++) s_sv[j * k + m] = sv[m];
+                const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
+                for (int m = 0; m < kw; m++) s_si[j * kw + m] = si[m];
+            }
+        }
+        __syncthreads();
+        if (!done) {
+            for (int j = 0; j < nb; j++) {
+                const float4 q2 = s_r2[j];
+                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+                if (px < (int)(rx & 0xffffu) || px > (int)(rx >> 16) || py < (int)(ry & 0xffffu) ||
+                    py > (int)(ry >> 16))
+                    continue;
+                const float4 q0 = s_r0[j], q1 = s_r1[j];
+                float G, dx, dy;
+                const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
+                if (alpha < amin) continue;
+                const float Tn = T * (1.f - alpha);
+                if (Tn < tmin) {
+                    done = true;
+                    break;
+                }
+                const float w = alpha * T;
+                const float4 col = s_col[j];
+                cr += col.x * w;
+                cg += col.y * w;
+                cb += col.z * w;
+                dd += col.w * w;
+                ss += w;
+                if (SEM != 0) {
+                    const float* sv = s_sv + j * k;
+                    const uint32_t* si = s_si + j * kw;
+#pragma unroll
+                    for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
+                        if (KT == 0 && mw >= kw) break;
+                        const uint32_t word = si[mw];
+#pragma unroll
+                        for (int b = 0; b < 4; b++) {
+                            const int m = mw * 4 + b;
+                            if (m < k) {
+                                const uint32_t cls = (word >> (8 * b)) & 0xffu;
+                                if (SEM == 1) acc[cls * kAccStride + tid] += sv[m] * w;
+                                else if (gacc) gacc[cls] += sv[m] * w;
+                            }
+                        }
+                    }
+                }
+                T = Tn;
+                ncon++;
+                last = b0 + j + 1;
+            }
+        }
+    }
+    res.T = T;
+    res.ncon = ncon;
+    res.inside = inside;
+    res.v = v;
+    res.px = px;
+    res.py = py;
+    res.tx = tx;
+    res.ty = ty;
+    res.last = last;
+    res.c[0] = cr; res.c[1] = cg; res.c[2] = cb;
+    res.d = dd;
+    res.s = ss;
+}
+
+template <int KT, int SEM>
+__global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
+    extern __shared__ float smem[];
+    const int gt = xcd_remap(blockIdx.x, gridDim.x);
+    if (gt >= a.num_tiles) return;
+    if (a.counters[kStatus] & SGR_ECAPACITY) return;
+    TileResult r;
+    composite_tile<KT, SEM>(a, gt, smem, r);
+    const ViewDev& vw = a.views[r.v];
+    if (r.inside) {
+        const int64_t pix = (int64_t)r.py * vw.width + r.px;
+        const MapPtrs& o = a.maps[r.v];
+        if (o.rgb) { o.rgb[3 * pix] = r.c[0]; o.rgb[3 * pix + 1] = r.c[1]; o.rgb[3 * pix + 2] = r.c[2]; }
+        if (o.depth) o.depth[pix] = r.d;
+        if (o.sil) o.sil[pix] = r.s;
+        if (o.t_final) o.t_final[pix] = r.T;
+        if (o.n_contrib) o.n_contrib[pix] = r.ncon;
+        a.pix_T[vw.pix_off + pix] = r.T;
+        a.pix_last[vw.pix_off + pix] = r.last;
+    }
+    if (SEM == 1) {
+        float* out = a.maps[r.v].sem;
+        if (!out) return;
+        __syncthreads();
+        const int C = a.C;
+        const int x0 = r.tx * kTile, y0 = r.ty * kTile;
+        const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
+        const int row_elems = kTile * C;
+        const int dl = kBlock / C, dc = kBlock % C;
+        for (int row = 0; row < hrows; row++) {
+            float* dst = out + ((int64_t)(y0 + row) * vw.width + x0) * C;
+            int lx = threadIdx.x / C, c = threadIdx.x % C;
+            for (int e = threadIdx.x; e < row_elems; e += kBlock) {
+                if (lx < wcols) dst[e] = smem[c * kAccStride + row * kTile + lx];
+                lx += dl;
+                c += dc;
+                if (c >= C) { c -= C; lx++; }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ scoring
+
+// Persistent: each workgroup takes (view, tile) items from a ticket counter
+// until none are left, composites the tile's silhouette count and semantic
+// accumulators, and writes the tile's empty-pixel count and summed entropy
+// to a fixed slot.  The last workgroup to finish reduces the slots of each
+// view in tile order (FP64), so the scores are deterministic.
+template <int KT>
+__global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, ScoreOut so) {
+    extern __shared__ float smem[];
+    __shared__ int s_item;
+    __shared__ double s_h[4];
+    __shared__ uint32_t s_e[4];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const bool ok = !(a.counters[kStatus] & SGR_ECAPACITY);
+    const int C = a.C;
+    const float ln2 = 0.69314718055994530942f;
+    const float lg_lo = -9.9657842846620870436f;  // log2(0.001)
+    for (;;) {
+        if (tid == 0) s_item = ok ? (int)atomicAdd(&a.counters[kWork], 1u) : (int)a.num_tiles;
+        __syncthreads();
+        const int gt = s_item;
+        __syncthreads();
+        if (gt >= a.num_tiles) break;
+        TileResult r;
+        composite_tile<KT, 1>(a, gt, smem, r);
+        __syncthreads();
+        double h = 0.0;
+        if (r.inside) {
+            float Z = 0.f, sxl = 0.f;
+            for (int c = 0; c < C; c++) {
+                const float x = fminf(fmaxf(smem[c * kAccStride + tid], 0.001f), 1.f);
+                const float lx = (x == 0.001f) ? lg_lo : __log2f(x);
+                Z += x;
+                sxl += x * lx;
+            }
+            h = (double)(ln2 * (__log2f(Z) - sxl / Z));
+        }
+        const uint64_t em = __ballot(r.inside && r.ncon == 0);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+        if (lane == 0) {
+            s_h[w] = h;
+            s_e[w] = (uint32_t)__popcll(em);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            so.tile_h[gt] = ((s_h[0] + s_h[1]) + s_h[2]) + s_h[3];
+            so.tile_e[gt] = s_e[0] + s_e[1] + s_e[2] + s_e[3];
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(&a.counters[kDone], 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int v = tid; v < a.V; v += kBlock) {
+        const ViewDev& vw = a.views[v];
+        const int t0 = vw.tile_off, nt = vw.tiles_x * vw.tiles_y;
+        double hs = 0.0;
+        uint32_t es = 0;
+        if (ok) {
+            const volatile double* th = so.tile_h;
+            const volatile uint32_t* te = so.tile_e;
+            for (int t = 0; t < nt; t++) {
+                hs += th[t0 + t];
+                es += te[t0 + t];
+            }
+        }
+        so.entropy_sum[v] = ok ? hs : 0.0;
+        so.n_empty[v] = ok ? es : 0u;
+    }
+}
+
+// ------------------------------------------------------------------ plain scoring from dense maps
+
+__global__ __launch_bounds__(kBlock) void score_maps_kernel(const float* __restrict__ sem,
+                                                            const int32_t* __restrict__ ncon, int64_t P, int C,
+                                                            double* __restrict__ blk_h, uint32_t* __restrict__ blk_e,
+                                                            uint32_t* done, uint32_t* n_empty, double* entropy_sum) {
+    __shared__ double s_h[4];
+    __shared__ uint32_t s_e[4];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t p = blockIdx.x * (int64_t)kBlock + tid;
+    const float ln2 = 0.69314718055994530942f;
+    const float lg_lo = -9.9657842846620870436f;
+    double h = 0.0;
+    bool empty = false;
+    if (p < P) {
+        const float* row = sem + p * C;
+        float Z = 0.f, sxl = 0.f;
+        for (int c = 0; c < C; c++) {
+            const float x = fminf(fmaxf(row[c], 0.001f), 1.f);
+            const float lx = (x == 0.001f) ? lg_lo : __log2f(x);
+            Z += x;
+            sxl += x * lx;
+        }
+        h = (double)(ln2 * (__log2f(Z) - sxl / Z));
+        empty = ncon[p] == 0;
+    }
+    const uint64_t em = __ballot(empty);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+    if (lane == 0) { s_h[w] = h; s_e[w] = (uint32_t)__popcll(em); }
+    __syncthreads();
+    if (tid == 0) {
+        blk_h[blockIdx.x] = ((s_h[0] + s_h[1]) + s_h[2]) + s_h[3];
+        blk_e[blockIdx.x] = s_e[0] + s_e[1] + s_e[2] + s_e[3];
+        __threadfence();
+        s_last = (atomicAdd(done, 1u) == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last || tid != 0) return;
+    __threadfence();
+    double hs = 0.0;
+    uint32_t es = 0;
+    const volatile double* bh = blk_h;
+    const volatile uint32_t* be = blk_e;
+    for (unsigned b = 0; b < gridDim.x; b++) { hs += bh[b]; es += be[b]; }
+    entropy_sum[0] = hs;
+    n_empty[0] = es;
+    *done = 0;
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename K>
+static void set_lds(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode) {
+    size_t b = (size_t)kFwdBatch * (4 * sizeof(float4) + k * sizeof(float) + kpad);
+    if (sem_mode == 1) b += (size_t)acc_floats(C) * sizeof(float);
+    return b;
+}
+
+static int sem_mode_for(const Plan& P, bool want_sem) {
+    if (!want_sem) return 0;
+    return fwd_lds_bytes(P.C, P.k, P.kpad, 1) <= device_max_lds() ? 1 : 2;
+}
+
+TileArgs make_tile_args(const Plan& P, char* ws) {
+    TileArgs a;
+    memset(&a, 0, sizeof(a));
+    a.views = (const ViewDev*)(ws + P.views);
+    a.V = P.V;
+    a.num_tiles = P.num_tiles;
+    a.k = P.k;
+    a.kpad = P.kpad;
+    a.C = P.C;
+    a.ranges = (const uint2*)(ws + P.ranges);
+    a.sgp = (const uint32_t*)(ws + P.sgp);
+    a.srec = (const Proj*)(ws + P.srec);
+    a.scol = (const float4*)(ws + P.scol);
+    a.ssv = (const float*)(ws + P.ssv);
+    a.ssi = (const uint8_t*)(ws + P.ssi);
+    a.counters = (uint32_t*)(ws + P.counters);
+    a.pix_T = (float*)(ws + P.pix_T);
+    a.pix_last = (uint32_t*)(ws + P.pix_last);
+    a.alpha_min = P.cfg.alpha_min;
+    a.alpha_max = P.cfg.alpha_max;
+    a.t_min = P.cfg.t_min;
+    return a;
+}
+
+template <int KT>
+static void fwd_dispatch_sem(int sem, const TileArgs& a, unsigned grid, size_t lds, hipStream_t st) {
+    if (sem == 0) {
+        set_lds(render_fwd_kernel<KT, 0>, lds);
+        render_fwd_kernel<KT, 0><<<grid, kBlock, lds, st>>>(a);
+    } else if (sem == 1) {
+        set_lds(render_fwd_kernel<KT, 1>, lds);
+        render_fwd_kernel<KT, 1><<<grid, kBlock, lds, st>>>(a);
+    } else {
+        set_lds(render_fwd_kernel<KT, 2>, lds);
+        render_fwd_kernel<KT, 2><<<grid, kBlock, lds, st>>>(a);
+    }
+}
+
+sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStream_t st) {
+    TileArgs a = make_tile_args(P, ws);
+    bool want_sem = false;
+    std::vector<MapPtrs> mp(P.V);
+    for (int v = 0; v < P.V; v++) {
+        mp[v] = MapPtrs{out[v].rgb, out[v].depth, out[v].sil, out[v].sem, out[v].t_final, out[v].n_contrib};
+        want_sem |= out[v].sem != nullptr;
+    }
+    upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
+    a.maps = (const MapPtrs*)(ws + P.map_table);
+    const int sem = sem_mode_for(P, want_sem);
+    const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, sem);
+    const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
+    if (P.k == 16) fwd_dispatch_sem<16>(sem, a, grid, lds, st);
+    else if (P.k == 3) fwd_dispatch_sem<3>(sem, a, grid, lds, st);
+    else fwd_dispatch_sem<0>(sem, a, grid, lds, st);
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, char* ws, hipStream_t st) {
+    TileArgs a = make_tile_args(P, ws);
+    ScoreOut so;
+    so.tile_h = (double*)(ws + P.tile_part);
+    so.tile_e = (uint32_t*)(ws + P.tile_part + sizeof(double) * P.num_tiles);
+    so.n_empty = n_empty;
+    so.entropy_sum = entropy_sum;
+    const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, 1);
+    if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
+    const int per_cu = std::max<int>(1, (int)(device_max_lds() / (lds + 4096)));
+    const unsigned grid = (unsigned)std::min<int64_t>(P.num_tiles, (int64_t)device_cu_count() * per_cu);
+    if (P.k == 16) {
+        set_lds(score_persistent_kernel<16>, lds);
+        score_persistent_kernel<16><<<grid, kBlock, lds, st>>>(a, so);
+    } else {
+        set_lds(score_persistent_kernel<0>, lds);
+        score_persistent_kernel<0><<<grid, kBlock, lds, st>>>(a, so);
+    }
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+sgr_status launch_score_maps(const float* sem, const int32_t* n_contrib, int W, int H, int C, uint32_t* n_empty,
+                             double* entropy_sum, char* scratch, hipStream_t st) {
+    const int64_t P = (int64_t)W * H;
+    const unsigned grid = (unsigned)div_up(P, kBlock);
+    double* bh = (double*)scratch;
+    uint32_t* be = (uint32_t*)(scratch + sizeof(double) * grid);
+    uint32_t* done = (uint32_t*)(scratch + (sizeof(double) + sizeof(uint32_t)) * grid);
+    zero_u32<<<1, 1, 0, st>>>(done);
+    score_maps_kernel<<<grid, kBlock, 0, st>>>(sem, n_contrib, P, C, bh, be, done, n_empty, entropy_sum);
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+}  // namespace sgr

@@ -1,0 +1,64 @@
+// Internal definitions shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sgr.h"
+
+namespace sgr {
+
+constexpr int kTile = 16;          // tile edge in pixels (16x16 = 256 pixels = 4 wave64)
+constexpr int kBlock = 256;        // threads per tile workgroup
+constexpr int kMaxK = 32;          // top-k limit
+constexpr int kMaxC = 256;         // class limit (u8 indices)
+constexpr int kAccStride = 257;    // LDS class-major stride: conflict-free for consecutive pixels
+constexpr uint32_t kInvalid = 0xffffffffu;
+
+// counters[] slots at the start of the workspace
+enum Counter : int {
+    kStatus = 0,      // bit 1: capacity exceeded
+    kNumVisible = 1,  // visible (view, Gaussian) pairs
+    kNumKeys = 2,     // tile keys (saturates at capacity+1 for the status check)
+    kWork = 3,        // persistent-kernel work ticket
+    kDone = 4,        // persistent-kernel finished-block count
+    kKeysLo = 5,      // exact key count, low 32 bits (the scan total)
+    kNumCounters = 16
+};
+
+// Per-view table on the device (64-byte aligned rows).
+struct alignas(16) ViewDev {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height, tiles_x, tiles_y;
+    int32_t tile_off;   // first global tile of this view
+    int32_t pad0;
+    int64_t pix_off;    // first pixel of this view in the per-pixel workspace arrays
+};
+
+// Projected record of one (view, Gaussian) pair, 48 bytes.
+//   r0 = (ix, iy as int bits, fx, fy): pixel-space mean = (ix + fx, iy + fy),
+//        integer part exact, fraction in [0,1) to fp32 precision
+//   r1 = (ca, cb, cc, o): exponent of the splat in base 2,
+//        log2 G = -(ca*u^2 + cc*dy^2), u = dx + cb*dy, with
+//        ca = a/(2 ln 2), cb = b/a, cc = (c - b^2/a)/(2 ln 2) for the conic
+//        Q = a dx^2 + 2 b dx dy + c dy^2 (both terms are non-negative, so
+//        fp32 evaluation has no cancellation)
+//   r2 = (col_lo | col_hi << 16, row_lo | row_hi << 16, z, 0)
+struct Proj {
+    float4 r0, r1, r2;
+};
+
+__host__ __device__ inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Tile launches are padded to a multiple of 8 workgroups.  Workgroup i runs
+// on XCD i % 8; mapping it to tile (i % 8) * (grid / 8) + i / 8 gives each
+// XCD a contiguous run of tiles, so neighbouring tiles (which share
+// Gaussians) hit the same L2.  Tiles past the real count exit at once.
+__device__ inline int xcd_remap(int bid, int grid8) {
+    const int per = grid8 >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+}  // namespace sgr

@@ -1,0 +1,47 @@
+// Scan and radix-sort launchers (device code in sort.hip).
+#pragma once
+
+#include "sgr_internal.h"
+
+namespace sgr {
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = 256 * kScanItems;
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = 256 * kRadixItems;
+
+// Element count of a scan or sort: *d_n if d_n is set (device-resident,
+// known only on the GPU), else host_n; clamped to cap when cap != 0.
+// radix_blocks: the count is 256 digit bins times the radix block count of n.
+struct CountSpec {
+    const uint32_t* d_n;
+    uint32_t host_n;
+    uint32_t cap;
+    uint32_t radix_blocks;
+};
+
+inline CountSpec host_count(uint32_t n) { return CountSpec{nullptr, n, 0, 0}; }
+inline CountSpec device_count(const uint32_t* d, uint32_t cap) { return CountSpec{d, 0, cap, 0}; }
+
+// Exclusive scan of in[0..n) into out (may alias in).  max_n bounds n and
+// sizes the grid; partial needs div_up(max_n, kScanTile) words.  The total
+// goes to *total_out (if set); total > cap sets SGR_ECAPACITY in *status.
+void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
+                    uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st);
+
+// Block sums of (in[i] != 0) over in[0..n), scanned: partial[b] is the
+// number of non-zero items before block b (blocks of kScanTile); the total
+// goes to *total_out.
+void scan_flag_partials(const uint32_t* in, uint32_t n, uint32_t* partial, uint32_t* total_out, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
+// 8 bits per pass, ping-ponging between the a and b buffers.  Returns the
+// pass count: the result is in the a buffers when it is even, else in b.
+// vals_identity: the a values are not read; value i is taken to be i.
+int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
+               CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st);
+
+inline size_t radix_hist_words(uint32_t max_n) { return 256u * (size_t)div_up(max_n, kRadixTile); }
+inline size_t scan_partial_words(size_t max_n) { return (size_t)div_up((int64_t)max_n, kScanTile) + 1; }
+
+}  // namespace sgr

@@ -1,0 +1,227 @@
+// Prefix scans and the stable LSD radix sort used for depth ordering and
+// tile binning.  Reduce-then-scan everywhere: no kernel waits on another
+// workgroup, so nothing here can spin.
+#include "sort.h"
+
+namespace sgr {
+
+__device__ __forceinline__ uint32_t count_of(const CountSpec& c) {
+    uint32_t n = c.d_n ? *c.d_n : c.host_n;
+    if (c.cap && n > c.cap) n = c.cap;
+    if (c.radix_blocks) n = 256u * (uint32_t)div_up(n, kRadixTile);
+    return n;
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads).
+__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t s = wsum[j];
+        pre += (j < w) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+template <bool FLAG>
+__global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restrict__ in, CountSpec cs,
+                                                       uint32_t* __restrict__ partial) {
+    __shared__ uint32_t wsum[4];
+    const uint32_t n = count_of(cs);
+    const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
+    if (blockIdx.x >= nblk) return;
+    const uint32_t base = blockIdx.x * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; r++) {
+        const uint32_t i = base + r * 256 + threadIdx.x;
+        if (i < n) {
+            const uint32_t x = in[i];
+            s += FLAG ? (x != 0u) : x;
+        }
+    }
+    uint32_t tot;
+    block_exscan(s, wsum, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// One workgroup: exclusive scan of partial[0..nblk) in place; writes the
+// grand total to *total_out (and, if given, the saturating capacity check).
+__global__ __launch_bounds__(256) void scan_partials(uint32_t* __restrict__ partial, CountSpec cs,
+                                                     uint32_t* __restrict__ total_out, uint32_t cap,
+                                                     uint32_t* __restrict__ status) {
+    __shared__ uint32_t wsum[4];
+    const uint32_t n = count_of(cs);
+    const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nblk; b0 += 256 * 8) {
+        uint32_t v[8], s = 0;
+#pragma unroll
+        for (int r = 0; r < 8; r++) {
+            const uint32_t i = b0 + threadIdx.x * 8 + r;
+            v[r] = i < nblk ? partial[i] : 0u;
+            s += v[r];
+        }
+        uint32_t tot;
+        uint32_t pre = block_exscan(s, wsum, &tot) + carry;
+#pragma unroll
+        for (int r = 0; r < 8; r++) {
+            const uint32_t i = b0 + threadIdx.x * 8 + r;
+            if (i < nblk) partial[i] = pre;
+            pre += v[r];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        if (total_out) *total_out = carry;
+        if (status && carry > cap) atomicOr(status, (uint32_t)SGR_ECAPACITY);
+    }
+}
+
+// Exclusive scan of `in` into `out` (may alias) using the scanned partials.
+__global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec cs,
+                                                  const uint32_t* __restrict__ partial, uint32_t* out) {
+    __shared__ uint32_t wsum[4];
+    const uint32_t n = count_of(cs);
+    const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
+    if (blockIdx.x >= nblk) return;
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanItems; r++) {
+        const uint32_t i = base + r;
+        v[r] = i < n ? in[i] : 0u;
+        s += v[r];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exscan(s, wsum, &tot) + partial[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < kScanItems; r++) {
+        const uint32_t i = base + r;
+        if (i < n) out[i] = pre;
+        pre += v[r];
+    }
+}
+
+// Note: scan_block_sums reads items strided by 256 while scan_apply reads
+// kScanItems consecutive items per thread; both cover the same kScanTile
+// items per block, which is all the block sums need.
+
+void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
+                    uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st) {
+    const uint32_t nblk_max = (uint32_t)div_up(max_n, kScanTile);
+    if (nblk_max == 0) return;
+    scan_block_sums<false><<<nblk_max, 256, 0, st>>>(in, cs, partial);
+    scan_partials<<<1, 256, 0, st>>>(partial, cs, total_out, cap, status);
+    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out);
+}
+
+// ------------------------------------------------------------------ radix
+
+__global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ keys, CountSpec cs, int shift,
+                                                  uint32_t* __restrict__ hist) {
+    __shared__ uint32_t cnt[256];
+    const uint32_t n = count_of(cs);
+    const uint32_t nblk = (uint32_t)div_up(n, kRadixTile);
+    if (blockIdx.x >= nblk) return;
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kRadixTile;
+#pragma unroll 4
+    for (int r = 0; r < kRadixItems; r++) {
+        const uint32_t i = base + r * 256 + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter of one 8-bit digit.  Items are taken in index order, 256
+// per round; within a wave the rank among equal digits comes from eight
+// ballots, across the four waves from per-digit wave counts in LDS.
+__global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict__ kin,
+                                                     const uint32_t* __restrict__ vin,
+                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                     CountSpec cs, int shift,
+                                                     const uint32_t* __restrict__ hist) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[4][256];
+    const uint32_t n = count_of(cs);
+    const uint32_t nblk = (uint32_t)div_up(n, kRadixTile);
+    if (blockIdx.x >= nblk) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    run[tid] = hist[tid * nblk + blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < 4; j++) wc[j][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t base = blockIdx.x * kRadixTile;
+    for (int r = 0; r < kRadixItems; r++) {
+        const uint32_t i = base + r * 256 + tid;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t val = valid ? (vin ? vin[i] : i) : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            match &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = __popcll(match & lt);
+        if (valid && rank == 0) wc[w][d] = __popcll(match);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = run[d] + rank;
+            for (int j = 0; j < w; j++) off += wc[j][d];
+            kout[off] = key;
+            vout[off] = val;
+        }
+        __syncthreads();
+        run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+        wc[0][tid] = 0; wc[1][tid] = 0; wc[2][tid] = 0; wc[3][tid] = 0;
+        __syncthreads();
+    }
+}
+
+void scan_flag_partials(const uint32_t* in, uint32_t n, uint32_t* partial, uint32_t* total_out, hipStream_t st) {
+    const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
+    if (nblk == 0) return;
+    scan_block_sums<true><<<nblk, 256, 0, st>>>(in, host_count(n), partial);
+    scan_partials<<<1, 256, 0, st>>>(partial, host_count(n), total_out, 0, nullptr);
+}
+
+int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
+               CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st) {
+    const uint32_t nblk_max = (uint32_t)div_up(max_n, kRadixTile);
+    if (nblk_max == 0) return 0;
+    int passes = (bits + 7) / 8;
+    uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
+    CountSpec hs = cs;
+    hs.radix_blocks = 1;
+    for (int p = 0; p < passes; p++) {
+        radix_hist<<<nblk_max, 256, 0, st>>>(ki, cs, 8 * p, hist);
+        scan_exclusive(hist, hist, hs, 256u * nblk_max, partial, nullptr, 0, nullptr, st);
+        radix_scatter<<<nblk_max, 256, 0, st>>>(ki, (p == 0 && vals_identity) ? nullptr : vi, ko, vo, cs, 8 * p,
+                                                hist);
+        uint32_t* t;
+        t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    return passes;
+}
+
+}  // namespace sgr

@@ -1,0 +1,256 @@
+"""Torch-facing layer over libsgr: device memory and streams come from
+PyTorch, every step of the rasterizer runs in the HIP library.
+
+    frame = Frame(n, cameras, make_config(C, k))
+    maps = render(gaussians, frame)                 # autograd-aware
+    n_empty, entropy = frame.score(gaussians)       # candidate-view scoring
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+DEFAULTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, z_near=0.2, lowpass=0.3)
+
+
+def make_config(num_classes: int, top_k: int, sem_grad_to_geometry: int = 0, **kw) -> L.sgr_config:
+    d = dict(DEFAULTS)
+    d.update(kw)
+    return L.sgr_config(d["alpha_min"], d["alpha_max"], d["t_min"], d["z_near"], d["lowpass"], int(num_classes),
+                        int(top_k), int(sem_grad_to_geometry), 16, 16)
+
+
+def camera_array(cams):
+    arr = (L.sgr_camera * len(cams))()
+    for j, c in enumerate(cams):
+        R = [float(x) for x in c.R.reshape(-1)]
+        t = [float(x) for x in c.t.reshape(-1)]
+        arr[j] = L.sgr_camera((ctypes.c_float * 9)(*R), (ctypes.c_float * 3)(*t), c.fx, c.fy, c.cx, c.cy,
+                              int(c.width), int(c.height))
+    return arr
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Gaussians:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opacity: torch.Tensor
+    rgb: torch.Tensor
+    sem_val: torch.Tensor
+    sem_idx: torch.Tensor  # uint8
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def k(self) -> int:
+        return int(self.sem_val.shape[1])
+
+    def c_struct(self) -> L.sgr_gaussians:
+        for name in ("means", "scales", "quats", "opacity", "rgb", "sem_val"):
+            t = getattr(self, name)
+            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name}: need a contiguous float32 CUDA tensor")
+        if self.sem_idx.dtype != torch.uint8 or not self.sem_idx.is_contiguous():
+            raise ValueError("sem_idx: need a contiguous uint8 tensor")
+        return L.sgr_gaussians(self.n, _ptr(self.means), _ptr(self.scales), _ptr(self.quats), _ptr(self.opacity),
+                               _ptr(self.rgb), _ptr(self.sem_val), _ptr(self.sem_idx))
+
+    @staticmethod
+    def from_scene(scene, device="cuda") -> "Gaussians":
+        f = lambda a: torch.from_numpy(a).to(device=device, dtype=torch.float32).contiguous()
+        return Gaussians(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opacity), f(scene.rgb),
+                         f(scene.sem_val), torch.from_numpy(scene.sem_idx).to(device).contiguous())
+
+
+class Frame:
+    """Cameras, config and the library workspace for one batch of views."""
+
+    def __init__(self, n: int, cams, cfg: L.sgr_config, key_capacity: int | None = None, device="cuda"):
+        L.lib()
+        self.n = int(n)
+        self.cam_list = list(cams)
+        self.cams = camera_array(self.cam_list)
+        self.V = len(self.cam_list)
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.sizes = [(int(c.height), int(c.width)) for c in self.cam_list]
+        self.pix = [h * w for h, w in self.sizes]
+        self.pix_off = [0]
+        for p in self.pix:
+            self.pix_off.append(self.pix_off[-1] + p)
+        self.key_capacity = int(key_capacity or max(1 << 16, 2 * self.n * self.V))
+        self._alloc()
+
+    def _alloc(self):
+        size = L.sgr_workspace_size(self.n, self.cams, self.V, self.cfg, self.key_capacity)
+        if size == 0:
+            raise L.SgrError(L.SGR_EINVAL, "sgr_workspace_size")
+        self.ws = torch.empty(size, dtype=torch.uint8, device=self.device)
+        self.layout = L.sgr_workspace_layout(self.n, self.cams, self.V, self.cfg, self.key_capacity)
+
+    @property
+    def stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _args(self):
+        return (self.cams, self.V, self.cfg, self.key_capacity)
+
+    # ------------------------------------------------------------ pipeline steps
+
+    def project(self, g: Gaussians):
+        L.check(L.sgr_project(g.c_struct(), *self._args(), _ptr(self.ws), self.ws.numel(), self.stream), "sgr_project")
+
+    def bin(self, g: Gaussians, d_num_keys=None):
+        L.check(L.sgr_bin(g.c_struct(), *self._args(), _ptr(d_num_keys), _ptr(self.ws), self.ws.numel(), self.stream),
+                "sgr_bin")
+
+    def status(self):
+        """(status, visible pairs, keys); synchronises the stream."""
+        return L.sgr_read_status(_ptr(self.ws), self.stream)
+
+    def prepare(self, g: Gaussians, check: bool = True):
+        """project + bin; with check, grows the key capacity when exceeded."""
+        for _ in range(3):
+            self.project(g)
+            self.bin(g)
+            if not check:
+                return
+            st, _, nk = self.status()
+            if st == L.SGR_ECAPACITY:
+                self.key_capacity = int(nk * 1.25) + 1024
+                self._alloc()
+                continue
+            L.check(st, "device status")
+            return
+        raise L.SgrError(L.SGR_ECAPACITY, "prepare")
+
+    def alloc_maps(self, want=("rgb", "depth", "sil", "sem")):
+        P = self.pix_off[-1]
+        C = self.cfg.num_classes
+        dev = self.device
+        maps = {
+            "rgb": torch.empty((P, 3), device=dev) if "rgb" in want else None,
+            "depth": torch.empty(P, device=dev) if "depth" in want else None,
+            "sil": torch.empty(P, device=dev) if "sil" in want else None,
+            "sem": torch.empty((P, C), device=dev) if "sem" in want else None,
+            "t_final": torch.empty(P, device=dev),
+            "n_contrib": torch.empty(P, dtype=torch.int32, device=dev),
+        }
+        return maps
+
+    def _view_ptrs(self, flat, ch, elem):
+        if flat is None:
+            return [None] * self.V
+        base = flat.data_ptr()
+        return [ctypes.c_void_p(base + self.pix_off[v] * ch * elem) for v in range(self.V)]
+
+    def forward(self, g: Gaussians, maps=None):
+        maps = maps if maps is not None else self.alloc_maps()
+        C = self.cfg.num_classes
+        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C, "t_final": 1, "n_contrib": 1}
+        ptrs = {key: self._view_ptrs(maps.get(key), cols[key], 4) for key in cols}
+        arr = (L.sgr_maps * self.V)()
+        for v in range(self.V):
+            arr[v] = L.sgr_maps(ptrs["rgb"][v], ptrs["depth"][v], ptrs["sil"][v], ptrs["sem"][v],
+                                ptrs["t_final"][v], ptrs["n_contrib"][v])
+        L.check(L.sgr_render_forward(g.c_struct(), *self._args(), arr, _ptr(self.ws), self.ws.numel(), self.stream),
+                "sgr_render_forward")
+        return maps
+
+    def backward(self, g: Gaussians, grads: dict, out: dict | None = None):
+        C = self.cfg.num_classes
+        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C}
+        gp = {}
+        for key in cols:
+            t = grads.get(key)
+            if t is not None:
+                t = t.contiguous()
+                if t.dtype != torch.float32:
+                    t = t.float()
+                grads[key] = t
+            gp[key] = self._view_ptrs(t, cols[key], 4)
+        arr = (L.sgr_map_grads * self.V)()
+        for v in range(self.V):
+            arr[v] = L.sgr_map_grads(gp["rgb"][v], gp["depth"][v], gp["sil"][v], gp["sem"][v])
+        if out is None:
+            out = {name: torch.empty_like(getattr(g, name)) for name in
+                   ("means", "scales", "quats", "opacity", "rgb", "sem_val")}
+        gr = L.sgr_grads(*[_ptr(out[name]) for name in ("means", "scales", "quats", "opacity", "rgb", "sem_val")])
+        L.check(L.sgr_render_backward(g.c_struct(), *self._args(), arr, gr, _ptr(self.ws), self.ws.numel(),
+                                      self.stream), "sgr_render_backward")
+        return out
+
+    def score(self, g: Gaussians, n_empty=None, entropy_sum=None):
+        n_empty = n_empty if n_empty is not None else torch.empty(self.V, dtype=torch.int32, device=self.device)
+        entropy_sum = entropy_sum if entropy_sum is not None else torch.empty(self.V, dtype=torch.float64,
+                                                                                device=self.device)
+        L.check(L.sgr_score_views(g.c_struct(), *self._args(), _ptr(n_empty), _ptr(entropy_sum), _ptr(self.ws),
+                                  self.ws.numel(), self.stream), "sgr_score_views")
+        return n_empty, entropy_sum
+
+    def split(self, flat):
+        """Per-view [H, W, ...] views of a flat [sum HW, ...] tensor."""
+        out = []
+        for v, (h, w) in enumerate(self.sizes):
+            t = flat[self.pix_off[v]:self.pix_off[v + 1]]
+            out.append(t.reshape(h, w, *flat.shape[1:]))
+        return out
+
+    # ------------------------------------------------------------ inspection
+
+    def workspace_u32(self, offset: int, count: int) -> torch.Tensor:
+        return self.ws[offset:offset + 4 * count].view(torch.int32)
+
+
+def score_maps(sem: torch.Tensor, n_contrib: torch.Tensor, num_classes: int, scratch: torch.Tensor | None = None,
+               n_empty=None, entropy_sum=None):
+    """Plain scoring of one dense view: sem [H, W, C], n_contrib [H, W]."""
+    H, W = int(n_contrib.shape[0]), int(n_contrib.shape[1])
+    need = L.sgr_score_maps_workspace_size(W, H)
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=sem.device)
+    n_empty = n_empty if n_empty is not None else torch.empty(1, dtype=torch.int32, device=sem.device)
+    entropy_sum = entropy_sum if entropy_sum is not None else torch.empty(1, dtype=torch.float64, device=sem.device)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(sem.device).cuda_stream)
+    L.check(L.sgr_score_maps(_ptr(sem), _ptr(n_contrib), W, H, int(num_classes), _ptr(n_empty), _ptr(entropy_sum),
+                             _ptr(scratch), scratch.numel(), stream), "sgr_score_maps")
+    return n_empty, entropy_sum
+
+
+class _Render(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, frame, sem_idx, check, means, scales, quats, opacity, rgb, sem_val):
+        g = Gaussians(means.detach(), scales.detach(), quats.detach(), opacity.detach(), rgb.detach(),
+                      sem_val.detach(), sem_idx)
+        frame.prepare(g, check=check)
+        maps = frame.forward(g)
+        ctx.frame = frame
+        ctx.g = g
+        ctx.mark_non_differentiable(maps["t_final"], maps["n_contrib"])
+        return maps["rgb"], maps["depth"], maps["sil"], maps["sem"], maps["t_final"], maps["n_contrib"]
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_sil, g_sem, _gt, _gn):
+        grads = ctx.frame.backward(ctx.g, {"rgb": g_rgb, "depth": g_depth, "sil": g_sil, "sem": g_sem})
+        return (None, None, None, grads["means"], grads["scales"], grads["quats"], grads["opacity"], grads["rgb"],
+                grads["sem_val"])
+
+
+def render(g: Gaussians, frame: Frame, check: bool = True):
+    """Differentiable render of every view of `frame`.  Returns flat
+    [sum HW, ...] tensors rgb, depth, sil, sem, t_final, n_contrib
+    (frame.split gives per-view images)."""
+    rgb, depth, sil, sem, t_final, n_contrib = _Render.apply(frame, g.sem_idx, check, g.means, g.scales, g.quats,
+                                                             g.opacity, g.rgb, g.sem_val)
+    return {"rgb": rgb, "depth": depth, "sil": sil, "sem": sem, "t_final": t_final, "n_contrib": n_contrib}
