@@ -1,0 +1,311 @@
+"""Benchmark of the semantic Gaussian rasterizer on one MI355X.
+
+Step = one mapping iteration on 1M Gaussians in a 10x8x3 m room seen by one
+1200x680 keyframe (fx=fy=600): project -> bin -> render_forward -> loss
+gradient -> render_backward -> Adam.  The loss is the mapping loss with the
+silhouette mask (S > 0.99: L1 depth + 0.5 L1 colour), plus L1(S, 1) and a
+cross-entropy on the semantic map.  Throughput is Gaussian-pixel blends per
+second (blends = sum of n_contrib, exact).  Candidate-view scoring (500k
+Gaussians, 64 views of mixed resolution) is timed batched and one view per
+launch.  Synthetic, seeded inputs; everything is resident in HBM before the
+timed region starts.
+
+    python bench.py [--gpus 1] [--steps 40] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd ms/iter & Gaussian-pixel blends/s @1M G 1200x680; views/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--score-views", type=int, default=64)
+    ap.add_argument("--score-n", type=int, default=500_000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-score", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream every library call
+    is enqueued on)."""
+
+    def __init__(self, torch, names):
+        self.torch = torch
+        self.names = names
+        self.ev = {nm: [] for nm in names}
+
+    def mark(self, name):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.ev[name].append(e)
+        return e
+
+    def pairs_ms(self, a, b):
+        return [x.elapsed_time(y) for x, y in zip(self.ev[a], self.ev[b])]
+
+
+def mapping_bench(args, torch, out):
+    from paper_2506_00225_amd import Frame, Gaussians, make_config, scenes
+
+    log("generating room scene", args.n)
+    sc = scenes.room_scene(n=args.n)
+    cam = sc.cameras[0]
+    H, W, C, k = cam.height, cam.width, sc.num_classes, sc.k
+    P = H * W
+    g = Gaussians.from_scene(sc)
+    params = [g.means, g.scales, g.quats, g.opacity, g.rgb, g.sem_val]
+    cfg = make_config(C, k)
+    fr = Frame(sc.n, [cam], cfg)
+    fr.prepare(g, check=True)
+    st, nvis, nkeys = fr.status()
+    fr.key_capacity = int(nkeys * 1.5) + 4096
+    fr._alloc()
+    dev = g.means.device
+    t_rgb = torch.from_numpy(sc.targets["rgb"]).to(dev).reshape(P, 3)
+    t_depth = torch.from_numpy(sc.targets["depth"]).to(dev).reshape(P)
+    label = torch.from_numpy(sc.targets["label"]).to(dev).reshape(P).long()
+    maps = fr.alloc_maps()
+    grads_in = {"rgb": torch.empty(P, 3, device=dev), "depth": torch.empty(P, device=dev),
+                "sil": torch.empty(P, device=dev), "sem": torch.zeros(P, C, device=dev)}
+    gout = {nm: torch.empty_like(getattr(g, nm)) for nm in ("means", "scales", "quats", "opacity", "rgb", "sem_val")}
+    opt = torch.optim.Adam(params, lr=1e-3, betas=(0.9, 0.999), foreach=True)
+    for p_, nm in zip(params, ("means", "scales", "quats", "opacity", "rgb", "sem_val")):
+        p_.grad = gout[nm]
+    blends = torch.zeros(args.steps + args.warmup, dtype=torch.int64, device=dev)
+    rows = torch.arange(P, device=dev)
+
+    def loss_grad():
+        # L = mean_p [ m (|D - D*| + 0.5 sum_c |C - C*|) + |S - 1| - ln max(P_label, 1e-6) ],  m = [S > 0.99]
+        s = maps["sil"]
+        m = (s > 0.99).float() / P
+        torch.mul(torch.sign(maps["depth"] - t_depth), m, out=grads_in["depth"])
+        torch.mul(torch.sign(maps["rgb"] - t_rgb), (0.5 * m).unsqueeze(1), out=grads_in["rgb"])
+        grads_in["sil"].fill_(-1.0 / P)
+        pl = maps["sem"][rows, label]
+        gsem = grads_in["sem"]
+        gsem.zero_()
+        gsem[rows, label] = torch.where(pl > 1e-6, -1.0 / (P * pl.clamp_min(1e-6)), torch.zeros_like(pl))
+
+    names = ["s0", "proj", "bin", "fwd", "loss", "bwd", "adam"]
+    tm = Timer(torch, names)
+
+    def step(i, timed):
+        mk = tm.mark if timed else (lambda _n: None)
+        mk("s0")
+        fr.project(g)
+        mk("proj")
+        fr.bin(g)
+        mk("bin")
+        fr.forward(g, maps)
+        mk("fwd")
+        torch.sum(maps["n_contrib"], dtype=torch.int64, out=blends[i])
+        loss_grad()
+        mk("loss")
+        fr.backward(g, grads_in, gout)
+        mk("bwd")
+        opt.step()
+        with torch.no_grad():
+            g.opacity.clamp_(1e-4, 0.9999)
+            g.sem_val.clamp_(min=0.0)
+        mk("adam")
+
+    log("warmup", args.warmup)
+    for i in range(args.warmup):
+        step(i, False)
+    torch.cuda.synchronize()
+    log("timed", args.steps)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st, nvis, nkeys = fr.status()
+    if st != 0:
+        raise RuntimeError(f"device status {st} after the timed steps (key capacity {fr.key_capacity}, K {nkeys})")
+    stage = {}
+    for a, b in zip(names[:-1], names[1:]):
+        stage[b] = float(np.mean(tm.pairs_ms(a, b)))
+    step_ms = float(np.mean(tm.pairs_ms("s0", "adam")))
+    B = blends[args.warmup:].double().mean().item()
+    fwd_bwd_ms = stage["proj"] + stage["bin"] + stage["fwd"] + stage["bwd"]
+    out.update(dict(step_ms=step_ms, wall_ms=wall * 1e3 / args.steps, stage_ms=stage, blends=B, nvis=nvis, keys=nkeys,
+                    fwd_bwd_ms=fwd_bwd_ms, pixels=P, C=C, k=k, n=sc.n))
+    log("stages ms", json.dumps({k_: round(v, 4) for k_, v in stage.items()}), "K", nkeys, "Nv", nvis, "B", B)
+    return sc
+
+
+def roofline(out):
+    """Algorithmic bytes of the dominant kernel call per launch (see the
+    design notes for the per-unit figures)."""
+    P, C, k, K, Nv, n = out["pixels"], out["C"], out["k"], out["keys"], out["nvis"], out["n"]
+    rec = 48 + 16 + 4 * k + ((k + 3) // 4) * 4  # projected record + rgb/z + top-k values + indices
+    alg = {
+        # read records once, sorted ids once; write maps and the two per-pixel words
+        "fwd": rec * Nv + 4 * K + P * (5 + C) * 4 + 8 * P,
+        # read dL/dmaps and per-pixel words, records and ids once; write per-Gaussian grads once
+        "bwd": P * (5 + C) * 4 + 8 * P + 4 * K + rec * Nv + (14 + k) * 4 * n + 44 * n,
+        "proj": 44 * n + (4 + 4 + 48) * n + 12 * Nv,
+        "bin": 12 * K * 3 + 8 * Nv,
+    }
+    stage = out["stage_ms"]
+    dom = max(("proj", "bin", "fwd", "bwd"), key=lambda s: stage[s])
+    t = stage[dom] * 1e-3
+    achieved = alg[dom] / t / 1e9
+    return dom, {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                 "alg_bytes": int(alg[dom]), "ms": round(stage[dom], 4)}
+
+
+def score_bench(args, torch, out):
+    from paper_2506_00225_amd import Frame, Gaussians, make_config, scenes, score_maps
+
+    log("generating candidate scene", args.score_n, args.score_views)
+    sc = scenes.candidate_scene(n=args.score_n, nviews=args.score_views)
+    g = Gaussians.from_scene(sc)
+    cfg = make_config(sc.num_classes, sc.k)
+    fr = Frame(sc.n, sc.cameras, cfg)
+    fr.prepare(g, check=True)
+    _, _, nk = fr.status()
+    fr.key_capacity = int(nk * 1.3) + 4096
+    fr._alloc()
+    ne = torch.empty(fr.V, dtype=torch.int32, device="cuda")
+    hs = torch.empty(fr.V, dtype=torch.float64, device="cuda")
+    reps = 10
+    for _ in range(2):
+        fr.score(g, ne, hs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fr.score(g, ne, hs)
+    e1.record()
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / reps
+    st, _, _ = fr.status()
+    assert st == 0
+    # plain: one frame per view, project/bin/render dense maps/score each
+    frames = []
+    for cam in sc.cameras:
+        f1 = Frame(sc.n, [cam], cfg)
+        f1.prepare(g, check=True)
+        frames.append((f1, f1.alloc_maps(want=("sem",)), cam))
+    pe = torch.empty(fr.V, dtype=torch.int32, device="cuda")
+    ph = torch.empty(fr.V, dtype=torch.float64, device="cuda")
+    scratch = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+
+    def plain():
+        for v, (f1, mp, cam) in enumerate(frames):
+            f1.project(g)
+            f1.bin(g)
+            f1.forward(g, mp)
+            score_maps(mp["sem"].view(cam.height, cam.width, -1), mp["n_contrib"].view(cam.height, cam.width),
+                       sc.num_classes, scratch, pe[v:v + 1], ph[v:v + 1])
+
+    plain()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        plain()
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / reps
+    P = np.array([c.width * c.height for c in sc.cameras], dtype=np.float64)
+    dmean = np.abs(ph.cpu().numpy() - hs.cpu().numpy()) / P
+    same_empty = bool(torch.equal(pe, ne))
+    out.update(dict(views_per_s_batched=fr.V / (batched_ms * 1e-3), views_per_s_plain=fr.V / (plain_ms * 1e-3),
+                    score_batched_ms=batched_ms, score_plain_ms=plain_ms, score_max_mean_entropy_diff=float(dmean.max()),
+                    score_n_empty_equal=same_empty, score_views=fr.V))
+    log("scoring batched", batched_ms, "ms plain", plain_ms, "ms")
+
+
+def cpu_baseline(sc, rows=48):
+    """The FP64 oracle (as it stands) on a band of `rows` image rows through
+    the middle of the same keyframe and the same 1M Gaussians: projection of
+    all Gaussians, forward render and analytic backward of the band."""
+    from oracle import oracle as O
+    from paper_2506_00225_amd import scenes
+
+    cam = sc.cameras[0]
+    band = scenes.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx, cam.cy - (cam.height - rows) / 2, cam.width, rows)
+    cfg = O.config_array()
+    rng = np.random.default_rng(0)
+    grads = {"rgb": rng.standard_normal((rows, cam.width, 3)), "depth": rng.standard_normal((rows, cam.width)),
+             "sil": rng.standard_normal((rows, cam.width)),
+             "sem": rng.standard_normal((rows, cam.width, sc.num_classes))}
+    t0 = time.perf_counter()
+    pr, mp = O.forward(O.scene_arrays(sc), band, cfg, sc.num_classes)
+    O.backward(O.scene_arrays(sc), band, cfg, sc.num_classes, grads, proj=pr)
+    t = time.perf_counter() - t0
+    B = int(mp["n_contrib"].sum())
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": B / t, "unit": "blends/s", "cores": threads, "kind": "oracle",
+            "sample": f"fwd+bwd of a {cam.width}x{rows} band through the keyframe centre, all {sc.n} Gaussians "
+                      f"projected; {B} blends in {t:.2f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); the rasterizer in this "
+              "repository has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    out = {}
+    sc = mapping_bench(args, torch, out)
+    if not args.no_score:
+        score_bench(args, torch, out)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(sc)
+    dom, roof = roofline(out)
+    value = out["blends"] / (out["step_ms"] * 1e-3)
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "blends/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(out["step_ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mapping iteration: 1M Gaussians, 10x8x3 m room, 1200x680 keyframe, C=102, k=16, "
+                               "fwd + loss + bwd + Adam", "gaussians": out["n"], "width": 1200, "height": 680,
+                   "classes": out["C"], "top_k": out["k"]},
+        "fwd_bwd_ms": round(out["fwd_bwd_ms"], 4),
+        "blends_per_s_fwd_bwd": round(out["blends"] / (out["fwd_bwd_ms"] * 1e-3), 1),
+        "blends_per_step": out["blends"], "keys": out["keys"], "visible": out["nvis"],
+        "stage_ms": {k_: round(v, 4) for k_, v in out["stage_ms"].items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    for key in ("views_per_s_batched", "views_per_s_plain", "score_batched_ms", "score_plain_ms",
+                "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views"):
+        if key in out:
+            line[key] = out[key]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -40,7 +40,7 @@ struct BwdArgs {
 // 6,7,8 rgb; 9 depth; 10.. semantic values.
 template <int KT>
 __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
-    extern __shared__ float smem[];
+    extern __shared__ __align__(16) float smem[];
     const TileArgs& a = b.t;
     const int gt = xcd_remap(blockIdx.x, gridDim.x);
     if (gt >= a.num_tiles) return;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
     __syncthreads();
     if (inside && last > start) atomicMax(&s_maxlast, last);
     __syncthreads();
-    const uint32_t maxlast = s_maxlast;
+    const uint32_t maxlast = __builtin_amdgcn_readfirstlane(s_maxlast);
     const float amin = a.alpha_min, amax = a.alpha_max;
     const float k2ln2 = 1.38629436111989061883f;  // 2 ln 2
     float R = 0.f;

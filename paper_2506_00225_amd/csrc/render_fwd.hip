@@ -49,7 +49,7 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min;
 
     for (uint32_t b0 = start; b0 < end; b0 += kFwdBatch) {
-        if (__syncthreads_count(done) == kBlock) break;
+        if (__builtin_amdgcn_readfirstlane(__syncthreads_count(done)) == kBlock) break;
         const int nb = (int)min((uint32_t)kFwdBatch, end - b0);
         if (tid < kFwdBatch) {
             if (tid < nb) {
@@ -134,7 +134,7 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
 
 template <int KT, int SEM>
 __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
-    extern __shared__ float smem[];
+    extern __shared__ __align__(16) float smem[];
     const int gt = xcd_remap(blockIdx.x, gridDim.x);
     if (gt >= a.num_tiles) return;
     if (a.counters[kStatus] & SGR_ECAPACITY) return;
@@ -176,15 +176,18 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
 
 // ------------------------------------------------------------------ scoring
 
-// Persistent: each workgroup takes (view, tile) items from a ticket counter
-// until none are left, composites the tile's silhouette count and semantic
-// accumulators, and writes the tile's empty-pixel count and summed entropy
-// to a fixed slot.  The last workgroup to finish reduces the slots of each
-// view in tile order (FP64), so the scores are deterministic.
+// Persistent: a grid of about one workgroup per CU walks the (view, tile)
+// items with a static stride.  Items are numbered so that the workgroups of
+// one XCD (workgroup i runs on XCD i % 8) cover one contiguous run of tiles.
+// Each item's silhouette count and semantic accumulators are composited, and
+// the tile's empty-pixel count and summed entropy go to a fixed slot.  The
+// last workgroup to finish reduces the slots of each view in tile order
+// (FP64), so the scores are deterministic.  The loop bounds depend only on
+// blockIdx and the grid, so every lane of every wave takes the same trip
+// count through the barriers.
 template <int KT>
 __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, ScoreOut so) {
-    extern __shared__ float smem[];
-    __shared__ int s_item;
+    extern __shared__ __align__(16) float smem[];
     __shared__ double s_h[4];
     __shared__ uint32_t s_e[4];
     __shared__ int s_last;
@@ -193,12 +196,13 @@ __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, Sc
     const int C = a.C;
     const float ln2 = 0.69314718055994530942f;
     const float lg_lo = -9.9657842846620870436f;  // log2(0.001)
-    for (;;) {
-        if (tid == 0) s_item = ok ? (int)atomicAdd(&a.counters[kWork], 1u) : (int)a.num_tiles;
-        __syncthreads();
-        const int gt = s_item;
-        __syncthreads();
-        if (gt >= a.num_tiles) break;
+    const int T = (int)a.num_tiles;
+    const int per = (T + 7) >> 3;       // tiles per XCD run
+    const int G = (int)gridDim.x;       // a multiple of 8
+    const int items = ok ? per * 8 : 0;
+    for (int item = (int)blockIdx.x; item < items; item += G) {
+        const int gt = (item & 7) * per + (item >> 3);
+        if (gt >= T) continue;
         TileResult r;
         composite_tile<KT, 1>(a, gt, smem, r);
         __syncthreads();
@@ -225,6 +229,7 @@ __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, Sc
             so.tile_h[gt] = ((s_h[0] + s_h[1]) + s_h[2]) + s_h[3];
             so.tile_e[gt] = s_e[0] + s_e[1] + s_e[2] + s_e[3];
         }
+        __syncthreads();
     }
     __threadfence();
     __syncthreads();
@@ -387,7 +392,8 @@ sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, c
     const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, 1);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
     const int per_cu = std::max<int>(1, (int)(device_max_lds() / (lds + 4096)));
-    const unsigned grid = (unsigned)std::min<int64_t>(P.num_tiles, (int64_t)device_cu_count() * per_cu);
+    const int64_t want = std::min<int64_t>(P.num_tiles, (int64_t)device_cu_count() * per_cu);
+    const unsigned grid = (unsigned)(div_up(want, 8) * 8);
     if (P.k == 16) {
         set_lds(score_persistent_kernel<16>, lds);
         score_persistent_kernel<16><<<grid, kBlock, lds, st>>>(a, so);

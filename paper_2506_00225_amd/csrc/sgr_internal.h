@@ -20,7 +20,7 @@ enum Counter : int {
     kStatus = 0,      // bit 1: capacity exceeded
     kNumVisible = 1,  // visible (view, Gaussian) pairs
     kNumKeys = 2,     // tile keys (saturates at capacity+1 for the status check)
-    kWork = 3,        // persistent-kernel work ticket
+    kWork = 3,        // reserved
     kDone = 4,        // persistent-kernel finished-block count
     kKeysLo = 5,      // exact key count, low 32 bits (the scan total)
     kNumCounters = 16

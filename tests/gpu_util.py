@@ -103,14 +103,17 @@ def tainted_gaussians(proj, flags):
 
 
 def compare_grads(got: dict, want: dict, exclude: np.ndarray, rtol=1e-3):
+    """Per parameter tensor: relative L2 error over all Gaussians <= rtol, and
+    element-wise |d| <= rtol |ref| + rtol rms(ref) on Gaussians that cover no
+    flagged pixel (where both compositing outcomes are correct)."""
     keep = ~exclude
     report = {"excluded": int(exclude.sum())}
     for name, ref in want.items():
-        g = got[name].astype(np.float64)[keep]
-        r = ref[keep]
-        d = g - r
-        rms = float(np.sqrt(np.mean(r * r))) + 1e-30
-        nrm = float(np.linalg.norm(d) / (np.linalg.norm(r) + 1e-30))
+        gall = got[name].astype(np.float64)
+        dall = gall - ref
+        nrm = float(np.linalg.norm(dall) / (np.linalg.norm(ref) + 1e-30))
+        d, r = dall[keep], ref[keep]
+        rms = float(np.sqrt(np.mean(ref * ref))) + 1e-30
         worst = float(np.max(np.abs(d) - rtol * np.abs(r) - rtol * rms)) if d.size else -1.0
         report[name] = (nrm, worst)
         assert nrm <= rtol, (name, report)
