@@ -120,7 +120,7 @@ def mapping_bench(args, torch, out):
         mk("bin")
         fr.forward(g, maps)
         mk("fwd")
-        torch.sum(maps["n_contrib"], dtype=torch.int64, out=blends[i])
+        blends[i].copy_(maps["n_contrib"].sum(dtype=torch.int64))
         loss_grad()
         mk("loss")
         fr.backward(g, grads_in, gout)

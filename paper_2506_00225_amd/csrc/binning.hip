@@ -177,29 +177,48 @@ __global__ __launch_bounds__(256) void compact_visible(const uint32_t* __restric
 
 // --------------------------------------------------------------- gather
 
-// Gathers the records of visible pairs in front-to-back order g.
+// Gathers the records of visible pairs in front-to-back order g.  Bit 31 of
+// the record's view word flags a Gaussian whose top-k list repeats a class
+// (the compositing kernels then add its values one at a time).
 __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
     const uint32_t g = blockIdx.x * 256u + threadIdx.x;
     const uint32_t nv = a.counters[kNumVisible];
     if (g >= nv) return;
     const uint32_t lin = a.order[g];
     const int64_t i = (int64_t)(lin % (uint64_t)a.n);
-    const Proj p = a.rec[lin];
-    a.srec[g] = p;
+    Proj p = a.rec[lin];
     a.scol[g] = make_float4(a.rgb[3 * i], a.rgb[3 * i + 1], a.rgb[3 * i + 2], p.r2.z);
     const int k = a.k;
-    for (int m = 0; m < k; m++) a.ssv[(size_t)g * k + m] = a.sem_val[i * k + m];
-    uint8_t* di = a.ssi + (size_t)g * a.kpad;
-    bool bad = false;
-    for (int m = 0; m < a.kpad; m++) {
-        uint8_t c = m < k ? a.sem_idx[i * k + m] : (uint8_t)0;
+    const float* sv = a.sem_val + i * k;
+    float* dv = a.ssv + (size_t)g * k;
+    if ((k & 3) == 0) {
+        for (int m = 0; m < k; m += 4) *(float4*)(dv + m) = *(const float4*)(sv + m);
+    } else {
+        for (int m = 0; m < k; m++) dv[m] = sv[m];
+    }
+    uint8_t cls[kMaxK];
+    bool bad = false, dup = false;
+    for (int m = 0; m < k; m++) {
+        uint8_t c = a.sem_idx[i * k + m];
         if ((int)c >= a.C) {  // never index past the class accumulators
             bad = true;
             c = 0;
         }
-        di[m] = c;
+        for (int q = 0; q < m; q++) dup |= cls[q] == c;
+        cls[m] = c;
+    }
+    uint32_t* di = (uint32_t*)(a.ssi + (size_t)g * a.kpad);
+    for (int w = 0; w < (a.kpad >> 2); w++) {
+        uint32_t word = 0;
+        for (int b = 0; b < 4; b++) {
+            const int m = 4 * w + b;
+            if (m < k) word |= (uint32_t)cls[m] << (8 * b);
+        }
+        di[w] = word;
     }
     if (bad) atomicOr(&a.counters[kStatus], Plan::kBadIndex);
+    p.r2.w = __uint_as_float(__float_as_uint(p.r2.w) | (dup ? 0x80000000u : 0u));
+    a.srec[g] = p;
     a.tcount[g] = a.count[lin];
     a.gp_of_lin[lin] = g;
 }
@@ -221,7 +240,7 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
         off[threadIdx.x] = a.toff[g];
         const float4 r2 = a.srec[g].r2;
         const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
-        const int v = __float_as_int(r2.w);
+        const int v = __float_as_int(r2.w) & 0x7fffffff;
         const int tx0 = (int)(rx & 0xffffu) / kTile, tx1 = (int)(rx >> 16) / kTile;
         const int ty0 = (int)(ry & 0xffffu) / kTile;
         const ViewDev& vw = a.views[v];

@@ -36,10 +36,18 @@ struct BwdArgs {
     int sem_in_lds;
 };
 
+constexpr int kBwdThreads = 128;  // 2 waves; each lane owns 2 pixels of the 16x16 tile
+constexpr int kBwdWaves = kBwdThreads / 64;
+
 // Per-key value layout: 0,1 mean2d; 2,3,4 conic (a, b, c); 5 opacity;
 // 6,7,8 rgb; 9 depth; 10.. semantic values.
+//
+// Wave w covers tile rows 8w..8w+7; lane l owns pixels (l & 15, 8w + (l >> 4))
+// and the one four rows below.  Per Gaussian the two pixels' terms are added
+// in registers and the wave reduces once, so a tile pays two wave reductions
+// per Gaussian instead of four.
 template <int KT>
-__global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
+__global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     extern __shared__ __align__(16) float smem[];
     const TileArgs& a = b.t;
     const int gt = xcd_remap(blockIdx.x, gridDim.x);
@@ -52,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
     constexpr int NVMAX = 10 + (KT > 0 ? KT : kMaxK);
     const int NV = 10 + k;
 
-    float* gp = smem;  // [C][257] dL/dsem of the tile's pixels (when staged)
+    float* gp = smem;  // [C][257] dL/dsem of the tile's pixels, column = ly * 16 + lx
     float* base = smem + (b.sem_in_lds ? acc_floats(C) : 0);
     float4* s_r0 = (float4*)base;
     float4* s_r1 = s_r0 + kBwdBatch;
@@ -60,58 +68,73 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
     float4* s_col = s_r2 + kBwdBatch;
     float* s_sv = (float*)(s_col + kBwdBatch);
     uint32_t* s_si = (uint32_t*)(s_sv + kBwdBatch * k);
-    float* part = (float*)(s_si + kBwdBatch * kw);           // [4][kBwdBatch][NV]
-    uint32_t* flag = (uint32_t*)(part + 4 * kBwdBatch * NV);   // [4][kBwdBatch]
+    float* part = (float*)(s_si + kBwdBatch * kw);                    // [waves][kBwdBatch][NV]
+    uint32_t* flag = (uint32_t*)(part + kBwdWaves * kBwdBatch * NV);  // [waves][kBwdBatch]
     __shared__ uint32_t s_maxlast;
 
     const int v = view_of_tile(a.views, a.V, gt);
     const ViewDev& vw = a.views[v];
     const int local = gt - vw.tile_off;
     const int tx = local % vw.tiles_x, ty = local / vw.tiles_x;
-    const int px = tx * kTile + (tid & (kTile - 1)), py = ty * kTile + (tid >> 4);
-    const bool inside = px < vw.width && py < vw.height;
+    const int lx = lane & 15;
+    const int ly0 = 8 * wv + (lane >> 4);
     const uint2 rg = a.ranges[gt];
     const uint32_t start = rg.x, end = rg.y;
     const GradPtrs gr = b.grads[v];
-    const int64_t pix = (int64_t)py * vw.width + px;
 
-    float T = 1.f;
-    uint32_t last = start;
-    float gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gS = 0.f;
-    if (inside) {
-        T = a.pix_T[vw.pix_off + pix];
-        last = a.pix_last[vw.pix_off + pix];
-        if (gr.rgb) { gC0 = gr.rgb[3 * pix]; gC1 = gr.rgb[3 * pix + 1]; gC2 = gr.rgb[3 * pix + 2]; }
-        if (gr.depth) gD = gr.depth[pix];
-        if (gr.sil) gS = gr.sil[pix];
+    int px[2], py[2], col_slot[2];
+    bool inside[2];
+    float T[2], gC0[2], gC1[2], gC2[2], gD[2], gS[2], R[2];
+    uint32_t last[2];
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int ly = ly0 + 4 * q;
+        px[q] = tx * kTile + lx;
+        py[q] = ty * kTile + ly;
+        col_slot[q] = ly * kTile + lx;
+        inside[q] = px[q] < vw.width && py[q] < vw.height;
+        T[q] = 1.f;
+        last[q] = start;
+        gC0[q] = gC1[q] = gC2[q] = gD[q] = gS[q] = R[q] = 0.f;
+        if (inside[q]) {
+            const int64_t pix = (int64_t)py[q] * vw.width + px[q];
+            T[q] = a.pix_T[vw.pix_off + pix];
+            last[q] = a.pix_last[vw.pix_off + pix];
+            if (gr.rgb) { gC0[q] = gr.rgb[3 * pix]; gC1[q] = gr.rgb[3 * pix + 1]; gC2[q] = gr.rgb[3 * pix + 2]; }
+            if (gr.depth) gD[q] = gr.depth[pix];
+            if (gr.sil) gS[q] = gr.sil[pix];
+        }
     }
     if (tid == 0) s_maxlast = start;
-    // stage dL/dsem for the tile, class-major
     if (b.sem_in_lds) {
         const int x0 = tx * kTile, y0 = ty * kTile;
         const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
         const int row_elems = kTile * C;
-        const int dl = kBlock / C, dc = kBlock % C;
+        const int dl = kBwdThreads / C, dc = kBwdThreads % C;
         for (int row = 0; row < kTile; row++) {
             const float* src = gr.sem ? gr.sem + ((int64_t)(y0 + row) * vw.width + x0) * C : nullptr;
-            int lx = tid / C, c = tid % C;
-            for (int e = tid; e < row_elems; e += kBlock) {
+            int cx = tid / C, c = tid % C;
+            for (int e = tid; e < row_elems; e += kBwdThreads) {
                 float val = 0.f;
-                if (src && row < hrows && lx < wcols) val = src[e];
-                gp[c * kAccStride + row * kTile + lx] = val;
-                lx += dl;
+                if (src && row < hrows && cx < wcols) val = src[e];
+                gp[c * kAccStride + row * kTile + cx] = val;
+                cx += dl;
                 c += dc;
-                if (c >= C) { c -= C; lx++; }
+                if (c >= C) { c -= C; cx++; }
             }
         }
     }
     __syncthreads();
-    if (inside && last > start) atomicMax(&s_maxlast, last);
+    {
+        uint32_t m = start;
+        if (inside[0] && last[0] > m) m = last[0];
+        if (inside[1] && last[1] > m) m = last[1];
+        if (m > start) atomicMax(&s_maxlast, m);
+    }
     __syncthreads();
     const uint32_t maxlast = __builtin_amdgcn_readfirstlane(s_maxlast);
     const float amin = a.alpha_min, amax = a.alpha_max;
     const float k2ln2 = 1.38629436111989061883f;  // 2 ln 2
-    float R = 0.f;
 
     for (int64_t bend = maxlast; bend > (int64_t)start; bend -= kBwdBatch) {
         const uint32_t b0 = (uint32_t)max((int64_t)start, bend - kBwdBatch);
@@ -123,8 +146,8 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
             s_r1[tid] = p.r1;
             s_r2[tid] = p.r2;
             s_col[tid] = a.scol[g];
-        } else if (tid >= 128 && tid - 128 < nb) {
-            const int j = tid - 128;
+        } else if (tid >= 64 && tid - 64 < nb) {
+            const int j = tid - 64;
             const uint32_t g = a.sgp[b0 + j];
             const float* sv = a.ssv + (size_t)g * k;
             for (int m = 0; m < k; m++) s_sv[j * k + m] = sv[m];
@@ -138,60 +161,59 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
 #pragma unroll
             for (int q = 0; q < NVMAX; q++) val[q] = 0.f;
             bool act = false;
-            if (s < last) {
-                const float4 q2 = s_r2[j];
-                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-                if (px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) && py >= (int)(ry & 0xffffu) &&
-                    py <= (int)(ry >> 16)) {
-                    const float4 q0 = s_r0[j], q1 = s_r1[j];
-                    float G, dx, dy;
-                    const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
-                    if (alpha >= amin) {
-                        act = true;
-                        const float om = 1.f - alpha;
-                        T = T / om;  // transmittance in front of this Gaussian
-                        const float w = alpha * T;
-                        const float4 col = s_col[j];
-                        val[6] = w * gC0;
-                        val[7] = w * gC1;
-                        val[8] = w * gC2;
-                        val[9] = w * gD;
-                        float e = col.x * gC0 + col.y * gC1 + col.z * gC2 + col.w * gD + gS;
-                        float es = 0.f;
-                        if (b.sem_in_lds) {
-                            const float* sv = s_sv + j * k;
-                            const uint32_t* si = s_si + j * kw;
+            const float4 q2 = s_r2[j];
+            const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+            const int c_lo = (int)(rx & 0xffffu), c_hi = (int)(rx >> 16);
+            const int r_lo = (int)(ry & 0xffffu), r_hi = (int)(ry >> 16);
+            const float4 q0 = s_r0[j], q1 = s_r1[j], col = s_col[j];
+            const float* sv = s_sv + j * k;
+            const uint32_t* si = s_si + j * kw;
 #pragma unroll
-                            for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
-                                if (KT == 0 && mw >= kw) break;
-                                const uint32_t word = si[mw];
+            for (int q = 0; q < 2; q++) {
+                if (s >= last[q] || px[q] < c_lo || px[q] > c_hi || py[q] < r_lo || py[q] > r_hi) continue;
+                float G, dx, dy;
+                const float alpha = eval_alpha(q0, q1, px[q], py[q], amax, &G, &dx, &dy);
+                if (alpha < amin) continue;
+                act = true;
+                const float om = 1.f - alpha;
+                T[q] = T[q] / om;  // transmittance in front of this Gaussian
+                const float w = alpha * T[q];
+                val[6] += w * gC0[q];
+                val[7] += w * gC1[q];
+                val[8] += w * gC2[q];
+                val[9] += w * gD[q];
+                float e = col.x * gC0[q] + col.y * gC1[q] + col.z * gC2[q] + col.w * gD[q] + gS[q];
+                float es = 0.f;
+                if (b.sem_in_lds) {
 #pragma unroll
-                                for (int bb = 0; bb < 4; bb++) {
-                                    const int m = mw * 4 + bb;
-                                    if (m < k) {
-                                        const float g = gp[((word >> (8 * bb)) & 0xffu) * kAccStride + tid];
-                                        val[10 + m] = w * g;
-                                        es += sv[m] * g;
-                                    }
-                                }
+                    for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
+                        if (KT == 0 && mw >= kw) break;
+                        const uint32_t word = si[mw];
+#pragma unroll
+                        for (int bb = 0; bb < 4; bb++) {
+                            const int m = mw * 4 + bb;
+                            if (m < k) {
+                                const float g = gp[((word >> (8 * bb)) & 0xffu) * kAccStride + col_slot[q]];
+                                val[10 + m] += w * g;
+                                es += sv[m] * g;
                             }
                         }
-                        if (b.semgeo) e += es;
-                        const float dalpha = T * e - R / om;
-                        R += e * w;
-                        if (q1.w * G < amax) {
-                            val[5] = dalpha * G;
-                            const float dQ = dalpha * (-0.5f * alpha);
-                            const float ca = q1.x * k2ln2;
-                            const float cb = q1.y * ca;
-                            const float cc = q1.z * k2ln2 + q1.y * cb;
-                            val[2] = dQ * dx * dx;
-                            val[3] = dQ * 2.f * dx * dy;
-                            val[4] = dQ * dy * dy;
-                            val[0] = -2.f * dQ * (ca * dx + cb * dy);
-                            val[1] = -2.f * dQ * (cb * dx + cc * dy);
-                        }
                     }
+                }
+                if (b.semgeo) e += es;
+                const float dalpha = T[q] * e - R[q] / om;
+                R[q] += e * w;
+                if (q1.w * G < amax) {
+                    val[5] += dalpha * G;
+                    const float dQ = dalpha * (-0.5f * alpha);
+                    const float ca = q1.x * k2ln2;
+                    const float cb = q1.y * ca;
+                    const float cc = q1.z * k2ln2 + q1.y * cb;
+                    val[2] += dQ * dx * dx;
+                    val[3] += dQ * 2.f * dx * dy;
+                    val[4] += dQ * dy * dy;
+                    val[0] += -2.f * dQ * (ca * dx + cb * dy);
+                    val[1] += -2.f * dQ * (cb * dx + cc * dy);
                 }
             }
             const uint64_t any = __ballot(act);
@@ -207,28 +229,31 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs b) {
             if (lane == 0) flag[wv * kBwdBatch + j] = any ? 1u : 0u;
         }
         __syncthreads();
-        for (int idx = tid; idx < nb * NV; idx += kBlock) {
+        for (int idx = tid; idx < nb * NV; idx += kBwdThreads) {
             const int j = idx / NV, q = idx - j * NV;
-            const uint32_t f0 = flag[j], f1 = flag[kBwdBatch + j], f2 = flag[2 * kBwdBatch + j],
-                           f3 = flag[3 * kBwdBatch + j];
+            const uint32_t f0 = flag[j], f1 = flag[kBwdBatch + j];
             const uint32_t e = b.svals[b0 + j];
-            const bool t = (f0 | f1 | f2 | f3) != 0u;
+            const bool t = (f0 | f1) != 0u;
             if (t) {
                 float sum = 0.f;
                 if (f0) sum += part[(0 * kBwdBatch + j) * NV + q];
                 if (f1) sum += part[(1 * kBwdBatch + j) * NV + q];
-                if (f2) sum += part[(2 * kBwdBatch + j) * NV + q];
-                if (f3) sum += part[(3 * kBwdBatch + j) * NV + q];
                 b.slots[(size_t)e * NV + q] = sum;
             }
             if (q == 0) b.touched[e] = t ? 1 : 0;
         }
         __syncthreads();
     }
-    for (uint32_t s = maxlast + tid; s < end; s += kBlock) b.touched[b.svals[s]] = 0;
+    for (uint32_t s = maxlast + tid; s < end; s += kBwdThreads) b.touched[b.svals[s]] = 0;
 }
 
-// Sum of each visible pair's key slots, in emission order.
+// Sum of each visible pair's key slots.  A pair with a short key segment is
+// summed by its own lane in emission order; long segments (a Gaussian near
+// the camera can cover thousands of tiles) are taken one at a time by the
+// whole wave: lane l sums keys l, l+64, ... and the wave reduces in a fixed
+// pattern.  Either way the result does not depend on timing.
+constexpr uint32_t kShortSeg = 16;
+
 template <int KT>
 __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ slots,
                                                     const uint8_t* __restrict__ touched,
@@ -236,15 +261,24 @@ __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ sl
                                                     const uint32_t* __restrict__ tcount,
                                                     const uint32_t* __restrict__ counters, int nv_rt,
                                                     float* __restrict__ g2d) {
-    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
-    if (g >= counters[kNumVisible]) return;
     constexpr int NVMAX = 10 + (KT > 0 ? KT : kMaxK);
     const int NV = KT > 0 ? 10 + KT : nv_rt;
-    float acc[NVMAX];
+    const uint32_t nvis = counters[kNumVisible];
+    const bool ok = !(counters[kStatus] & SGR_ECAPACITY);
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t gbase = g - (threadIdx.x & 63);
+    const int lane = threadIdx.x & 63;
+    const bool valid = g < nvis;
+    uint32_t e0 = 0, e1 = 0;
+    if (valid && ok) {
+        e0 = toff[g];
+        e1 = e0 + tcount[g];
+    }
+    const bool longseg = e1 - e0 > kShortSeg;
+    if (valid && !longseg) {
+        float acc[NVMAX];
 #pragma unroll
-    for (int q = 0; q < NVMAX; q++) acc[q] = 0.f;
-    if (!(counters[kStatus] & SGR_ECAPACITY)) {
-        const uint32_t e0 = toff[g], e1 = e0 + tcount[g];
+        for (int q = 0; q < NVMAX; q++) acc[q] = 0.f;
         for (uint32_t e = e0; e < e1; e++) {
             if (!touched[e]) continue;
             const float* sl = slots + (size_t)e * NV;
@@ -252,10 +286,33 @@ __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ sl
             for (int q = 0; q < NVMAX; q++)
                 if (q < NV) acc[q] += sl[q];
         }
-    }
 #pragma unroll
-    for (int q = 0; q < NVMAX; q++)
-        if (q < NV) g2d[(size_t)g * NV + q] = acc[q];
+        for (int q = 0; q < NVMAX; q++)
+            if (q < NV) g2d[(size_t)g * NV + q] = acc[q];
+    }
+    uint64_t lm = __ballot(valid && longseg);
+    while (lm) {
+        const int src = __ffsll((long long)lm) - 1;
+        lm &= lm - 1;
+        const uint32_t s0 = __shfl(e0, src, 64), s1 = __shfl(e1, src, 64);
+        float acc[NVMAX];
+#pragma unroll
+        for (int q = 0; q < NVMAX; q++) acc[q] = 0.f;
+        for (uint32_t e = s0 + lane; e < s1; e += 64) {
+            if (!touched[e]) continue;
+            const float* sl = slots + (size_t)e * NV;
+#pragma unroll
+            for (int q = 0; q < NVMAX; q++)
+                if (q < NV) acc[q] += sl[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NVMAX; q++) {
+            if (q < NV) {
+                const float sum = wave_sum_lane63(acc[q]);
+                if (lane == 63) g2d[(size_t)(gbase + src) * NV + q] = sum;
+            }
+        }
+    }
 }
 
 struct ProjBwdArgs {
@@ -389,7 +446,7 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
 
 static size_t bwd_lds_bytes(int C, int k, int kpad, bool sem_lds) {
     size_t b = (size_t)kBwdBatch * (4 * sizeof(float4) + k * sizeof(float) + kpad);
-    b += (size_t)4 * kBwdBatch * (10 + k) * sizeof(float) + 4 * kBwdBatch * sizeof(uint32_t);
+    b += (size_t)kBwdWaves * kBwdBatch * (10 + k) * sizeof(float) + kBwdWaves * kBwdBatch * sizeof(uint32_t);
     if (sem_lds) b += (size_t)acc_floats(C) * sizeof(float);
     return b;
 }
@@ -420,13 +477,13 @@ sgr_status launch_backward(const Plan& P, const sgr_gaussians* g, const sgr_map_
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
     if (P.k == 16) {
         set_lds_b(render_bwd_kernel<16>, lds);
-        render_bwd_kernel<16><<<grid, kBlock, lds, st>>>(b);
+        render_bwd_kernel<16><<<grid, kBwdThreads, lds, st>>>(b);
     } else if (P.k == 3) {
         set_lds_b(render_bwd_kernel<3>, lds);
-        render_bwd_kernel<3><<<grid, kBlock, lds, st>>>(b);
+        render_bwd_kernel<3><<<grid, kBwdThreads, lds, st>>>(b);
     } else {
         set_lds_b(render_bwd_kernel<0>, lds);
-        render_bwd_kernel<0><<<grid, kBlock, lds, st>>>(b);
+        render_bwd_kernel<0><<<grid, kBwdThreads, lds, st>>>(b);
     }
     const uint32_t* counters = (const uint32_t*)(ws + P.counters);
     const unsigned ggrid = (unsigned)div_up(P.vn, 256);

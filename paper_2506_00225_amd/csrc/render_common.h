@@ -56,6 +56,16 @@ struct ScoreOut {
     double* entropy_sum;
 };
 
+// Pixel layout of a 16x16 tile over 256 threads: wave w covers the 8x8
+// quadrant (w & 1, w >> 1), lane l the pixel (l & 7, l >> 3) inside it, so a
+// small Gaussian touches few waves.  slot_of gives the thread (and LDS
+// column) that owns tile pixel (lx, ly).
+__host__ __device__ inline int tile_px(int t) { return ((t >> 6) & 1) * 8 + (t & 7); }
+__host__ __device__ inline int tile_py(int t) { return ((t >> 7) & 1) * 8 + ((t >> 3) & 7); }
+__host__ __device__ inline int slot_of(int lx, int ly) {
+    return (((ly >> 3) << 1) | (lx >> 3)) * 64 + ((ly & 7) << 3) + (lx & 7);
+}
+
 __device__ inline int view_of_tile(const ViewDev* views, int V, int gt) {
     int lo = 0, hi = V - 1;
     while (lo < hi) {
@@ -75,7 +85,7 @@ __device__ __forceinline__ float eval_alpha(const float4& q0, const float4& q1, 
     const float ddy = (float)(py - __float_as_int(q0.y)) + (0.5f - q0.w);
     const float u = fmaf(q1.y, ddy, ddx);
     const float e = fmaf(q1.x * u, u, q1.z * ddy * ddy);
-    const float g = exp2f(-e);
+    const float g = __builtin_amdgcn_exp2f(-e);  // v_exp_f32; e >= 0 here
     *G = g;
     *dx = ddx;
     *dy = ddy;

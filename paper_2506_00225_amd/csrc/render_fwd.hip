@@ -29,7 +29,7 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     const ViewDev& vw = a.views[v];
     const int local = gt - vw.tile_off;
     const int tx = local % vw.tiles_x, ty = local / vw.tiles_x;
-    const int px = tx * kTile + (tid & (kTile - 1)), py = ty * kTile + (tid >> 4);
+    const int px = tx * kTile + tile_px(tid), py = ty * kTile + tile_py(tid);
     const bool inside = px < vw.width && py < vw.height;
     const uint2 rg = a.ranges[gt];
     const uint32_t start = rg.x, end = rg.y;
@@ -97,17 +97,42 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                 if (SEM != 0) {
                     const float* sv = s_sv + j * k;
                     const uint32_t* si = s_si + j * kw;
+                    const bool dup = (__float_as_uint(q2.w) >> 31) != 0u;
+                    if (KT > 0 && SEM == 1 && !dup) {
+                        // distinct classes: all reads, then all updates
+                        constexpr int KK = KT > 0 ? KT : 1;
+                        float vals[KK];
+                        uint32_t cls[KK];
+                        if constexpr (KT > 0 && (KT & 3) == 0) {
 #pragma unroll
-                    for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
-                        if (KT == 0 && mw >= kw) break;
-                        const uint32_t word = si[mw];
+                            for (int m = 0; m < KK; m += 4) {
+                                const float4 v4 = *(const float4*)(sv + m);
+                                vals[m] = v4.x; vals[m + 1] = v4.y; vals[m + 2] = v4.z; vals[m + 3] = v4.w;
+                            }
+                        } else {
 #pragma unroll
-                        for (int b = 0; b < 4; b++) {
-                            const int m = mw * 4 + b;
-                            if (m < k) {
-                                const uint32_t cls = (word >> (8 * b)) & 0xffu;
-                                if (SEM == 1) acc[cls * kAccStride + tid] += sv[m] * w;
-                                else if (gacc) gacc[cls] += sv[m] * w;
+                            for (int m = 0; m < KK; m++) vals[m] = sv[m];
+                        }
+#pragma unroll
+                        for (int m = 0; m < KK; m++) cls[m] = ((si[m >> 2] >> (8 * (m & 3))) & 0xffu) * kAccStride + tid;
+                        float cur[KK];
+#pragma unroll
+                        for (int m = 0; m < KK; m++) cur[m] = acc[cls[m]];
+#pragma unroll
+                        for (int m = 0; m < KK; m++) acc[cls[m]] = fmaf(vals[m], w, cur[m]);
+                    } else {
+#pragma unroll
+                        for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
+                            if (KT == 0 && mw >= kw) break;
+                            const uint32_t word = si[mw];
+#pragma unroll
+                            for (int b = 0; b < 4; b++) {
+                                const int m = mw * 4 + b;
+                                if (m < k) {
+                                    const uint32_t cl = (word >> (8 * b)) & 0xffu;
+                                    if (SEM == 1) acc[cl * kAccStride + tid] += sv[m] * w;
+                                    else if (gacc) gacc[cl] += sv[m] * w;
+                                }
                             }
                         }
                     }
@@ -165,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
             float* dst = out + ((int64_t)(y0 + row) * vw.width + x0) * C;
             int lx = threadIdx.x / C, c = threadIdx.x % C;
             for (int e = threadIdx.x; e < row_elems; e += kBlock) {
-                if (lx < wcols) dst[e] = smem[c * kAccStride + row * kTile + lx];
+                if (lx < wcols) dst[e] = smem[c * kAccStride + slot_of(lx, row)];
                 lx += dl;
                 c += dc;
                 if (c >= C) { c -= C; lx++; }
