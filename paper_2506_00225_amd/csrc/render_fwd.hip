@@ -72,13 +72,21 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
         }
         __syncthreads();
         if (!done) {
+            // The next Gaussian's record is loaded before this one's
+            // accumulator updates are issued (records never alias the
+            // accumulators), hiding one LDS round trip per Gaussian.
+            float4 n0 = s_r0[0], n1 = s_r1[0], n2 = s_r2[0];
             for (int j = 0; j < nb; j++) {
-                const float4 q2 = s_r2[j];
+                const float4 q0 = n0, q1 = n1, q2 = n2;
+                if (j + 1 < nb) {
+                    n0 = s_r0[j + 1];
+                    n1 = s_r1[j + 1];
+                    n2 = s_r2[j + 1];
+                }
                 const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
                 if (px < (int)(rx & 0xffffu) || px > (int)(rx >> 16) || py < (int)(ry & 0xffffu) ||
                     py > (int)(ry >> 16))
                     continue;
-                const float4 q0 = s_r0[j], q1 = s_r1[j];
                 float G, dx, dy;
                 const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
                 if (alpha < amin) continue;
