@@ -67,7 +67,7 @@ class Timer:
 
 
 def mapping_bench(args, torch, out):
-    from paper_2506_00225_amd import Frame, Gaussians, make_config, scenes
+    from paper_2506_00225_amd import Frame, FusedAdam, Gaussians, make_config, mapping_loss_grad, scenes
 
     log("generating room scene", args.n)
     sc = scenes.room_scene(n=args.n)
@@ -85,28 +85,22 @@ def mapping_bench(args, torch, out):
     dev = g.means.device
     t_rgb = torch.from_numpy(sc.targets["rgb"]).to(dev).reshape(P, 3)
     t_depth = torch.from_numpy(sc.targets["depth"]).to(dev).reshape(P)
-    label = torch.from_numpy(sc.targets["label"]).to(dev).reshape(P).long()
+    label = torch.from_numpy(sc.targets["label"]).to(dev).reshape(P).int().contiguous()
     maps = fr.alloc_maps()
     grads_in = {"rgb": torch.empty(P, 3, device=dev), "depth": torch.empty(P, device=dev),
-                "sil": torch.empty(P, device=dev), "sem": torch.zeros(P, C, device=dev)}
+                "sil": torch.empty(P, device=dev), "sem": torch.empty(P, C, device=dev)}
+    scratch = torch.empty(P, device=dev)
     gout = {nm: torch.empty_like(getattr(g, nm)) for nm in ("means", "scales", "quats", "opacity", "rgb", "sem_val")}
-    opt = torch.optim.Adam(params, lr=1e-3, betas=(0.9, 0.999), foreach=True)
-    for p_, nm in zip(params, ("means", "scales", "quats", "opacity", "rgb", "sem_val")):
-        p_.grad = gout[nm]
+    inf = float("inf")
+    opt = FusedAdam([(g.means, gout["means"], -inf, inf), (g.scales, gout["scales"], -inf, inf),
+                     (g.quats, gout["quats"], -inf, inf), (g.opacity, gout["opacity"], 1e-4, 0.9999),
+                     (g.rgb, gout["rgb"], -inf, inf), (g.sem_val, gout["sem_val"], 0.0, inf)],
+                    lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
     blends = torch.zeros(args.steps + args.warmup, dtype=torch.int64, device=dev)
-    rows = torch.arange(P, device=dev)
 
     def loss_grad():
-        # L = mean_p [ m (|D - D*| + 0.5 sum_c |C - C*|) + |S - 1| - ln max(P_label, 1e-6) ],  m = [S > 0.99]
-        s = maps["sil"]
-        m = (s > 0.99).float() / P
-        torch.mul(torch.sign(maps["depth"] - t_depth), m, out=grads_in["depth"])
-        torch.mul(torch.sign(maps["rgb"] - t_rgb), (0.5 * m).unsqueeze(1), out=grads_in["rgb"])
-        grads_in["sil"].fill_(-1.0 / P)
-        pl = maps["sem"][rows, label]
-        gsem = grads_in["sem"]
-        gsem.zero_()
-        gsem[rows, label] = torch.where(pl > 1e-6, -1.0 / (P * pl.clamp_min(1e-6)), torch.zeros_like(pl))
+        # mapping loss (Sec. 3.1 silhouette-masked depth + 0.5 colour L1) + L1(S, 1) + cross-entropy
+        mapping_loss_grad(maps, t_rgb, t_depth, label, C, out=grads_in, scratch=scratch)
 
     names = ["s0", "proj", "bin", "fwd", "loss", "bwd", "adam"]
     tm = Timer(torch, names)
@@ -126,9 +120,6 @@ def mapping_bench(args, torch, out):
         fr.backward(g, grads_in, gout)
         mk("bwd")
         opt.step()
-        with torch.no_grad():
-            g.opacity.clamp_(1e-4, 0.9999)
-            g.sem_val.clamp_(min=0.0)
         mk("adam")
 
     log("warmup", args.warmup)

@@ -213,6 +213,48 @@ sgr_status sgr_score_maps(const float *sem, const int32_t *n_contrib, int32_t wi
                           int32_t num_classes, uint32_t *n_empty, double *entropy_sum, void *workspace,
                           size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Mapping-iteration helpers (used by a mapping step around the rasterizer).
+ * ------------------------------------------------------------------------ */
+
+/*
+ * sgr_mapping_loss_grad -- gradient with respect to the rendered maps of
+ *   L = (1/P) sum_p [ m(p) (w0 |D - D*| + w1 sum_ch |C - C*|) + w2 |S - 1|
+ *                     - w3 ln max(P_label(p), 1e-6) ],   m(p) = [S(p) > w4],
+ * the silhouette-masked depth + colour L1 of Sec. 3.1 (w0 = 1, w1 = 0.5,
+ * w4 = 0.99) plus silhouette and cross-entropy terms.  The mask is not
+ * differentiated.  weights is a HOST array {w0, w1, w2, w3, w4}.  Maps and
+ * targets are device arrays of num_pixels pixels (rgb [P][3], sem [P][C],
+ * label int32 [P] with values < num_classes); outputs are overwritten,
+ * g_sem densely.  scratch is a device float array of num_pixels.
+ */
+sgr_status sgr_mapping_loss_grad(const float *rgb, const float *depth, const float *sil, const float *sem,
+                                 const float *t_rgb, const float *t_depth, const int32_t *label, int64_t num_pixels,
+                                 int32_t num_classes, const float *weights, float *g_rgb, float *g_depth, float *g_sil,
+                                 float *g_sem, float *scratch, void *stream);
+
+/* One Adam segment: parameters p, gradient g, moments m and v (device, n
+ * floats each); after the update p is clamped to [lo, hi]. */
+typedef struct {
+    float *p;
+    const float *g;
+    float *m, *v;
+    int64_t n;
+    float lo, hi;
+} sgr_adam_segment;
+
+#define SGR_MAX_ADAM_SEGMENTS 8
+
+/*
+ * sgr_adam_step -- one fused Adam update (bias-corrected, step >= 1) of up
+ * to SGR_MAX_ADAM_SEGMENTS segments in a single launch:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p = clamp(p - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), lo, hi).
+ * `segments` is a HOST array.
+ */
+sgr_status sgr_adam_step(const sgr_adam_segment *segments, int32_t num_segments, float lr, float beta1, float beta2,
+                         float eps, int32_t step, void *stream);
+
 /* Synchronises `stream` and reads the status word, the visible-pair count
  * and the key count of the workspace (host outputs; any may be NULL). */
 sgr_status sgr_read_status(const void *workspace, void *stream, int64_t *num_visible, int64_t *num_keys);

@@ -8,6 +8,8 @@ marshals arguments and takes device memory and streams from PyTorch.
 """
 from . import _lib
 from ._lib import SgrError
-from .rasterizer import Frame, Gaussians, camera_array, make_config, render, score_maps
+from .rasterizer import (FusedAdam, Frame, Gaussians, camera_array, make_config, mapping_loss_grad, render,
+                         score_maps)
 
-__all__ = ["Frame", "Gaussians", "SgrError", "camera_array", "make_config", "render", "score_maps", "_lib"]
+__all__ = ["FusedAdam", "Frame", "Gaussians", "SgrError", "camera_array", "make_config", "mapping_loss_grad", "render",
+           "score_maps", "_lib"]

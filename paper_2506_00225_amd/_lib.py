@@ -48,6 +48,14 @@ class sgr_grads(ctypes.Structure):
     _fields_ = [("means", P), ("scales", P), ("quats", P), ("opacity", P), ("rgb", P), ("sem_val", P)]
 
 
+class sgr_adam_segment(ctypes.Structure):
+    _fields_ = [("p", P), ("g", P), ("m", P), ("v", P), ("n", ctypes.c_int64), ("lo", ctypes.c_float),
+                ("hi", ctypes.c_float)]
+
+
+SGR_MAX_ADAM_SEGMENTS = 8
+
+
 class sgr_layout(ctypes.Structure):
     _fields_ = [(name, ctypes.c_size_t) for name in (
         "total_bytes", "counters", "views", "proj_count", "proj_zbits", "proj_rec", "order", "sorted_keys",
@@ -58,7 +66,7 @@ class sgr_layout(ctypes.Structure):
 EXPORTS = (
     "sgr_workspace_size", "sgr_workspace_layout", "sgr_project", "sgr_bin", "sgr_render_forward",
     "sgr_render_backward", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
-    "sgr_read_status", "sgr_status_string",
+    "sgr_read_status", "sgr_status_string", "sgr_mapping_loss_grad", "sgr_adam_step",
 )
 
 _lib = None
@@ -97,6 +105,11 @@ def lib():
     L.sgr_score_maps.restype = i32
     L.sgr_read_status.argtypes = [P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.sgr_read_status.restype = i32
+    L.sgr_mapping_loss_grad.argtypes = [P] * 7 + [i64, i32, P] + [P] * 5 + [P]
+    L.sgr_mapping_loss_grad.restype = i32
+    L.sgr_adam_step.argtypes = [ctypes.POINTER(sgr_adam_segment), i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, i32, P]
+    L.sgr_adam_step.restype = i32
     L.sgr_status_string.argtypes = [i32]
     L.sgr_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -171,3 +184,14 @@ def sgr_read_status(workspace, stream):
 
 def sgr_status_string(status):
     return lib().sgr_status_string(int(status)).decode()
+
+
+def sgr_mapping_loss_grad(rgb, depth, sil, sem, t_rgb, t_depth, label, num_pixels, num_classes, weights, g_rgb,
+                          g_depth, g_sil, g_sem, scratch, stream):
+    w = (ctypes.c_float * 5)(*[float(x) for x in weights])
+    return lib().sgr_mapping_loss_grad(rgb, depth, sil, sem, t_rgb, t_depth, label, num_pixels, num_classes, w, g_rgb,
+                                       g_depth, g_sil, g_sem, scratch, stream)
+
+
+def sgr_adam_step(segments, num_segments, lr, beta1, beta2, eps, step, stream):
+    return lib().sgr_adam_step(segments, num_segments, lr, beta1, beta2, eps, step, stream)

@@ -9,7 +9,8 @@
 
 namespace sgr {
 
-constexpr int kViewChunk = 16;  // cameras per upload launch (kernel-argument payload)
+constexpr int kViewChunk = 16;
+constexpr int kMaxAdamSegs = SGR_MAX_ADAM_SEGMENTS;  // cameras per upload launch (kernel-argument payload)
 
 // Workspace layout of one frame: a pure function of the call arguments.
 struct Plan {

@@ -254,3 +254,48 @@ def render(g: Gaussians, frame: Frame, check: bool = True):
     rgb, depth, sil, sem, t_final, n_contrib = _Render.apply(frame, g.sem_idx, check, g.means, g.scales, g.quats,
                                                              g.opacity, g.rgb, g.sem_val)
     return {"rgb": rgb, "depth": depth, "sil": sil, "sem": sem, "t_final": t_final, "n_contrib": n_contrib}
+
+
+MAPPING_LOSS_WEIGHTS = (1.0, 0.5, 1.0, 1.0, 0.99)  # depth, colour, silhouette, cross-entropy, mask threshold
+
+
+def mapping_loss_grad(maps: dict, t_rgb, t_depth, label, num_classes: int, out: dict | None = None,
+                      scratch=None, weights=MAPPING_LOSS_WEIGHTS):
+    """dL/d(maps) of the mapping loss (see sgr_mapping_loss_grad); all flat
+    [P, ...] tensors on one device."""
+    P = int(maps["depth"].shape[0])
+    dev = maps["depth"].device
+    if out is None:
+        out = {"rgb": torch.empty(P, 3, device=dev), "depth": torch.empty(P, device=dev),
+               "sil": torch.empty(P, device=dev), "sem": torch.empty(P, num_classes, device=dev)}
+    if scratch is None:
+        scratch = torch.empty(P, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    L.check(L.sgr_mapping_loss_grad(_ptr(maps["rgb"]), _ptr(maps["depth"]), _ptr(maps["sil"]), _ptr(maps["sem"]),
+                                    _ptr(t_rgb), _ptr(t_depth), _ptr(label), P, int(num_classes), weights,
+                                    _ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["sil"]), _ptr(out["sem"]),
+                                    _ptr(scratch), stream), "sgr_mapping_loss_grad")
+    return out
+
+
+class FusedAdam:
+    """Adam over a list of (param, grad, lo, hi) float32 tensors in one launch
+    per step (sgr_adam_step), with the clamp applied after each update."""
+
+    def __init__(self, groups, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+        if len(groups) > L.SGR_MAX_ADAM_SEGMENTS:
+            raise ValueError("too many parameter tensors for one fused Adam launch")
+        self.groups = groups
+        self.lr, self.b1, self.b2, self.eps = lr, betas[0], betas[1], eps
+        self.m = [torch.zeros_like(p) for p, _, _, _ in groups]
+        self.v = [torch.zeros_like(p) for p, _, _, _ in groups]
+        self.t = 0
+        self.segs = (L.sgr_adam_segment * len(groups))()
+        for i, ((p, g, lo, hi), m, v) in enumerate(zip(groups, self.m, self.v)):
+            self.segs[i] = L.sgr_adam_segment(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), float(lo), float(hi))
+
+    def step(self):
+        self.t += 1
+        stream = ctypes.c_void_p(torch.cuda.current_stream(self.m[0].device).cuda_stream)
+        L.check(L.sgr_adam_step(self.segs, len(self.groups), self.lr, self.b1, self.b2, self.eps, self.t, stream),
+                "sgr_adam_step")
