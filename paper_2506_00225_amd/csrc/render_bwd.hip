@@ -218,11 +218,20 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
             }
             const uint64_t any = __ballot(act);
             if (any) {
+                if ((any & (any - 1)) == 0) {
+                    // one active lane: its values are the wave's sums
+                    if (act) {
 #pragma unroll
-                for (int q = 0; q < NVMAX; q++) {
-                    if (q < NV) {
-                        const float sum = wave_sum_lane63(val[q]);
-                        if (lane == 63) part[(wv * kBwdBatch + j) * NV + q] = sum;
+                        for (int q = 0; q < NVMAX; q++)
+                            if (q < NV) part[(wv * kBwdBatch + j) * NV + q] = val[q];
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NVMAX; q++) {
+                        if (q < NV) {
+                            const float sum = wave_sum_lane63(val[q]);
+                            if (lane == 63) part[(wv * kBwdBatch + j) * NV + q] = sum;
+                        }
                     }
                 }
             }
