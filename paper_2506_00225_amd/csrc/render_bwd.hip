@@ -36,16 +36,72 @@ struct BwdArgs {
     int sem_in_lds;
 };
 
-constexpr int kBwdThreads = 128;  // 2 waves; each lane owns 2 pixels of the 16x16 tile
+constexpr int kBwdThreads = 256;  // 4 waves, one pixel per lane, 8x8 pixel block per wave
 constexpr int kBwdWaves = kBwdThreads / 64;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_perm(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+// Transposed wave reduction of NP (16 or 32) values per lane.  Each step
+// halves the number of registers while doubling the lanes each partial sum
+// covers: permlane32 and permlane16 swaps pair lanes 32 and 16 apart, then
+// row rotate-by-8, half-row mirror and quad permutes pair lanes 8, 4 and 2
+// apart, the lane's own bit choosing which value it keeps.  About 70
+// instructions for 32 values instead of 6 DPP steps per value.  On return
+// every lane holds the full 64-lane sum of value
+//   NP = 32: 16 b1 + 8 b2 + 4 b3 + 2 b4 + b5,   NP = 16: 8 b2 + 4 b3 + 2 b4 + b5
+// (b_i = bit i of the lane id); see transposed_value_index.
+template <int NP>
+__device__ __forceinline__ float wave_transpose_sum(float (&v)[NP], int lane) {
+    static_assert(NP == 16 || NP == 32, "16 or 32 values");
+    float r1[NP / 2];
+#pragma unroll
+    for (int i = 0; i < NP / 2; i++) {
+        const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]), __float_as_uint(v[2 * i + 1]),
+                                                       false, false);
+        r1[i] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    }
+    float r2[NP / 4];
+#pragma unroll
+    for (int i = 0; i < NP / 4; i++) {
+        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(r1[2 * i]), __float_as_uint(r1[2 * i + 1]),
+                                                       false, false);
+        r2[i] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    }
+    const bool h8 = lane & 8, h4 = lane & 4, h2 = lane & 2;
+    float r3[NP / 8];
+#pragma unroll
+    for (int i = 0; i < NP / 8; i++) {
+        const float keep = h8 ? r2[2 * i + 1] : r2[2 * i], send = h8 ? r2[2 * i] : r2[2 * i + 1];
+        r3[i] = keep + dpp_perm<0x128>(send);  // row_ror:8 (lane ^ 8 within a row)
+    }
+    float r4[NP / 16];
+#pragma unroll
+    for (int i = 0; i < NP / 16; i++) {
+        const float keep = h4 ? r3[2 * i + 1] : r3[2 * i], send = h4 ? r3[2 * i] : r3[2 * i + 1];
+        r4[i] = keep + dpp_perm<0x141>(send);  // row_half_mirror
+    }
+    float x;
+    if constexpr (NP == 32) {
+        const float keep = h2 ? r4[1] : r4[0], send = h2 ? r4[0] : r4[1];
+        x = keep + dpp_perm<0x4e>(send);  // quad_perm [2,3,0,1]
+    } else {
+        x = r4[0] + dpp_perm<0x4e>(r4[0]);
+    }
+    return x + dpp_perm<0xb1>(x);  // quad_perm [1,0,3,2]
+}
+
+template <int NP>
+__device__ __forceinline__ int transposed_value_index(int lane) {
+    const int b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1, b4 = (lane >> 4) & 1,
+              b5 = (lane >> 5) & 1;
+    return NP == 32 ? 16 * b1 + 8 * b2 + 4 * b3 + 2 * b4 + b5 : 8 * b2 + 4 * b3 + 2 * b4 + b5;
+}
 
 // Per-key value layout: 0,1 mean2d; 2,3,4 conic (a, b, c); 5 opacity;
 // 6,7,8 rgb; 9 depth; 10.. semantic values.
-//
-// Wave w covers tile rows 8w..8w+7; lane l owns pixels (l & 15, 8w + (l >> 4))
-// and the one four rows below.  Per Gaussian the two pixels' terms are added
-// in registers and the wave reduces once, so a tile pays two wave reductions
-// per Gaussian instead of four.
 template <int KT>
 __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     extern __shared__ __align__(16) float smem[];
@@ -58,9 +114,12 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
     const int C = a.C;
     constexpr int NVMAX = 10 + (KT > 0 ? KT : kMaxK);
+    // padded value count of the transposed reduction (0: per-value DPP sums)
+    constexpr int NP = (KT > 0 && NVMAX <= 16) ? 16 : ((KT > 0 && NVMAX <= 32) ? 32 : 0);
+    constexpr int NREG = NP > 0 ? NP : NVMAX;
     const int NV = 10 + k;
 
-    float* gp = smem;  // [C][257] dL/dsem of the tile's pixels, column = ly * 16 + lx
+    float* gp = smem;  // [C][257] dL/dsem of the tile's pixels, column = owning thread
     float* base = smem + (b.sem_in_lds ? acc_floats(C) : 0);
     float4* s_r0 = (float4*)base;
     float4* s_r1 = s_r0 + kBwdBatch;
@@ -76,34 +135,22 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     const ViewDev& vw = a.views[v];
     const int local = gt - vw.tile_off;
     const int tx = local % vw.tiles_x, ty = local / vw.tiles_x;
-    const int lx = lane & 15;
-    const int ly0 = 8 * wv + (lane >> 4);
+    const int px = tx * kTile + tile_px(tid), py = ty * kTile + tile_py(tid);
+    const bool inside = px < vw.width && py < vw.height;
     const uint2 rg = a.ranges[gt];
     const uint32_t start = rg.x, end = rg.y;
     const GradPtrs gr = b.grads[v];
+    const int64_t pix = (int64_t)py * vw.width + px;
 
-    int px[2], py[2], col_slot[2];
-    bool inside[2];
-    float T[2], gC0[2], gC1[2], gC2[2], gD[2], gS[2], R[2];
-    uint32_t last[2];
-#pragma unroll
-    for (int q = 0; q < 2; q++) {
-        const int ly = ly0 + 4 * q;
-        px[q] = tx * kTile + lx;
-        py[q] = ty * kTile + ly;
-        col_slot[q] = ly * kTile + lx;
-        inside[q] = px[q] < vw.width && py[q] < vw.height;
-        T[q] = 1.f;
-        last[q] = start;
-        gC0[q] = gC1[q] = gC2[q] = gD[q] = gS[q] = R[q] = 0.f;
-        if (inside[q]) {
-            const int64_t pix = (int64_t)py[q] * vw.width + px[q];
-            T[q] = a.pix_T[vw.pix_off + pix];
-            last[q] = a.pix_last[vw.pix_off + pix];
-            if (gr.rgb) { gC0[q] = gr.rgb[3 * pix]; gC1[q] = gr.rgb[3 * pix + 1]; gC2[q] = gr.rgb[3 * pix + 2]; }
-            if (gr.depth) gD[q] = gr.depth[pix];
-            if (gr.sil) gS[q] = gr.sil[pix];
-        }
+    float T = 1.f;
+    uint32_t last = start;
+    float gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gS = 0.f;
+    if (inside) {
+        T = a.pix_T[vw.pix_off + pix];
+        last = a.pix_last[vw.pix_off + pix];
+        if (gr.rgb) { gC0 = gr.rgb[3 * pix]; gC1 = gr.rgb[3 * pix + 1]; gC2 = gr.rgb[3 * pix + 2]; }
+        if (gr.depth) gD = gr.depth[pix];
+        if (gr.sil) gS = gr.sil[pix];
     }
     if (tid == 0) s_maxlast = start;
     if (b.sem_in_lds) {
@@ -117,7 +164,7 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
             for (int e = tid; e < row_elems; e += kBwdThreads) {
                 float val = 0.f;
                 if (src && row < hrows && cx < wcols) val = src[e];
-                gp[c * kAccStride + row * kTile + cx] = val;
+                gp[c * kAccStride + slot_of(cx, row)] = val;
                 cx += dl;
                 c += dc;
                 if (c >= C) { c -= C; cx++; }
@@ -125,16 +172,12 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         }
     }
     __syncthreads();
-    {
-        uint32_t m = start;
-        if (inside[0] && last[0] > m) m = last[0];
-        if (inside[1] && last[1] > m) m = last[1];
-        if (m > start) atomicMax(&s_maxlast, m);
-    }
+    if (inside && last > start) atomicMax(&s_maxlast, last);
     __syncthreads();
     const uint32_t maxlast = __builtin_amdgcn_readfirstlane(s_maxlast);
     const float amin = a.alpha_min, amax = a.alpha_max;
     const float k2ln2 = 1.38629436111989061883f;  // 2 ln 2
+    float R = 0.f;
 
     for (int64_t bend = maxlast; bend > (int64_t)start; bend -= kBwdBatch) {
         const uint32_t b0 = (uint32_t)max((int64_t)start, bend - kBwdBatch);
@@ -146,8 +189,8 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
             s_r1[tid] = p.r1;
             s_r2[tid] = p.r2;
             s_col[tid] = a.scol[g];
-        } else if (tid >= 64 && tid - 64 < nb) {
-            const int j = tid - 64;
+        } else if (tid >= 128 && tid - 128 < nb) {
+            const int j = tid - 128;
             const uint32_t g = a.sgp[b0 + j];
             const float* sv = a.ssv + (size_t)g * k;
             for (int m = 0; m < k; m++) s_sv[j * k + m] = sv[m];
@@ -157,80 +200,86 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         __syncthreads();
         for (int j = nb - 1; j >= 0; j--) {
             const uint32_t s = b0 + j;
-            float val[NVMAX];
+            float val[NREG];
 #pragma unroll
-            for (int q = 0; q < NVMAX; q++) val[q] = 0.f;
+            for (int q = 0; q < NREG; q++) val[q] = 0.f;
             bool act = false;
-            const float4 q2 = s_r2[j];
-            const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-            const int c_lo = (int)(rx & 0xffffu), c_hi = (int)(rx >> 16);
-            const int r_lo = (int)(ry & 0xffffu), r_hi = (int)(ry >> 16);
-            const float4 q0 = s_r0[j], q1 = s_r1[j], col = s_col[j];
-            const float* sv = s_sv + j * k;
-            const uint32_t* si = s_si + j * kw;
+            if (s < last) {
+                const float4 q2 = s_r2[j];
+                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+                if (px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) && py >= (int)(ry & 0xffffu) &&
+                    py <= (int)(ry >> 16)) {
+                    const float4 q0 = s_r0[j], q1 = s_r1[j];
+                    float G, dx, dy;
+                    const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
+                    if (alpha >= amin) {
+                        act = true;
+                        const float om = 1.f - alpha;
+                        T = T / om;  // transmittance in front of this Gaussian
+                        const float w = alpha * T;
+                        const float4 col = s_col[j];
+                        val[6] = w * gC0;
+                        val[7] = w * gC1;
+                        val[8] = w * gC2;
+                        val[9] = w * gD;
+                        float e = col.x * gC0 + col.y * gC1 + col.z * gC2 + col.w * gD + gS;
+                        float es = 0.f;
+                        if (b.sem_in_lds) {
+                            const float* sv = s_sv + j * k;
+                            const uint32_t* si = s_si + j * kw;
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                if (s >= last[q] || px[q] < c_lo || px[q] > c_hi || py[q] < r_lo || py[q] > r_hi) continue;
-                float G, dx, dy;
-                const float alpha = eval_alpha(q0, q1, px[q], py[q], amax, &G, &dx, &dy);
-                if (alpha < amin) continue;
-                act = true;
-                const float om = 1.f - alpha;
-                T[q] = T[q] / om;  // transmittance in front of this Gaussian
-                const float w = alpha * T[q];
-                val[6] += w * gC0[q];
-                val[7] += w * gC1[q];
-                val[8] += w * gC2[q];
-                val[9] += w * gD[q];
-                float e = col.x * gC0[q] + col.y * gC1[q] + col.z * gC2[q] + col.w * gD[q] + gS[q];
-                float es = 0.f;
-                if (b.sem_in_lds) {
+                            for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
+                                if (KT == 0 && mw >= kw) break;
+                                const uint32_t word = si[mw];
 #pragma unroll
-                    for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
-                        if (KT == 0 && mw >= kw) break;
-                        const uint32_t word = si[mw];
-#pragma unroll
-                        for (int bb = 0; bb < 4; bb++) {
-                            const int m = mw * 4 + bb;
-                            if (m < k) {
-                                const float g = gp[((word >> (8 * bb)) & 0xffu) * kAccStride + col_slot[q]];
-                                val[10 + m] += w * g;
-                                es += sv[m] * g;
+                                for (int bb = 0; bb < 4; bb++) {
+                                    const int m = mw * 4 + bb;
+                                    if (m < k) {
+                                        const float g = gp[((word >> (8 * bb)) & 0xffu) * kAccStride + tid];
+                                        val[10 + m] = w * g;
+                                        es += sv[m] * g;
+                                    }
+                                }
                             }
+                        }
+                        if (b.semgeo) e += es;
+                        const float dalpha = T * e - R / om;
+                        R += e * w;
+                        if (q1.w * G < amax) {
+                            val[5] = dalpha * G;
+                            const float dQ = dalpha * (-0.5f * alpha);
+                            const float ca = q1.x * k2ln2;
+                            const float cb = q1.y * ca;
+                            const float cc = q1.z * k2ln2 + q1.y * cb;
+                            val[2] = dQ * dx * dx;
+                            val[3] = dQ * 2.f * dx * dy;
+                            val[4] = dQ * dy * dy;
+                            val[0] = -2.f * dQ * (ca * dx + cb * dy);
+                            val[1] = -2.f * dQ * (cb * dx + cc * dy);
                         }
                     }
                 }
-                if (b.semgeo) e += es;
-                const float dalpha = T[q] * e - R[q] / om;
-                R[q] += e * w;
-                if (q1.w * G < amax) {
-                    val[5] += dalpha * G;
-                    const float dQ = dalpha * (-0.5f * alpha);
-                    const float ca = q1.x * k2ln2;
-                    const float cb = q1.y * ca;
-                    const float cc = q1.z * k2ln2 + q1.y * cb;
-                    val[2] += dQ * dx * dx;
-                    val[3] += dQ * 2.f * dx * dy;
-                    val[4] += dQ * dy * dy;
-                    val[0] += -2.f * dQ * (ca * dx + cb * dy);
-                    val[1] += -2.f * dQ * (cb * dx + cc * dy);
-                }
             }
             const uint64_t any = __ballot(act);
+            float* dst = part + (wv * kBwdBatch + j) * NV;
             if (any) {
                 if ((any & (any - 1)) == 0) {
                     // one active lane: its values are the wave's sums
                     if (act) {
 #pragma unroll
-                        for (int q = 0; q < NVMAX; q++)
-                            if (q < NV) part[(wv * kBwdBatch + j) * NV + q] = val[q];
+                        for (int q = 0; q < NREG; q++)
+                            if (q < NV) dst[q] = val[q];
                     }
+                } else if constexpr (NP > 0) {
+                    const float sum = wave_transpose_sum<NP>(val, lane);
+                    const int q = transposed_value_index<NP>(lane);
+                    if ((lane & (NP == 32 ? 1 : 3)) == 0 && q < NV) dst[q] = sum;
                 } else {
 #pragma unroll
-                    for (int q = 0; q < NVMAX; q++) {
+                    for (int q = 0; q < NREG; q++) {
                         if (q < NV) {
                             const float sum = wave_sum_lane63(val[q]);
-                            if (lane == 63) part[(wv * kBwdBatch + j) * NV + q] = sum;
+                            if (lane == 63) dst[q] = sum;
                         }
                     }
                 }
@@ -240,13 +289,19 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         __syncthreads();
         for (int idx = tid; idx < nb * NV; idx += kBwdThreads) {
             const int j = idx / NV, q = idx - j * NV;
-            const uint32_t f0 = flag[j], f1 = flag[kBwdBatch + j];
             const uint32_t e = b.svals[b0 + j];
-            const bool t = (f0 | f1) != 0u;
+            uint32_t fl[kBwdWaves];
+            bool t = false;
+#pragma unroll
+            for (int w = 0; w < kBwdWaves; w++) {
+                fl[w] = flag[w * kBwdBatch + j];
+                t |= fl[w] != 0u;
+            }
             if (t) {
                 float sum = 0.f;
-                if (f0) sum += part[(0 * kBwdBatch + j) * NV + q];
-                if (f1) sum += part[(1 * kBwdBatch + j) * NV + q];
+#pragma unroll
+                for (int w = 0; w < kBwdWaves; w++)
+                    if (fl[w]) sum += part[(w * kBwdBatch + j) * NV + q];
                 b.slots[(size_t)e * NV + q] = sum;
             }
             if (q == 0) b.touched[e] = t ? 1 : 0;
