@@ -115,8 +115,8 @@ typedef struct {
     size_t views;           /* per-view device table */
     size_t proj_count;      /* uint32 [V*n]: tiles touched per (view, Gaussian); 0 = culled */
     size_t proj_zbits;      /* uint32 [V*n]: bits of fp32 camera-space z */
-    size_t proj_rec;        /* 3 x float4 [V*n]: projected record */
     size_t order;           /* uint32 [V*n]: (view*n + id) of each visible pair, front to back */
+    size_t sorted_rec;      /* 3 x float4 [V*n]: compositing record of each visible pair, front to back */
     size_t sorted_keys;     /* uint32 [key_capacity]: global tile id, sorted */
     size_t sorted_vals;     /* uint32 [key_capacity]: emission index of each sorted key */
     size_t sorted_gauss;    /* uint32 [key_capacity]: front-to-back index of each sorted key */

@@ -58,7 +58,7 @@ SGR_MAX_ADAM_SEGMENTS = 8
 
 class sgr_layout(ctypes.Structure):
     _fields_ = [(name, ctypes.c_size_t) for name in (
-        "total_bytes", "counters", "views", "proj_count", "proj_zbits", "proj_rec", "order", "sorted_keys",
+        "total_bytes", "counters", "views", "proj_count", "proj_zbits", "order", "sorted_rec", "sorted_keys",
         "sorted_vals", "sorted_gauss", "ranges", "tile_offsets")] + [
         ("num_tiles", ctypes.c_int64), ("num_pixels", ctypes.c_int64), ("vn", ctypes.c_int64)]
 

@@ -80,7 +80,6 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     P->count = take(4 * vns);
     P->zbits = take(4 * vns);
     P->gp_of_lin = take(4 * vns);
-    P->rec = take(sizeof(Proj) * vns);
     P->vis_k0 = take(4 * vns);
     P->vis_v0 = take(4 * vns);
     P->vis_k1 = take(4 * vns);
@@ -220,7 +219,7 @@ sgr_status sgr_workspace_layout(int64_t n, const sgr_camera* cams, int32_t num_v
     out->views = P.views;
     out->proj_count = P.count;
     out->proj_zbits = P.zbits;
-    out->proj_rec = P.rec;
+    out->sorted_rec = P.srec;
     out->order = P.order;
     out->sorted_keys = P.sorted_keys;
     out->sorted_vals = P.sorted_vals;

@@ -30,19 +30,15 @@ __global__ void publish_num_keys(const uint32_t* counters, int64_t* d_num_keys) 
 
 // --------------------------------------------------------------- projection
 
-// One thread per (view, Gaussian).  Everything that decides binning (the
-// camera-space point, the 2D covariance, the pixel rectangle, the depth
-// key) is evaluated in double precision with the same operation order as
-// the FP64 reference and no contraction into FMA, so the tile keys agree
-// bit for bit; the compositing record is then rounded to fp32.
-__global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
+// Projection of Gaussian i into view vw.  Everything that decides binning
+// (the camera-space point, the 2D covariance, the pixel rectangle, the depth
+// key) is evaluated in double precision with the same operation order as the
+// FP64 reference and no contraction into FMA, so the tile keys agree bit for
+// bit; the compositing record is then rounded to fp32.  Returns the number
+// of tiles the pixel rectangle touches (0: culled).
+__device__ __forceinline__ uint32_t project_pair(const ProjectArgs& a, const ViewDev& vw, int v, int64_t i,
+                                                 uint32_t* zbits, Proj* rec) {
 #pragma clang fp contract(off)
-    const int64_t lin = blockIdx.x * 256ll + threadIdx.x;
-    if (lin >= a.vn) return;
-    const int v = (int)(lin / a.n);
-    const int64_t i = lin - (int64_t)v * a.n;
-    const ViewDev& vw = a.views[v];
-    a.gp_of_lin[lin] = kInvalid;
     uint32_t count = 0;
     const double m0 = a.means[3 * i], m1 = a.means[3 * i + 1], m2 = a.means[3 * i + 2];
     double p[3];
@@ -51,89 +47,95 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
         p[r] = (double)vw.R[3 * r] * m0 + (double)vw.R[3 * r + 1] * m1 + (double)vw.R[3 * r + 2] * m2 +
                (double)vw.t[r];
     const float zf = (float)p[2];
-    a.zbits[lin] = __float_as_uint(zf);
-    Proj rec;
-    bool vis = p[2] > (double)a.z_near;
-    if (vis) {
-        const double q0 = a.quats[4 * i], q1 = a.quats[4 * i + 1], q2 = a.quats[4 * i + 2], q3 = a.quats[4 * i + 3];
-        const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-        const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
-        double Rq[9];
-        Rq[0] = 1 - 2 * (y * y + z * z); Rq[1] = 2 * (x * y - w * z);     Rq[2] = 2 * (x * z + w * y);
-        Rq[3] = 2 * (x * y + w * z);     Rq[4] = 1 - 2 * (x * x + z * z); Rq[5] = 2 * (y * z - w * x);
-        Rq[6] = 2 * (x * z - w * y);     Rq[7] = 2 * (y * z + w * x);     Rq[8] = 1 - 2 * (x * x + y * y);
-        const double s[3] = {(double)a.scales[3 * i], (double)a.scales[3 * i + 1], (double)a.scales[3 * i + 2]};
-        double S3[9];
+    *zbits = __float_as_uint(zf);
+    if (!(p[2] > (double)a.z_near)) return 0;
+    const double q0 = a.quats[4 * i], q1 = a.quats[4 * i + 1], q2 = a.quats[4 * i + 2], q3 = a.quats[4 * i + 3];
+    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+    double Rq[9];
+    Rq[0] = 1 - 2 * (y * y + z * z); Rq[1] = 2 * (x * y - w * z);     Rq[2] = 2 * (x * z + w * y);
+    Rq[3] = 2 * (x * y + w * z);     Rq[4] = 1 - 2 * (x * x + z * z); Rq[5] = 2 * (y * z - w * x);
+    Rq[6] = 2 * (x * z - w * y);     Rq[7] = 2 * (y * z + w * x);     Rq[8] = 1 - 2 * (x * x + y * y);
+    const double s[3] = {(double)a.scales[3 * i], (double)a.scales[3 * i + 1], (double)a.scales[3 * i + 2]};
+    double S3[9];
 #pragma unroll
-        for (int r = 0; r < 3; r++)
+    for (int r = 0; r < 3; r++)
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                double acc = 0;
+        for (int c = 0; c < 3; c++) {
+            double acc = 0;
 #pragma unroll
-                for (int e = 0; e < 3; e++) acc += Rq[3 * r + e] * s[e] * s[e] * Rq[3 * c + e];
-                S3[3 * r + c] = acc;
-            }
-        const double fx = vw.fx, fy = vw.fy, zz = p[2];
-        const double J[6] = {fx / zz, 0, -fx * p[0] / (zz * zz), 0, fy / zz, -fy * p[1] / (zz * zz)};
-        double T[6];
-#pragma unroll
-        for (int r = 0; r < 2; r++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                double acc = 0;
-#pragma unroll
-                for (int e = 0; e < 3; e++) acc += J[3 * r + e] * (double)vw.R[3 * e + c];
-                T[3 * r + c] = acc;
-            }
-        double S2[4];
-#pragma unroll
-        for (int r = 0; r < 2; r++)
-#pragma unroll
-            for (int c = 0; c < 2; c++) {
-                double acc = 0;
-#pragma unroll
-                for (int e = 0; e < 3; e++)
-#pragma unroll
-                    for (int f = 0; f < 3; f++) acc += T[3 * r + e] * S3[3 * e + f] * T[3 * c + f];
-                S2[2 * r + c] = acc;
-            }
-        const double lp = a.lowpass;
-        S2[0] += lp;
-        S2[3] += lp;
-        const double sxx = S2[0], sxy = 0.5 * (S2[1] + S2[2]), syy = S2[3];
-        const double det = sxx * syy - sxy * sxy;
-        const double o = a.opacity[i];
-        vis = det > 0 && o >= (double)a.alpha_min;
-        if (vis) {
-            const double mx = fx * p[0] / zz + (double)vw.cx, my = fy * p[1] / zz + (double)vw.cy;
-            const double qmax = 2.0 * log(o / (double)a.alpha_min);
-            const double ex = sqrt(qmax * sxx), ey = sqrt(qmax * syy);
-            double clo = ceil(mx - ex - 0.5), chi = floor(mx + ex - 0.5);
-            double rlo = ceil(my - ey - 0.5), rhi = floor(my + ey - 0.5);
-            if (clo < 0) clo = 0;
-            if (chi > vw.width - 1) chi = vw.width - 1;
-            if (rlo < 0) rlo = 0;
-            if (rhi > vw.height - 1) rhi = vw.height - 1;
-            // |mean| beyond 2^30 px cannot be represented in the record; such a
-            // Gaussian would need an astronomically large footprint to reach the
-            // image and is treated as culled on both sides of the parity check.
-            vis = clo <= chi && rlo <= rhi && fabs(mx) < 1073741824.0 && fabs(my) < 1073741824.0;
-            if (vis) {
-                const int c0 = (int)clo, c1 = (int)chi, r0 = (int)rlo, r1 = (int)rhi;
-                count = (uint32_t)((c1 / kTile - c0 / kTile + 1) * (r1 / kTile - r0 / kTile + 1));
-                const double ixd = floor(mx), iyd = floor(my);
-                const double a_ = syy / det;  // conic entries
-                const double kInv2Ln2 = 0.72134752044448170368;  // 1 / (2 ln 2)
-                rec.r0 = make_float4(__int_as_float((int)ixd), __int_as_float((int)iyd), (float)(mx - ixd),
-                                     (float)(my - iyd));
-                rec.r1 = make_float4((float)(a_ * kInv2Ln2), (float)(-sxy / syy), (float)(kInv2Ln2 / syy), (float)o);
-                rec.r2 = make_float4(__uint_as_float((uint32_t)c0 | ((uint32_t)c1 << 16)),
-                                     __uint_as_float((uint32_t)r0 | ((uint32_t)r1 << 16)), zf, __int_as_float(v));
-                a.rec[lin] = rec;
-            }
+            for (int e = 0; e < 3; e++) acc += Rq[3 * r + e] * s[e] * s[e] * Rq[3 * c + e];
+            S3[3 * r + c] = acc;
         }
+    const double fx = vw.fx, fy = vw.fy, zz = p[2];
+    const double J[6] = {fx / zz, 0, -fx * p[0] / (zz * zz), 0, fy / zz, -fy * p[1] / (zz * zz)};
+    double T[6];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            double acc = 0;
+#pragma unroll
+            for (int e = 0; e < 3; e++) acc += J[3 * r + e] * (double)vw.R[3 * e + c];
+            T[3 * r + c] = acc;
+        }
+    double S2[4];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            double acc = 0;
+#pragma unroll
+            for (int e = 0; e < 3; e++)
+#pragma unroll
+                for (int f = 0; f < 3; f++) acc += T[3 * r + e] * S3[3 * e + f] * T[3 * c + f];
+            S2[2 * r + c] = acc;
+        }
+    const double lp = a.lowpass;
+    S2[0] += lp;
+    S2[3] += lp;
+    const double sxx = S2[0], sxy = 0.5 * (S2[1] + S2[2]), syy = S2[3];
+    const double det = sxx * syy - sxy * sxy;
+    const double o = a.opacity[i];
+    if (!(det > 0 && o >= (double)a.alpha_min)) return 0;
+    const double mx = fx * p[0] / zz + (double)vw.cx, my = fy * p[1] / zz + (double)vw.cy;
+    const double qmax = 2.0 * log(o / (double)a.alpha_min);
+    const double ex = sqrt(qmax * sxx), ey = sqrt(qmax * syy);
+    double clo = ceil(mx - ex - 0.5), chi = floor(mx + ex - 0.5);
+    double rlo = ceil(my - ey - 0.5), rhi = floor(my + ey - 0.5);
+    if (clo < 0) clo = 0;
+    if (chi > vw.width - 1) chi = vw.width - 1;
+    if (rlo < 0) rlo = 0;
+    if (rhi > vw.height - 1) rhi = vw.height - 1;
+    // |mean| beyond 2^30 px cannot be represented in the record; such a
+    // Gaussian would need an astronomically large footprint to reach the
+    // image and is treated as culled on both sides of the parity check.
+    if (!(clo <= chi && rlo <= rhi && fabs(mx) < 1073741824.0 && fabs(my) < 1073741824.0)) return 0;
+    const int c0 = (int)clo, c1 = (int)chi, r0 = (int)rlo, r1 = (int)rhi;
+    count = (uint32_t)((c1 / kTile - c0 / kTile + 1) * (r1 / kTile - r0 / kTile + 1));
+    if (rec) {
+        const double ixd = floor(mx), iyd = floor(my);
+        const double a_ = syy / det;  // conic entries
+        const double kInv2Ln2 = 0.72134752044448170368;  // 1 / (2 ln 2)
+        rec->r0 = make_float4(__int_as_float((int)ixd), __int_as_float((int)iyd), (float)(mx - ixd), (float)(my - iyd));
+        rec->r1 = make_float4((float)(a_ * kInv2Ln2), (float)(-sxy / syy), (float)(kInv2Ln2 / syy), (float)o);
+        rec->r2 = make_float4(__uint_as_float((uint32_t)c0 | ((uint32_t)c1 << 16)),
+                              __uint_as_float((uint32_t)r0 | ((uint32_t)r1 << 16)), zf, __int_as_float(v));
     }
-    a.count[lin] = count;
+    return count;
+}
+
+// One thread per (view, Gaussian): tile count and depth key only; the
+// compositing record is recomputed later for the visible pairs alone.
+__global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
+    const int64_t lin = blockIdx.x * 256ll + threadIdx.x;
+    if (lin >= a.vn) return;
+    const int v = (int)(lin / a.n);
+    const int64_t i = lin - (int64_t)v * a.n;
+    a.gp_of_lin[lin] = kInvalid;
+    uint32_t zb;
+    a.count[lin] = project_pair(a, a.views[v], v, i, &zb, nullptr);
+    a.zbits[lin] = zb;
 }
 
 // --------------------------------------------------------------- compaction
@@ -185,8 +187,11 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
     const uint32_t nv = a.counters[kNumVisible];
     if (g >= nv) return;
     const uint32_t lin = a.order[g];
-    const int64_t i = (int64_t)(lin % (uint64_t)a.n);
-    Proj p = a.rec[lin];
+    const int v = (int)(lin / (uint64_t)a.n);
+    const int64_t i = (int64_t)lin - (int64_t)v * a.n;
+    Proj p;
+    uint32_t zb;
+    project_pair(a.proj, a.proj.views[v], v, i, &zb, &p);
     a.scol[g] = make_float4(a.rgb[3 * i], a.rgb[3 * i + 1], a.rgb[3 * i + 2], p.r2.z);
     const int k = a.k;
     const float* sv = a.sem_val + i * k;
@@ -311,7 +316,7 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
     pa.views = views; pa.n = P.n; pa.vn = P.vn;
     pa.alpha_min = P.cfg.alpha_min; pa.z_near = P.cfg.z_near; pa.lowpass = P.cfg.lowpass;
     pa.count = (uint32_t*)(ws + P.count); pa.zbits = (uint32_t*)(ws + P.zbits);
-    pa.rec = (Proj*)(ws + P.rec); pa.gp_of_lin = (uint32_t*)(ws + P.gp_of_lin);
+    pa.gp_of_lin = (uint32_t*)(ws + P.gp_of_lin);
     if (P.vn == 0) return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
     project_kernel<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(pa);
     // compaction of visible pairs, then the depth sort
@@ -327,7 +332,7 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
                                   (uint32_t)P.vn, 32, (uint32_t*)(ws + P.hist), partial, st);
     (void)passes;  // 4 passes: the result is back in the *0 buffers (P.order)
     GatherArgs ga;
-    ga.order = (const uint32_t*)(ws + P.order); ga.rec = pa.rec; ga.count = pa.count;
+    ga.order = (const uint32_t*)(ws + P.order); ga.proj = pa; ga.count = pa.count;
     ga.rgb = g->rgb; ga.sem_val = g->sem_val; ga.sem_idx = g->sem_idx;
     ga.n = P.n; ga.k = P.k; ga.kpad = P.kpad; ga.C = P.C; ga.counters = counters;
     ga.srec = (Proj*)(ws + P.srec); ga.scol = (float4*)(ws + P.scol); ga.ssv = (float*)(ws + P.ssv);

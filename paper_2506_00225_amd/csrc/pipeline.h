@@ -23,7 +23,7 @@ struct Plan {
     std::vector<ViewDev> view_table;
     // byte offsets
     size_t counters = 0, views = 0;
-    size_t count = 0, zbits = 0, rec = 0, gp_of_lin = 0;
+    size_t count = 0, zbits = 0, gp_of_lin = 0;
     size_t vis_k0 = 0, vis_v0 = 0, vis_k1 = 0, vis_v1 = 0, order = 0;
     size_t srec = 0, scol = 0, ssv = 0, ssi = 0, tcount = 0, toff = 0;
     size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, sgp = 0, ranges = 0;
@@ -44,12 +44,11 @@ struct ProjectArgs {
     int64_t n, vn;
     float alpha_min, z_near, lowpass;
     uint32_t *count, *zbits, *gp_of_lin;
-    Proj* rec;
 };
 
 struct GatherArgs {
     const uint32_t* order;
-    const Proj* rec;
+    ProjectArgs proj;
     const uint32_t* count;
     const float *rgb, *sem_val;
     const uint8_t* sem_idx;

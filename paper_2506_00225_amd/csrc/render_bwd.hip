@@ -175,6 +175,12 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     if (inside && last > start) atomicMax(&s_maxlast, last);
     __syncthreads();
     const uint32_t maxlast = __builtin_amdgcn_readfirstlane(s_maxlast);
+    // this wave's bound on blended list positions, and its 8x8 pixel block
+    uint32_t wlast = inside ? last : start;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
+    wlast = __builtin_amdgcn_readfirstlane(wlast);
+    const int bx0 = tx * kTile + (wv & 1) * 8, by0 = ty * kTile + (wv >> 1) * 8;
     const float amin = a.alpha_min, amax = a.alpha_max;
     const float k2ln2 = 1.38629436111989061883f;  // 2 ln 2
     float R = 0.f;
@@ -200,6 +206,18 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         __syncthreads();
         for (int j = nb - 1; j >= 0; j--) {
             const uint32_t s = b0 + j;
+            {
+                // scalar culling: past every pixel's last blend, or the
+                // rectangle misses this wave's block
+                const float4 q2u = s_r2[j];
+                const uint32_t rxu = __builtin_amdgcn_readfirstlane(__float_as_uint(q2u.x));
+                const uint32_t ryu = __builtin_amdgcn_readfirstlane(__float_as_uint(q2u.y));
+                if (s >= wlast || (int)(rxu >> 16) < bx0 || (int)(rxu & 0xffffu) > bx0 + 7 ||
+                    (int)(ryu >> 16) < by0 || (int)(ryu & 0xffffu) > by0 + 7) {
+                    if (lane == 0) flag[wv * kBwdBatch + j] = 0u;
+                    continue;
+                }
+            }
             float val[NREG];
 #pragma unroll
             for (int q = 0; q < NREG; q++) val[q] = 0.f;

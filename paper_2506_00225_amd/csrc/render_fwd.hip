@@ -30,6 +30,7 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     const int local = gt - vw.tile_off;
     const int tx = local % vw.tiles_x, ty = local / vw.tiles_x;
     const int px = tx * kTile + tile_px(tid), py = ty * kTile + tile_py(tid);
+    const int bx0 = tx * kTile + ((tid >> 6) & 1) * 8, by0 = ty * kTile + ((tid >> 7) & 1) * 8;
     const bool inside = px < vw.width && py < vw.height;
     const uint2 rg = a.ranges[gt];
     const uint32_t start = rg.x, end = rg.y;
@@ -83,10 +84,13 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                     n1 = s_r1[j + 1];
                     n2 = s_r2[j + 1];
                 }
-                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-                if (px < (int)(rx & 0xffffu) || px > (int)(rx >> 16) || py < (int)(ry & 0xffffu) ||
-                    py > (int)(ry >> 16))
-                    continue;
+                const uint32_t rx = __builtin_amdgcn_readfirstlane(__float_as_uint(q2.x));
+                const uint32_t ry = __builtin_amdgcn_readfirstlane(__float_as_uint(q2.y));
+                const int c_lo = (int)(rx & 0xffffu), c_hi = (int)(rx >> 16);
+                const int r_lo = (int)(ry & 0xffffu), r_hi = (int)(ry >> 16);
+                // scalar test: the rectangle misses this wave's 8x8 block
+                if (c_hi < bx0 || c_lo > bx0 + 7 || r_hi < by0 || r_lo > by0 + 7) continue;
+                if (px < c_lo || px > c_hi || py < r_lo || py > r_hi) continue;
                 float G, dx, dy;
                 const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
                 if (alpha < amin) continue;

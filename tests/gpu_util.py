@@ -52,12 +52,18 @@ def gpu_keys(fr):
 
 
 def gpu_proj(fr):
-    """Projected records of view 0: visible, rect, zbits, mean2d, conic."""
+    """Projected records of view 0 (indexed by Gaussian id): visible, rect,
+    zbits, tile count, mean2d, conic; taken from the front-to-back records."""
     lay = fr.layout
     n = fr.n
     cnt = ws_u32(fr, lay.proj_count, n)
     zb = ws_u32(fr, lay.proj_zbits, n)
-    rec = fr.ws[lay.proj_rec:lay.proj_rec + 48 * n].view(torch.float32).cpu().numpy().reshape(n, 12)
+    nvis = int(counters(fr)[1])
+    order = ws_u32(fr, lay.order, nvis).astype(np.int64)
+    srec = fr.ws[lay.sorted_rec:lay.sorted_rec + 48 * nvis].view(torch.float32).cpu().numpy().reshape(nvis, 12)
+    rec = np.zeros((n, 12), np.float32)
+    mask = order < n  # view 0 only
+    rec[order[mask]] = srec[mask]
     ri = rec.view(np.int32)
     ru = rec.view(np.uint32)
     mean2d = np.stack([ri[:, 0] + rec[:, 2].astype(np.float64), ri[:, 1] + rec[:, 3].astype(np.float64)], 1)
