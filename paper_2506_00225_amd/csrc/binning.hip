@@ -179,9 +179,8 @@ __global__ __launch_bounds__(256) void compact_visible(const uint32_t* __restric
 
 // --------------------------------------------------------------- gather
 
-// Gathers the records of visible pairs in front-to-back order g.  Bit 31 of
-// the record's view word flags a Gaussian whose top-k list repeats a class
-// (the compositing kernels then add its values one at a time).
+// Gathers the records of visible pairs in front-to-back order g.
+template <int KT>
 __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
     const uint32_t g = blockIdx.x * 256u + threadIdx.x;
     const uint32_t nv = a.counters[kNumVisible];
@@ -193,36 +192,49 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
     uint32_t zb;
     project_pair(a.proj, a.proj.views[v], v, i, &zb, &p);
     a.scol[g] = make_float4(a.rgb[3 * i], a.rgb[3 * i + 1], a.rgb[3 * i + 2], p.r2.z);
-    const int k = a.k;
+    const int k = KT > 0 ? KT : a.k;
+    const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
+    constexpr int KM = KT > 0 ? KT : kMaxK;
+    constexpr int KWM = (KM + 3) / 4;
     const float* sv = a.sem_val + i * k;
     float* dv = a.ssv + (size_t)g * k;
-    if ((k & 3) == 0) {
-        for (int m = 0; m < k; m += 4) *(float4*)(dv + m) = *(const float4*)(sv + m);
+    if constexpr (KT > 0 && (KT & 3) == 0) {
+#pragma unroll
+        for (int m = 0; m < KT; m += 4) *(float4*)(dv + m) = *(const float4*)(sv + m);
     } else {
         for (int m = 0; m < k; m++) dv[m] = sv[m];
     }
-    uint8_t cls[kMaxK];
-    bool bad = false, dup = false;
-    for (int m = 0; m < k; m++) {
-        uint8_t c = a.sem_idx[i * k + m];
+    // class indices, four per word
+    uint32_t words[KWM];
+    const uint8_t* si = a.sem_idx + i * k;
+    if constexpr (KT > 0 && (KT & 3) == 0) {
+#pragma unroll
+        for (int w = 0; w < KWM; w++) words[w] = *(const uint32_t*)(si + 4 * w);
+    } else {
+#pragma unroll
+        for (int w = 0; w < KWM; w++) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+                if (4 * w + b < k) word |= (uint32_t)si[4 * w + b] << (8 * b);
+            words[w] = word;
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int m = 0; m < KM; m++) {
+        if (m >= k) break;
+        const uint32_t c = (words[m >> 2] >> (8 * (m & 3))) & 0xffu;
         if ((int)c >= a.C) {  // never index past the class accumulators
             bad = true;
-            c = 0;
+            words[m >> 2] &= ~(0xffu << (8 * (m & 3)));
         }
-        for (int q = 0; q < m; q++) dup |= cls[q] == c;
-        cls[m] = c;
     }
     uint32_t* di = (uint32_t*)(a.ssi + (size_t)g * a.kpad);
-    for (int w = 0; w < (a.kpad >> 2); w++) {
-        uint32_t word = 0;
-        for (int b = 0; b < 4; b++) {
-            const int m = 4 * w + b;
-            if (m < k) word |= (uint32_t)cls[m] << (8 * b);
-        }
-        di[w] = word;
-    }
+#pragma unroll
+    for (int w = 0; w < KWM; w++)
+        if (w < kw) di[w] = words[w];
     if (bad) atomicOr(&a.counters[kStatus], Plan::kBadIndex);
-    p.r2.w = __uint_as_float(__float_as_uint(p.r2.w) | (dup ? 0x80000000u : 0u));
     a.srec[g] = p;
     a.tcount[g] = a.count[lin];
     a.gp_of_lin[lin] = g;
@@ -245,7 +257,7 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
         off[threadIdx.x] = a.toff[g];
         const float4 r2 = a.srec[g].r2;
         const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
-        const int v = __float_as_int(r2.w) & 0x7fffffff;
+        const int v = __float_as_int(r2.w);
         const int tx0 = (int)(rx & 0xffffu) / kTile, tx1 = (int)(rx >> 16) / kTile;
         const int ty0 = (int)(ry & 0xffffu) / kTile;
         const ViewDev& vw = a.views[v];
@@ -337,7 +349,10 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
     ga.n = P.n; ga.k = P.k; ga.kpad = P.kpad; ga.C = P.C; ga.counters = counters;
     ga.srec = (Proj*)(ws + P.srec); ga.scol = (float4*)(ws + P.scol); ga.ssv = (float*)(ws + P.ssv);
     ga.ssi = (uint8_t*)(ws + P.ssi); ga.tcount = (uint32_t*)(ws + P.tcount); ga.gp_of_lin = pa.gp_of_lin;
-    gather_sorted<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(ga);
+    const unsigned ggrid = (unsigned)div_up(P.vn, 256);
+    if (P.k == 16) gather_sorted<16><<<ggrid, 256, 0, st>>>(ga);
+    else if (P.k == 3) gather_sorted<3><<<ggrid, 256, 0, st>>>(ga);
+    else gather_sorted<0><<<ggrid, 256, 0, st>>>(ga);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }
 

@@ -175,12 +175,11 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     if (inside && last > start) atomicMax(&s_maxlast, last);
     __syncthreads();
     const uint32_t maxlast = __builtin_amdgcn_readfirstlane(s_maxlast);
-    // this wave's bound on blended list positions, and its 8x8 pixel block
+    // this wave's bound on blended list positions
     uint32_t wlast = inside ? last : start;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
     wlast = __builtin_amdgcn_readfirstlane(wlast);
-    const int bx0 = tx * kTile + (wv & 1) * 8, by0 = ty * kTile + (wv >> 1) * 8;
     const float amin = a.alpha_min, amax = a.alpha_max;
     const float k2ln2 = 1.38629436111989061883f;  // 2 ln 2
     float R = 0.f;
@@ -206,17 +205,9 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         __syncthreads();
         for (int j = nb - 1; j >= 0; j--) {
             const uint32_t s = b0 + j;
-            {
-                // scalar culling: past every pixel's last blend, or the
-                // rectangle misses this wave's block
-                const float4 q2u = s_r2[j];
-                const uint32_t rxu = __builtin_amdgcn_readfirstlane(__float_as_uint(q2u.x));
-                const uint32_t ryu = __builtin_amdgcn_readfirstlane(__float_as_uint(q2u.y));
-                if (s >= wlast || (int)(rxu >> 16) < bx0 || (int)(rxu & 0xffffu) > bx0 + 7 ||
-                    (int)(ryu >> 16) < by0 || (int)(ryu & 0xffffu) > by0 + 7) {
-                    if (lane == 0) flag[wv * kBwdBatch + j] = 0u;
-                    continue;
-                }
+            if (s >= wlast) {  // past every blend of this wave's pixels
+                if (lane == 0) flag[wv * kBwdBatch + j] = 0u;
+                continue;
             }
             float val[NREG];
 #pragma unroll
@@ -347,8 +338,10 @@ __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ sl
     const int NV = KT > 0 ? 10 + KT : nv_rt;
     const uint32_t nvis = counters[kNumVisible];
     const bool ok = !(counters[kStatus] & SGR_ECAPACITY);
-    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t gbase = g - (threadIdx.x & 63);
+    // Pairs are in depth order, so the nearest ones (the longest segments)
+    // are adjacent; striding pairs across workgroups spreads them over the
+    // machine instead of queueing them in one wave.
+    const uint32_t g = threadIdx.x * gridDim.x + blockIdx.x;
     const int lane = threadIdx.x & 63;
     const bool valid = g < nvis;
     uint32_t e0 = 0, e1 = 0;
@@ -377,6 +370,7 @@ __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ sl
         const int src = __ffsll((long long)lm) - 1;
         lm &= lm - 1;
         const uint32_t s0 = __shfl(e0, src, 64), s1 = __shfl(e1, src, 64);
+        const uint32_t gsrc = __shfl(g, src, 64);
         float acc[NVMAX];
 #pragma unroll
         for (int q = 0; q < NVMAX; q++) acc[q] = 0.f;
@@ -391,7 +385,7 @@ __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ sl
         for (int q = 0; q < NVMAX; q++) {
             if (q < NV) {
                 const float sum = wave_sum_lane63(acc[q]);
-                if (lane == 63) g2d[(size_t)(gbase + src) * NV + q] = sum;
+                if (lane == 63) g2d[(size_t)gsrc * NV + q] = sum;
             }
         }
     }

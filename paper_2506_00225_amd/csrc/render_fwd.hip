@@ -30,7 +30,6 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     const int local = gt - vw.tile_off;
     const int tx = local % vw.tiles_x, ty = local / vw.tiles_x;
     const int px = tx * kTile + tile_px(tid), py = ty * kTile + tile_py(tid);
-    const int bx0 = tx * kTile + ((tid >> 6) & 1) * 8, by0 = ty * kTile + ((tid >> 7) & 1) * 8;
     const bool inside = px < vw.width && py < vw.height;
     const uint2 rg = a.ranges[gt];
     const uint32_t start = rg.x, end = rg.y;
@@ -84,13 +83,10 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                     n1 = s_r1[j + 1];
                     n2 = s_r2[j + 1];
                 }
-                const uint32_t rx = __builtin_amdgcn_readfirstlane(__float_as_uint(q2.x));
-                const uint32_t ry = __builtin_amdgcn_readfirstlane(__float_as_uint(q2.y));
-                const int c_lo = (int)(rx & 0xffffu), c_hi = (int)(rx >> 16);
-                const int r_lo = (int)(ry & 0xffffu), r_hi = (int)(ry >> 16);
-                // scalar test: the rectangle misses this wave's 8x8 block
-                if (c_hi < bx0 || c_lo > bx0 + 7 || r_hi < by0 || r_lo > by0 + 7) continue;
-                if (px < c_lo || px > c_hi || py < r_lo || py > r_hi) continue;
+                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+                if (px < (int)(rx & 0xffffu) || px > (int)(rx >> 16) || py < (int)(ry & 0xffffu) ||
+                    py > (int)(ry >> 16))
+                    continue;
                 float G, dx, dy;
                 const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
                 if (alpha < amin) continue;
@@ -107,46 +103,30 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                 dd += col.w * w;
                 ss += w;
                 if (SEM != 0) {
+                    // Accumulator updates are LDS atomic adds without return:
+                    // each address belongs to this lane, so they are
+                    // uncontended, stay in program order (deterministic, and
+                    // repeated classes simply add), and need no read round trip.
                     const float* sv = s_sv + j * k;
                     const uint32_t* si = s_si + j * kw;
-                    const bool dup = (__float_as_uint(q2.w) >> 31) != 0u;
-                    if (KT > 0 && SEM == 1 && !dup) {
-                        // distinct classes: all reads, then all updates
-                        constexpr int KK = KT > 0 ? KT : 1;
-                        float vals[KK];
-                        uint32_t cls[KK];
-                        if constexpr (KT > 0 && (KT & 3) == 0) {
+                    constexpr int KK = KT > 0 ? KT : kMaxK;
+                    float vals[KK];
+                    if constexpr (KT > 0 && (KT & 3) == 0) {
 #pragma unroll
-                            for (int m = 0; m < KK; m += 4) {
-                                const float4 v4 = *(const float4*)(sv + m);
-                                vals[m] = v4.x; vals[m + 1] = v4.y; vals[m + 2] = v4.z; vals[m + 3] = v4.w;
-                            }
-                        } else {
-#pragma unroll
-                            for (int m = 0; m < KK; m++) vals[m] = sv[m];
+                        for (int m = 0; m < KK; m += 4) {
+                            const float4 v4 = *(const float4*)(sv + m);
+                            vals[m] = v4.x; vals[m + 1] = v4.y; vals[m + 2] = v4.z; vals[m + 3] = v4.w;
                         }
-#pragma unroll
-                        for (int m = 0; m < KK; m++) cls[m] = ((si[m >> 2] >> (8 * (m & 3))) & 0xffu) * kAccStride + tid;
-                        float cur[KK];
-#pragma unroll
-                        for (int m = 0; m < KK; m++) cur[m] = acc[cls[m]];
-#pragma unroll
-                        for (int m = 0; m < KK; m++) acc[cls[m]] = fmaf(vals[m], w, cur[m]);
                     } else {
 #pragma unroll
-                        for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
-                            if (KT == 0 && mw >= kw) break;
-                            const uint32_t word = si[mw];
+                        for (int m = 0; m < KK; m++) vals[m] = m < k ? sv[m] : 0.f;
+                    }
 #pragma unroll
-                            for (int b = 0; b < 4; b++) {
-                                const int m = mw * 4 + b;
-                                if (m < k) {
-                                    const uint32_t cl = (word >> (8 * b)) & 0xffu;
-                                    if (SEM == 1) acc[cl * kAccStride + tid] += sv[m] * w;
-                                    else if (gacc) gacc[cl] += sv[m] * w;
-                                }
-                            }
-                        }
+                    for (int m = 0; m < KK; m++) {
+                        if (KT == 0 && m >= k) break;
+                        const uint32_t cl = (si[m >> 2] >> (8 * (m & 3))) & 0xffu;
+                        if (SEM == 1) atomicAdd(&acc[cl * kAccStride + tid], vals[m] * w);
+                        else if (gacc) gacc[cl] += vals[m] * w;
                     }
                 }
                 T = Tn;
