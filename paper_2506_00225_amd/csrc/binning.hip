@@ -179,7 +179,9 @@ __global__ __launch_bounds__(256) void compact_visible(const uint32_t* __restric
 
 // --------------------------------------------------------------- gather
 
-// Gathers the records of visible pairs in front-to-back order g.
+// Gathers the records of visible pairs in front-to-back order g.  Bit 31 of
+// the record's view word flags a Gaussian whose top-k list repeats a class
+// (the forward then adds its values one at a time).
 template <int KT>
 __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
     const uint32_t g = blockIdx.x * 256u + threadIdx.x;
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
             words[w] = word;
         }
     }
-    bool bad = false;
+    bool bad = false, dup = false;
 #pragma unroll
     for (int m = 0; m < KM; m++) {
         if (m >= k) break;
@@ -229,12 +231,16 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
             bad = true;
             words[m >> 2] &= ~(0xffu << (8 * (m & 3)));
         }
+#pragma unroll
+        for (int q = 0; q < KM; q++)
+            if (q < m) dup |= ((words[q >> 2] >> (8 * (q & 3))) & 0xffu) == ((words[m >> 2] >> (8 * (m & 3))) & 0xffu);
     }
     uint32_t* di = (uint32_t*)(a.ssi + (size_t)g * a.kpad);
 #pragma unroll
     for (int w = 0; w < KWM; w++)
         if (w < kw) di[w] = words[w];
     if (bad) atomicOr(&a.counters[kStatus], Plan::kBadIndex);
+    p.r2.w = __uint_as_float(__float_as_uint(p.r2.w) | (dup ? 0x80000000u : 0u));
     a.srec[g] = p;
     a.tcount[g] = a.count[lin];
     a.gp_of_lin[lin] = g;
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
         off[threadIdx.x] = a.toff[g];
         const float4 r2 = a.srec[g].r2;
         const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
-        const int v = __float_as_int(r2.w);
+        const int v = __float_as_int(r2.w) & 0x7fffffff;
         const int tx0 = (int)(rx & 0xffffu) / kTile, tx1 = (int)(rx >> 16) / kTile;
         const int ty0 = (int)(ry & 0xffffu) / kTile;
         const ViewDev& vw = a.views[v];

@@ -103,30 +103,46 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                 dd += col.w * w;
                 ss += w;
                 if (SEM != 0) {
-                    // Accumulator updates are LDS atomic adds without return:
-                    // each address belongs to this lane, so they are
-                    // uncontended, stay in program order (deterministic, and
-                    // repeated classes simply add), and need no read round trip.
                     const float* sv = s_sv + j * k;
                     const uint32_t* si = s_si + j * kw;
-                    constexpr int KK = KT > 0 ? KT : kMaxK;
-                    float vals[KK];
-                    if constexpr (KT > 0 && (KT & 3) == 0) {
+                    const bool dup = (__float_as_uint(q2.w) >> 31) != 0u;
+                    if (KT > 0 && SEM == 1 && !dup) {
+                        // distinct classes: all reads, then all updates
+                        constexpr int KK = KT > 0 ? KT : 1;
+                        float vals[KK];
+                        uint32_t cls[KK];
+                        if constexpr (KT > 0 && (KT & 3) == 0) {
 #pragma unroll
-                        for (int m = 0; m < KK; m += 4) {
-                            const float4 v4 = *(const float4*)(sv + m);
-                            vals[m] = v4.x; vals[m + 1] = v4.y; vals[m + 2] = v4.z; vals[m + 3] = v4.w;
+                            for (int m = 0; m < KK; m += 4) {
+                                const float4 v4 = *(const float4*)(sv + m);
+                                vals[m] = v4.x; vals[m + 1] = v4.y; vals[m + 2] = v4.z; vals[m + 3] = v4.w;
+                            }
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < KK; m++) vals[m] = sv[m];
                         }
+#pragma unroll
+                        for (int m = 0; m < KK; m++) cls[m] = ((si[m >> 2] >> (8 * (m & 3))) & 0xffu) * kAccStride + tid;
+                        float cur[KK];
+#pragma unroll
+                        for (int m = 0; m < KK; m++) cur[m] = acc[cls[m]];
+#pragma unroll
+                        for (int m = 0; m < KK; m++) acc[cls[m]] = fmaf(vals[m], w, cur[m]);
                     } else {
 #pragma unroll
-                        for (int m = 0; m < KK; m++) vals[m] = m < k ? sv[m] : 0.f;
-                    }
+                        for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
+                            if (KT == 0 && mw >= kw) break;
+                            const uint32_t word = si[mw];
 #pragma unroll
-                    for (int m = 0; m < KK; m++) {
-                        if (KT == 0 && m >= k) break;
-                        const uint32_t cl = (si[m >> 2] >> (8 * (m & 3))) & 0xffu;
-                        if (SEM == 1) atomicAdd(&acc[cl * kAccStride + tid], vals[m] * w);
-                        else if (gacc) gacc[cl] += vals[m] * w;
+                            for (int b = 0; b < 4; b++) {
+                                const int m = mw * 4 + b;
+                                if (m < k) {
+                                    const uint32_t cl = (word >> (8 * b)) & 0xffu;
+                                    if (SEM == 1) acc[cl * kAccStride + tid] += sv[m] * w;
+                                    else if (gacc) gacc[cl] += sv[m] * w;
+                                }
+                            }
+                        }
                     }
                 }
                 T = Tn;

@@ -318,3 +318,30 @@ def test_score_views_vs_oracle_and_plain_path():
         torch.cuda.synchronize()
         assert int(pe[0]) == int(ne[v])
         assert abs(float(ph[0]) - hs[v]) <= 1e-9 * P
+
+
+def test_duplicate_top_k_classes_add():
+    """Repeated class indices within a Gaussian's top-k add (Eq. 3 with
+    p_{i,m} the sum of its entries); checked against the oracle."""
+    _say("duplicate classes")
+    sc = scenes.tiny_scene(seed=9)
+    rng = np.random.default_rng(3)
+    dup = rng.random(sc.n) < 0.3
+    sc.sem_idx[dup, 1] = sc.sem_idx[dup, 0]
+    _, got, _, want = _forward_case(sc)
+    U.compare_maps(got, want, want["flags"])
+
+
+def test_out_of_range_class_index_reported():
+    """An index >= C is an input error: reported as SGR_EINVAL by the status
+    word, never used to address memory."""
+    _say("bad class index")
+    sc = scenes.tiny_scene(seed=10)
+    sc.sem_idx[5, 0] = sc.num_classes + 3
+    fr = U.frame_for(sc)
+    g = Gaussians.from_scene(sc)
+    with pytest.raises(Exception) as e:
+        fr.prepare(g)
+    assert getattr(e.value, "status", None) == 1
+    fr.forward(g)
+    torch.cuda.synchronize()
