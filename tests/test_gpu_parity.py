@@ -337,7 +337,9 @@ def test_out_of_range_class_index_reported():
     word, never used to address memory."""
     _say("bad class index")
     sc = scenes.tiny_scene(seed=10)
-    sc.sem_idx[5, 0] = sc.num_classes + 3
+    pr = O.project(sc.means, sc.scales, sc.quats, sc.opacity, sc.cameras[0], O.config_array())
+    i = int(np.nonzero(pr["visible"])[0][0])
+    sc.sem_idx[i, 0] = sc.num_classes + 3
     fr = U.frame_for(sc)
     g = Gaussians.from_scene(sc)
     with pytest.raises(Exception) as e:
