@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--score-n", type=int, default=500_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-score", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run a plain streaming kernel over this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -147,6 +149,24 @@ def mapping_bench(args, torch, out):
     return sc
 
 
+def counted_traffic(kernel_file):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a streaming kernel), if
+    that summary was taken on the current kernel source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "render_bwd_1M_traffic.json")
+    src = os.path.join(ROOT, "paper_2506_00225_amd", "csrc", kernel_file)
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def roofline(out):
     """Algorithmic bytes of the dominant kernel call per launch (see the
     design notes for the per-unit figures)."""
@@ -164,8 +184,9 @@ def roofline(out):
     dom = max(("proj", "bin", "fwd", "bwd"), key=lambda s: stage[s])
     t = stage[dom] * 1e-3
     achieved = alg[dom] / t / 1e9
+    traffic = counted_traffic("render_bwd.hip") if dom == "bwd" else None
     return dom, {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                  "alg_bytes": int(alg[dom]), "ms": round(stage[dom], 4)}
 
 
@@ -196,6 +217,16 @@ def score_bench(args, torch, out):
     batched_ms = e0.elapsed_time(e1) / reps
     st, _, _ = fr.status()
     assert st == 0
+    graph, gne, ghs = fr.capture_score(g)
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_same = bool(torch.equal(gne, ne) and torch.equal(ghs, hs))
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / reps
     # plain: one frame per view, project/bin/render dense maps/score each
     frames = []
     for cam in sc.cameras:
@@ -226,6 +257,7 @@ def score_bench(args, torch, out):
     dmean = np.abs(ph.cpu().numpy() - hs.cpu().numpy()) / P
     same_empty = bool(torch.equal(pe, ne))
     out.update(dict(views_per_s_batched=fr.V / (batched_ms * 1e-3), views_per_s_plain=fr.V / (plain_ms * 1e-3),
+                    views_per_s_graph=fr.V / (graph_ms * 1e-3), score_graph_ms=graph_ms, score_graph_equal=graph_same,
                     score_batched_ms=batched_ms, score_plain_ms=plain_ms, score_max_mean_entropy_diff=float(dmean.max()),
                     score_n_empty_equal=same_empty, score_views=fr.V))
     log("scoring batched", batched_ms, "ms plain", plain_ms, "ms")
@@ -271,6 +303,14 @@ def main():
     sc = mapping_bench(args, torch, out)
     if not args.no_score:
         score_bench(args, torch, out)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # reads and writes copy_probe MiB each
+        torch.cuda.synchronize()
+        log("copy probe", args.copy_probe, "MiB x3")
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
@@ -291,7 +331,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    for key in ("views_per_s_batched", "views_per_s_plain", "score_batched_ms", "score_plain_ms",
+    for key in ("views_per_s_batched", "views_per_s_graph", "views_per_s_plain", "score_batched_ms", "score_graph_ms",
+                "score_graph_equal", "score_plain_ms",
                 "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views"):
         if key in out:
             line[key] = out[key]

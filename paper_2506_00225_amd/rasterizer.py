@@ -199,6 +199,22 @@ class Frame:
                                   self.ws.numel(), self.stream), "sgr_score_views")
         return n_empty, entropy_sum
 
+    def capture_score(self, g: Gaussians, n_empty=None, entropy_sum=None):
+        """Captures sgr_score_views for these cameras into a HIP graph (every
+        launch of the frame goes on the capture stream; camera tables travel
+        as kernel arguments, so nothing is copied from the host).  Returns
+        (graph, n_empty, entropy_sum); graph.replay() rescores the current
+        contents of the Gaussian tensors."""
+        n_empty = n_empty if n_empty is not None else torch.empty(self.V, dtype=torch.int32, device=self.device)
+        entropy_sum = entropy_sum if entropy_sum is not None else torch.empty(self.V, dtype=torch.float64,
+                                                                                device=self.device)
+        self.score(g, n_empty, entropy_sum)  # warm-up outside capture (sets kernel attributes)
+        torch.cuda.synchronize(self.device)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.score(g, n_empty, entropy_sum)
+        return graph, n_empty, entropy_sum
+
     def split(self, flat):
         """Per-view [H, W, ...] views of a flat [sum HW, ...] tensor."""
         out = []

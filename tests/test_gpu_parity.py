@@ -347,3 +347,93 @@ def test_out_of_range_class_index_reported():
     assert getattr(e.value, "status", None) == 1
     fr.forward(g)
     torch.cuda.synchronize()
+
+
+def test_multiview_forward_backward_sums_over_views():
+    """Three keyframes rendered and differentiated in one batch; the
+    gradient is the sum of the per-view oracle gradients."""
+    _say("multiview fwd+bwd")
+    sc = scenes.room_scene(n=30_000, targets=False)
+    base = sc.cameras[0]
+    cams = []
+    for j, (w, h) in enumerate([(320, 200), (256, 256), (400, 150)]):
+        c = scenes.look_at(base.center + np.array([0.3 * j, -0.2 * j, 0.1 * j]),
+                           base.center + np.array([3.0, 0.5 * (j - 1), 0.0]), w, h, 0.6 * w, 0.6 * w)
+        cams.append(c)
+    sc.cameras = cams
+    rng = np.random.default_rng(4)
+    fr = U.frame_for(sc)
+    g = Gaussians.from_scene(sc)
+    fr.prepare(g)
+    maps = fr.forward(g)
+    dls = [_grad_maps(rng, c.height, c.width, sc.num_classes) for c in cams]
+    flat = {k: torch.from_numpy(np.concatenate([d[k].reshape(c.height * c.width, -1) for d, c in zip(dls, cams)])
+                                ).cuda().squeeze(-1).contiguous() for k in ("rgb", "depth", "sil", "sem")}
+    out = fr.backward(g, flat)
+    torch.cuda.synchronize()
+    got = {k: U.to_np(v) for k, v in out.items()}
+    cfg = U.oracle_cfg()
+    want, bad = None, np.zeros(sc.n, bool)
+    for v, (c, dl) in enumerate(zip(cams, dls)):
+        pr, mp = O.forward(O.scene_arrays(sc), c, cfg, sc.num_classes)
+        U.compare_maps({k: fr.split(maps[k])[v].cpu().numpy() for k in maps}, mp, mp["flags"])
+        gv, _ = O.backward(O.scene_arrays(sc), c, cfg, sc.num_classes, dl, proj=pr)
+        want = gv if want is None else {k: want[k] + gv[k] for k in want}
+        bad |= U.tainted_gaussians(pr, mp["flags"])
+    U.compare_grads(got, want, bad)
+
+
+def test_full_size_mapping_frame_1m():
+    """The benchmarked workload at full size: 1M Gaussians, 1200x680, with
+    the key capacity and launch configuration the benchmark uses; forward
+    maps and gradients against the oracle."""
+    _say("full size 1M 1200x680")
+    sc = scenes.room_scene(n=1_000_000, targets=False)
+    cam = sc.cameras[0]
+    fr = U.frame_for(sc)
+    g = Gaussians.from_scene(sc)
+    fr.prepare(g)
+    _, _, nk = fr.status()
+    fr.key_capacity = int(nk * 1.5) + 4096
+    fr._alloc()
+    fr.prepare(g, check=False)
+    maps = fr.forward(g)
+    st, _, _ = fr.status()
+    assert st == 0
+    rng = np.random.default_rng(11)
+    dl = _grad_maps(rng, cam.height, cam.width, sc.num_classes)
+    gg = {k: torch.from_numpy(v).cuda().reshape(cam.height * cam.width, -1).squeeze(-1).contiguous()
+          for k, v in dl.items()}
+    out = fr.backward(g, gg)
+    torch.cuda.synchronize()
+    got_maps = {k: fr.split(v)[0].cpu().numpy() for k, v in maps.items()}
+    cfg = U.oracle_cfg()
+    pr, mp = O.forward(O.scene_arrays(sc), cam, cfg, sc.num_classes)
+    rep = U.compare_maps(got_maps, mp, mp["flags"])
+    assert rep["flagged"] <= 0.002 * mp["flags"].size, rep
+    want, _ = O.backward(O.scene_arrays(sc), cam, cfg, sc.num_classes, dl, proj=pr)
+    got = {k: U.to_np(v) for k, v in out.items()}
+    print("full size report", rep, U.compare_grads(got, want, U.tainted_gaussians(pr, mp["flags"])), flush=True)
+
+
+def test_score_views_graph_replay_matches_eager():
+    """sgr_score_views captured in a HIP graph: every replay, with eager work
+    and synchronisations in between, equals the eager result bit for bit."""
+    _say("score graph")
+    sc = scenes.candidate_scene(n=40_000, nviews=7)
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc)
+    ne0, hs0 = fr.score(g)
+    torch.cuda.synchronize()
+    ne0, hs0 = ne0.clone(), hs0.clone()
+    graph, ne, hs = fr.capture_score(g)
+    for r in range(4):
+        ne.fill_(-1)
+        hs.fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ne, ne0) and torch.equal(hs, hs0), r
+        fr.score(g)  # eager work between replays
+        torch.cuda.synchronize()
+    st, _, _ = fr.status()
+    assert st == 0
