@@ -104,7 +104,7 @@ def mapping_bench(args, torch, out):
         # mapping loss (Sec. 3.1 silhouette-masked depth + 0.5 colour L1) + L1(S, 1) + cross-entropy
         mapping_loss_grad(maps, t_rgb, t_depth, label, C, out=grads_in, scratch=scratch)
 
-    names = ["s0", "proj", "bin", "fwd", "loss", "bwd", "adam"]
+    names = ["s0", "proj", "bin", "fwd", "loss", "bwd_tiles", "bwd_gather", "adam"]
     tm = Timer(torch, names)
 
     def step(i, timed):
@@ -119,8 +119,10 @@ def mapping_bench(args, torch, out):
         blends[i].copy_(maps["n_contrib"].sum(dtype=torch.int64))
         loss_grad()
         mk("loss")
-        fr.backward(g, grads_in, gout)
-        mk("bwd")
+        fr.backward_tiles(g, grads_in)
+        mk("bwd_tiles")
+        fr.backward_gather(g, gout)
+        mk("bwd_gather")
         opt.step()
         mk("adam")
 
@@ -140,6 +142,7 @@ def mapping_bench(args, torch, out):
     stage = {}
     for a, b in zip(names[:-1], names[1:]):
         stage[b] = float(np.mean(tm.pairs_ms(a, b)))
+    stage["bwd"] = stage["bwd_tiles"] + stage["bwd_gather"]
     step_ms = float(np.mean(tm.pairs_ms("s0", "adam")))
     B = blends[args.warmup:].double().mean().item()
     fwd_bwd_ms = stage["proj"] + stage["bin"] + stage["fwd"] + stage["bwd"]
@@ -149,44 +152,58 @@ def mapping_bench(args, torch, out):
     return sc
 
 
-def counted_traffic(kernel_file):
-    """HBM bytes per launch of the dominant kernel from the committed PMC
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a streaming kernel), if
-    that summary was taken on the current kernel source; else None."""
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_bwd_kernel_1M_traffic.json")
+KERNEL_SOURCES = {"bwd_tiles": ("render_bwd.hip", "render_common.h", "pipeline.h", "sgr_internal.h"),
+                  "fwd": ("render_fwd.hip", "render_common.h", "pipeline.h", "sgr_internal.h")}
+
+
+def source_sha(stage):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "render_bwd_1M_traffic.json")
-    src = os.path.join(ROOT, "paper_2506_00225_amd", "csrc", kernel_file)
-    if not os.path.exists(path) or not os.path.exists(src):
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[stage]:
+        with open(os.path.join(ROOT, "paper_2506_00225_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counted_traffic(stage):
+    """HBM bytes per launch of the stage's kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain
+    streaming kernel of known size), if the summary was taken on the current
+    kernel sources; else None."""
+    if stage not in KERNEL_SOURCES or not os.path.exists(TRAFFIC_FILE):
         return None
-    with open(path) as f:
-        rec = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f).get(stage)
+    if not rec or rec.get("source_sha256") != source_sha(stage):
         return None
     return rec.get("bytes_per_launch")
 
 
 def roofline(out):
-    """Algorithmic bytes of the dominant kernel call per launch (see the
-    design notes for the per-unit figures)."""
+    """Algorithmic bytes per launch of each stage (every input read once,
+    every output and compulsory intermediate written once), over its HIP-event
+    time; the dominant stage is reported.  Per-key record reads and gradient
+    slots are implementation traffic and are not counted."""
     P, C, k, K, Nv, n = out["pixels"], out["C"], out["k"], out["keys"], out["nvis"], out["n"]
     rec = 48 + 16 + 4 * k + ((k + 3) // 4) * 4  # projected record + rgb/z + top-k values + indices
+    g2d = (10 + k) * 4  # per visible Gaussian: 2D mean, conic, opacity, rgb, depth, top-k values
     alg = {
+        "proj": 44 * n + 8 * n + 12 * Nv,
+        "bin": 12 * K * 3 + 8 * Nv,
         # read records once, sorted ids once; write maps and the two per-pixel words
         "fwd": rec * Nv + 4 * K + P * (5 + C) * 4 + 8 * P,
-        # read dL/dmaps and per-pixel words, records and ids once; write per-Gaussian grads once
-        "bwd": P * (5 + C) * 4 + 8 * P + 4 * K + rec * Nv + (14 + k) * 4 * n + 44 * n,
-        "proj": 44 * n + (4 + 4 + 48) * n + 12 * Nv,
-        "bin": 12 * K * 3 + 8 * Nv,
+        # read dL/dmaps, the per-pixel words, sorted ids and records once; write 2D gradients once
+        "bwd_tiles": P * (5 + C) * 4 + 8 * P + 4 * K + rec * Nv + g2d * Nv,
+        # read 2D gradients and parameters once; write per-Gaussian gradients once
+        "bwd_gather": g2d * Nv + 44 * n + (14 + k) * 4 * n,
     }
     stage = out["stage_ms"]
-    dom = max(("proj", "bin", "fwd", "bwd"), key=lambda s: stage[s])
-    t = stage[dom] * 1e-3
-    achieved = alg[dom] / t / 1e9
-    traffic = counted_traffic("render_bwd.hip") if dom == "bwd" else None
+    dom = max(alg, key=lambda s: stage[s])
+    achieved = alg[dom] / (stage[dom] * 1e-3) / 1e9
+    kern = {"fwd": "render_fwd_kernel", "bwd_tiles": "render_bwd_kernel"}.get(dom, dom)
     return dom, {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom), "kernel": kern,
                  "alg_bytes": int(alg[dom]), "ms": round(stage[dom], 4)}
 
 

@@ -188,6 +188,31 @@ sgr_status sgr_render_backward(const sgr_gaussians *g, const sgr_camera *cams, i
                                const sgr_grads *out, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * The two halves of sgr_render_backward, for callers that time or schedule
+ * them apart; called in this order on the same workspace they give the same
+ * bits as sgr_render_backward.
+ *
+ * sgr_render_backward_tiles -- the compositing part (Eq. 1 and Eq. 3
+ * differentiated per pixel): every (view, tile) walks its list back to front
+ * and writes, for each of its keys, the tile's summed gradient with respect
+ * to the projected 2D mean, conic, opacity, colour, depth and top-k values
+ * into that key's slot in the workspace (no atomics).  Must follow
+ * sgr_render_forward.
+ *
+ * sgr_render_backward_gather -- sums each Gaussian's key slots in a fixed
+ * order and chains the result through the EWA projection (Sec. 3.1's
+ * splatting of 3D Gaussians) to means, scales (linear), quats (including
+ * their normalisation), opacity, rgb and sem_val, summed over views.  `out`
+ * is overwritten.  Must follow sgr_render_backward_tiles.
+ */
+sgr_status sgr_render_backward_tiles(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views,
+                                     const sgr_config *cfg, int64_t key_capacity, const sgr_map_grads *dL,
+                                     void *workspace, size_t workspace_bytes, void *stream);
+sgr_status sgr_render_backward_gather(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views,
+                                      const sgr_config *cfg, int64_t key_capacity, const sgr_grads *out,
+                                      void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * sgr_score_views -- Sec. 3.2, Eq. 4-6: for each of num_views candidate
  * views (sizes may differ), render the silhouette and semantics without
  * writing maps and reduce per view: n_empty[v] = number of pixels where no

@@ -65,7 +65,7 @@ class sgr_layout(ctypes.Structure):
 
 EXPORTS = (
     "sgr_workspace_size", "sgr_workspace_layout", "sgr_project", "sgr_bin", "sgr_render_forward",
-    "sgr_render_backward", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
+    "sgr_render_backward", "sgr_render_backward_tiles", "sgr_render_backward_gather", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
     "sgr_read_status", "sgr_status_string", "sgr_mapping_loss_grad", "sgr_adam_step",
 )
 
@@ -97,6 +97,10 @@ def lib():
     L.sgr_render_backward.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_map_grads),
                                       ctypes.POINTER(sgr_grads), P, sz, P]
     L.sgr_render_backward.restype = i32
+    L.sgr_render_backward_tiles.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_map_grads), P, sz, P]
+    L.sgr_render_backward_tiles.restype = i32
+    L.sgr_render_backward_gather.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_grads), P, sz, P]
+    L.sgr_render_backward_gather.restype = i32
     L.sgr_score_views.argtypes = [g_p, cam_p, i32, cfg_p, i64, P, P, P, sz, P]
     L.sgr_score_views.restype = i32
     L.sgr_score_maps_workspace_size.argtypes = [i32, i32]
@@ -159,6 +163,16 @@ def sgr_render_forward(g, cams, num_views, cfg, key_capacity, maps, workspace, w
 def sgr_render_backward(g, cams, num_views, cfg, key_capacity, dl, grads, workspace, workspace_bytes, stream):
     return lib().sgr_render_backward(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, dl,
                                      ctypes.byref(grads), workspace, workspace_bytes, stream)
+
+
+def sgr_render_backward_tiles(g, cams, num_views, cfg, key_capacity, dl, workspace, workspace_bytes, stream):
+    return lib().sgr_render_backward_tiles(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, dl,
+                                           workspace, workspace_bytes, stream)
+
+
+def sgr_render_backward_gather(g, cams, num_views, cfg, key_capacity, grads, workspace, workspace_bytes, stream):
+    return lib().sgr_render_backward_gather(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity,
+                                            ctypes.byref(grads), workspace, workspace_bytes, stream)
 
 
 def sgr_score_views(g, cams, num_views, cfg, key_capacity, n_empty, entropy_sum, workspace, workspace_bytes, stream):

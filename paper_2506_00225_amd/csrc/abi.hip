@@ -266,7 +266,28 @@ sgr_status sgr_render_backward(const sgr_gaussians* g, const sgr_camera* cams, i
     Plan P;
     sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
     if (s != SGR_OK) return s;
-    return launch_backward(P, g, dL, out, (char*)workspace, (hipStream_t)stream);
+    if ((s = launch_backward_tiles(P, dL, (char*)workspace, (hipStream_t)stream)) != SGR_OK) return s;
+    return launch_backward_gather(P, g, out, (char*)workspace, (hipStream_t)stream);
+}
+
+sgr_status sgr_render_backward_tiles(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
+                                     const sgr_config* cfg, int64_t key_capacity, const sgr_map_grads* dL,
+                                     void* workspace, size_t workspace_bytes, void* stream) {
+    if (!dL) return SGR_EINVAL;
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    return launch_backward_tiles(P, dL, (char*)workspace, (hipStream_t)stream);
+}
+
+sgr_status sgr_render_backward_gather(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
+                                      const sgr_config* cfg, int64_t key_capacity, const sgr_grads* out,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+    if (!out) return SGR_EINVAL;
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    return launch_backward_gather(P, g, out, (char*)workspace, (hipStream_t)stream);
 }
 
 sgr_status sgr_score_views(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,

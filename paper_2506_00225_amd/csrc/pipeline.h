@@ -74,8 +74,9 @@ struct KeyArgs {
 sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st);
 sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t st);
 sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStream_t st);
-sgr_status launch_backward(const Plan& P, const sgr_gaussians* g, const sgr_map_grads* dL, const sgr_grads* out,
-                           char* ws, hipStream_t st);
+sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* ws, hipStream_t st);
+sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const sgr_grads* out, char* ws,
+                                  hipStream_t st);
 sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, char* ws, hipStream_t st);
 sgr_status launch_score_maps(const float* sem, const int32_t* n_contrib, int W, int H, int C, uint32_t* n_empty,
                              double* entropy_sum, char* scratch, hipStream_t st);

@@ -533,8 +533,7 @@ static void set_lds_b(K kernel, size_t bytes) {
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-sgr_status launch_backward(const Plan& P, const sgr_gaussians* g, const sgr_map_grads* dL, const sgr_grads* out,
-                           char* ws, hipStream_t st) {
+sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* ws, hipStream_t st) {
     BwdArgs b;
     memset(&b, 0, sizeof(b));
     b.t = make_tile_args(P, ws);
@@ -561,20 +560,28 @@ sgr_status launch_backward(const Plan& P, const sgr_gaussians* g, const sgr_map_
         set_lds_b(render_bwd_kernel<0>, lds);
         render_bwd_kernel<0><<<grid, kBwdThreads, lds, st>>>(b);
     }
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const sgr_grads* out, char* ws,
+                                  hipStream_t st) {
     const uint32_t* counters = (const uint32_t*)(ws + P.counters);
+    const int nvals = 10 + P.k;
     const unsigned ggrid = (unsigned)div_up(P.vn, 256);
     if (ggrid > 0) {
+        const float* slots = (const float*)(ws + P.slots);
+        const uint8_t* touched = (const uint8_t*)(ws + P.touched);
         const uint32_t* toff = (const uint32_t*)(ws + P.toff);
         const uint32_t* tcount = (const uint32_t*)(ws + P.tcount);
         float* g2d = (float*)(ws + P.g2d);
-        if (P.k == 16) gather_slots<16><<<ggrid, 256, 0, st>>>(b.slots, b.touched, toff, tcount, counters, b.nvals, g2d);
-        else if (P.k == 3) gather_slots<3><<<ggrid, 256, 0, st>>>(b.slots, b.touched, toff, tcount, counters, b.nvals, g2d);
-        else gather_slots<0><<<ggrid, 256, 0, st>>>(b.slots, b.touched, toff, tcount, counters, b.nvals, g2d);
+        if (P.k == 16) gather_slots<16><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, counters, nvals, g2d);
+        else if (P.k == 3) gather_slots<3><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, counters, nvals, g2d);
+        else gather_slots<0><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, counters, nvals, g2d);
     }
     ProjBwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opacity = g->opacity;
     pa.views = (const ViewDev*)(ws + P.views);
-    pa.n = P.n; pa.V = P.V; pa.k = P.k; pa.NV = b.nvals;
+    pa.n = P.n; pa.V = P.V; pa.k = P.k; pa.NV = nvals;
     pa.lowpass = P.cfg.lowpass;
     pa.gp_of_lin = (const uint32_t*)(ws + P.gp_of_lin);
     pa.g2d = (const float*)(ws + P.g2d);

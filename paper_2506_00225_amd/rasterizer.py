@@ -168,7 +168,7 @@ class Frame:
                 "sgr_render_forward")
         return maps
 
-    def backward(self, g: Gaussians, grads: dict, out: dict | None = None):
+    def _map_grads(self, grads: dict):
         C = self.cfg.num_classes
         cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C}
         gp = {}
@@ -183,12 +183,34 @@ class Frame:
         arr = (L.sgr_map_grads * self.V)()
         for v in range(self.V):
             arr[v] = L.sgr_map_grads(gp["rgb"][v], gp["depth"][v], gp["sil"][v], gp["sem"][v])
+        return arr
+
+    @staticmethod
+    def _grads(g: Gaussians, out: dict | None):
         if out is None:
             out = {name: torch.empty_like(getattr(g, name)) for name in
                    ("means", "scales", "quats", "opacity", "rgb", "sem_val")}
         gr = L.sgr_grads(*[_ptr(out[name]) for name in ("means", "scales", "quats", "opacity", "rgb", "sem_val")])
+        return out, gr
+
+    def backward(self, g: Gaussians, grads: dict, out: dict | None = None):
+        arr = self._map_grads(grads)
+        out, gr = self._grads(g, out)
         L.check(L.sgr_render_backward(g.c_struct(), *self._args(), arr, gr, _ptr(self.ws), self.ws.numel(),
                                       self.stream), "sgr_render_backward")
+        return out
+
+    def backward_tiles(self, g: Gaussians, grads: dict):
+        """First half of backward: per-key gradient slots (kept in the workspace)."""
+        arr = self._map_grads(grads)
+        L.check(L.sgr_render_backward_tiles(g.c_struct(), *self._args(), arr, _ptr(self.ws), self.ws.numel(),
+                                            self.stream), "sgr_render_backward_tiles")
+
+    def backward_gather(self, g: Gaussians, out: dict | None = None):
+        """Second half of backward: per-Gaussian gradients from the key slots."""
+        out, gr = self._grads(g, out)
+        L.check(L.sgr_render_backward_gather(g.c_struct(), *self._args(), gr, _ptr(self.ws), self.ws.numel(),
+                                             self.stream), "sgr_render_backward_gather")
         return out
 
     def score(self, g: Gaussians, n_empty=None, entropy_sum=None):

@@ -228,6 +228,25 @@ def test_bitwise_determinism():
         assert torch.equal(res[0][1][k], res[1][1][k]), k
 
 
+def test_backward_halves_equal_full_backward():
+    """sgr_render_backward_tiles followed by sgr_render_backward_gather gives
+    the bits of sgr_render_backward."""
+    _say("backward halves")
+    sc = scenes.tiny_scene(seed=9)
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc)
+    fr.prepare(g)
+    maps = fr.forward(g)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    dl = {k: torch.randn(maps[k].shape, generator=gen, device="cuda") for k in ("rgb", "depth", "sil", "sem")}
+    full = {k: v.clone() for k, v in fr.backward(g, dict(dl)).items()}
+    fr.backward_tiles(g, dict(dl))
+    halves = fr.backward_gather(g)
+    torch.cuda.synchronize()
+    for k in full:
+        assert torch.equal(full[k], halves[k]), k
+
+
 def test_permutation_invariance():
     _say("permutation")
     sc = scenes.tiny_scene(seed=8)
