@@ -6,7 +6,8 @@
 
 namespace sgr {
 
-constexpr int kBwdBatch = 32;
+constexpr int kBwdBatch = 64;  // keys per batch: one per lane of the culling ballot
+static_assert(kBwdBatch == 64, "the backward culls a batch with one 64-lane ballot");
 
 // Sum over the 64 lanes of a wave; the total lands in lane 63.  Row-wise
 // inclusive scan with row_shr (zero fill), then row_bcast:15 / row_bcast:31
@@ -33,7 +34,6 @@ struct BwdArgs {
     const uint32_t* svals;     // sorted emission index of each key
     int nvals;                 // 10 + k
     int semgeo;
-    int sem_in_lds;
 };
 
 constexpr int kBwdThreads = 256;  // 4 waves, one pixel per lane, 8x8 pixel block per wave
@@ -119,13 +119,15 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     constexpr int NREG = NP > 0 ? NP : NVMAX;
     const int NV = 10 + k;
 
+    constexpr int KM = KT > 0 ? KT : kMaxK;  // register bound on k
+    constexpr int KWM = (KM + 3) / 4;         // ... and on the index words
     float* gp = smem;  // [C][257] dL/dsem of the tile's pixels, column = owning thread
-    float* base = smem + (b.sem_in_lds ? acc_floats(C) : 0);
-    float4* s_r0 = (float4*)base;
+    float4* s_r0 = (float4*)(smem + acc_floats(C));
     float4* s_r1 = s_r0 + kBwdBatch;
     float4* s_r2 = s_r1 + kBwdBatch;
     float4* s_col = s_r2 + kBwdBatch;
-    float* s_sv = (float*)(s_col + kBwdBatch);
+    uint32_t* s_e = (uint32_t*)(s_col + kBwdBatch);                   // emission index of each key
+    float* s_sv = (float*)(s_e + kBwdBatch);
     uint32_t* s_si = (uint32_t*)(s_sv + kBwdBatch * k);
     float* part = (float*)(s_si + kBwdBatch * kw);                    // [waves][kBwdBatch][NV]
     uint32_t* flag = (uint32_t*)(part + kBwdWaves * kBwdBatch * NV);  // [waves][kBwdBatch]
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         if (gr.sil) gS = gr.sil[pix];
     }
     if (tid == 0) s_maxlast = start;
-    if (b.sem_in_lds) {
+    {
         const int x0 = tx * kTile, y0 = ty * kTile;
         const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
         const int row_elems = kTile * C;
@@ -182,96 +184,149 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     wlast = __builtin_amdgcn_readfirstlane(wlast);
     const float amin = a.alpha_min, amax = a.alpha_max;
     const float k2ln2 = 1.38629436111989061883f;  // 2 ln 2
+    const int wx0 = tx * kTile + (wv & 1) * 8, wy0 = ty * kTile + (wv >> 1) * 8;  // this wave's 8x8 block
     float R = 0.f;
 
-    for (int64_t bend = maxlast; bend > (int64_t)start; bend -= kBwdBatch) {
-        const uint32_t b0 = (uint32_t)max((int64_t)start, bend - kBwdBatch);
+    // Staging registers: thread j < kBwdBatch carries key j's record, colour
+    // and emission index, thread 128 + j its top-k values and class indices.
+    // The next batch is fetched into them while the current one is composited.
+    float4 p0 = {}, p1 = {}, p2 = {}, pc = {};
+    uint32_t pe = 0;
+    float psv[KM];
+    uint32_t psi[KWM];
+    auto fetch = [&](uint32_t f0, int fn) {
+        if (tid < fn) {
+            const uint32_t g = a.sgp[f0 + tid];
+            const Proj p = a.srec[g];
+            p0 = p.r0;
+            p1 = p.r1;
+            p2 = p.r2;
+            pc = a.scol[g];
+            pe = b.svals[f0 + tid];
+        } else if (tid >= 128 && tid - 128 < fn) {
+            const uint32_t g = a.sgp[f0 + tid - 128];
+            const float* sv = a.ssv + (size_t)g * k;
+            if constexpr (KT > 0 && (KT & 3) == 0) {
+#pragma unroll
+                for (int m = 0; m < KM; m += 4) {
+                    const float4 v4 = *(const float4*)(sv + m);
+                    psv[m] = v4.x; psv[m + 1] = v4.y; psv[m + 2] = v4.z; psv[m + 3] = v4.w;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < KM; m++)
+                    if (m < k) psv[m] = sv[m];
+            }
+            const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
+#pragma unroll
+            for (int m = 0; m < KWM; m++)
+                if (m < kw) psi[m] = si[m];
+        }
+    };
+
+    int64_t bend = maxlast;
+    uint32_t b0 = (uint32_t)max((int64_t)start, bend - kBwdBatch);
+    if (bend > (int64_t)start) fetch(b0, (int)(bend - b0));
+    while (bend > (int64_t)start) {
         const int nb = (int)(bend - b0);
         if (tid < nb) {
-            const uint32_t g = a.sgp[b0 + tid];
-            const Proj p = a.srec[g];
-            s_r0[tid] = p.r0;
-            s_r1[tid] = p.r1;
-            s_r2[tid] = p.r2;
-            s_col[tid] = a.scol[g];
+            s_r0[tid] = p0;
+            s_r1[tid] = p1;
+            s_r2[tid] = p2;
+            s_col[tid] = pc;
+            s_e[tid] = pe;
         } else if (tid >= 128 && tid - 128 < nb) {
             const int j = tid - 128;
-            const uint32_t g = a.sgp[b0 + j];
-            const float* sv = a.ssv + (size_t)g * k;
-            for (int m = 0; m < k; m++) s_sv[j * k + m] = sv[m];
-            const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
-            for (int m = 0; m < kw; m++) s_si[j * kw + m] = si[m];
+#pragma unroll
+            for (int m = 0; m < KM; m++)
+                if (m < k) s_sv[j * k + m] = psv[m];
+#pragma unroll
+            for (int m = 0; m < KWM; m++)
+                if (m < kw) s_si[j * kw + m] = psi[m];
         }
         __syncthreads();
-        for (int j = nb - 1; j >= 0; j--) {
+        const int64_t nend = b0;
+        const uint32_t nb0 = (uint32_t)max((int64_t)start, nend - kBwdBatch);
+        if (nend > (int64_t)start) fetch(nb0, (int)(nend - nb0));
+
+        // Keys of this batch that can touch this wave's pixels: before the
+        // wave's last blend and with a pixel rectangle meeting its block.
+        bool hit = false;
+        if (lane < nb) {
+            const float4 q2 = s_r2[lane];
+            const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+            hit = b0 + lane < wlast && (int)(rx & 0xffffu) <= wx0 + 7 && (int)(rx >> 16) >= wx0 &&
+                  (int)(ry & 0xffffu) <= wy0 + 7 && (int)(ry >> 16) >= wy0;
+            if (!hit) flag[wv * kBwdBatch + lane] = 0u;
+        }
+        uint64_t todo = __ballot(hit);
+        while (todo) {  // back to front
+            const int j = 63 - __builtin_clzll(todo);
+            todo &= ~(1ull << j);
             const uint32_t s = b0 + j;
-            if (s >= wlast) {  // past every blend of this wave's pixels
-                if (lane == 0) flag[wv * kBwdBatch + j] = 0u;
-                continue;
-            }
-            float val[NREG];
+            const float4 q0 = s_r0[j], q1 = s_r1[j], q2 = s_r2[j];
+            const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+            float G, dx, dy;
+            const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
+            const bool act = s < last && px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) &&
+                             py >= (int)(ry & 0xffffu) && py <= (int)(ry >> 16) && alpha >= amin;
+            const uint64_t any = __ballot(act);
+            if (any) {
+                float val[NREG];
 #pragma unroll
-            for (int q = 0; q < NREG; q++) val[q] = 0.f;
-            bool act = false;
-            if (s < last) {
-                const float4 q2 = s_r2[j];
-                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-                if (px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) && py >= (int)(ry & 0xffffu) &&
-                    py <= (int)(ry >> 16)) {
-                    const float4 q0 = s_r0[j], q1 = s_r1[j];
-                    float G, dx, dy;
-                    const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
-                    if (alpha >= amin) {
-                        act = true;
-                        const float om = 1.f - alpha;
-                        T = T / om;  // transmittance in front of this Gaussian
-                        const float w = alpha * T;
-                        const float4 col = s_col[j];
-                        val[6] = w * gC0;
-                        val[7] = w * gC1;
-                        val[8] = w * gC2;
-                        val[9] = w * gD;
-                        float e = col.x * gC0 + col.y * gC1 + col.z * gC2 + col.w * gD + gS;
-                        float es = 0.f;
-                        if (b.sem_in_lds) {
-                            const float* sv = s_sv + j * k;
-                            const uint32_t* si = s_si + j * kw;
+                for (int q = 0; q < NREG; q++) val[q] = 0.f;
+                const float4 col = s_col[j];
+                // the pixel's dL/dsem at the key's top-k classes
+                float sg[KM];
+                float es = 0.f;
+                {
+                    const float* sv = s_sv + j * k;
+                    const uint32_t* si = s_si + j * kw;
 #pragma unroll
-                            for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
-                                if (KT == 0 && mw >= kw) break;
-                                const uint32_t word = si[mw];
+                    for (int mw = 0; mw < KWM; mw++) {
+                        if (KT == 0 && mw >= kw) break;
+                        const uint32_t word = si[mw];
 #pragma unroll
-                                for (int bb = 0; bb < 4; bb++) {
-                                    const int m = mw * 4 + bb;
-                                    if (m < k) {
-                                        const float g = gp[((word >> (8 * bb)) & 0xffu) * kAccStride + tid];
-                                        val[10 + m] = w * g;
-                                        es += sv[m] * g;
-                                    }
-                                }
+                        for (int bb = 0; bb < 4; bb++) {
+                            const int m = mw * 4 + bb;
+                            if (m < k) {
+                                sg[m] = gp[((word >> (8 * bb)) & 0xffu) * kAccStride + tid];
+                                es += sv[m] * sg[m];
                             }
-                        }
-                        if (b.semgeo) e += es;
-                        const float dalpha = T * e - R / om;
-                        R += e * w;
-                        if (q1.w * G < amax) {
-                            val[5] = dalpha * G;
-                            const float dQ = dalpha * (-0.5f * alpha);
-                            const float ca = q1.x * k2ln2;
-                            const float cb = q1.y * ca;
-                            const float cc = q1.z * k2ln2 + q1.y * cb;
-                            val[2] = dQ * dx * dx;
-                            val[3] = dQ * 2.f * dx * dy;
-                            val[4] = dQ * dy * dy;
-                            val[0] = -2.f * dQ * (ca * dx + cb * dy);
-                            val[1] = -2.f * dQ * (cb * dx + cc * dy);
                         }
                     }
                 }
-            }
-            const uint64_t any = __ballot(act);
-            float* dst = part + (wv * kBwdBatch + j) * NV;
-            if (any) {
+                const float om = 1.f - alpha;
+                const float rom = __builtin_amdgcn_rcpf(om);
+                const float Tf = T * rom;  // transmittance in front of this Gaussian
+                const float w = alpha * Tf;
+                float e = col.x * gC0 + col.y * gC1 + col.z * gC2 + col.w * gD + gS;
+                if (b.semgeo) e += es;
+                const float dalpha = Tf * e - R * rom;
+                if (act) {
+                    T = Tf;
+                    R += e * w;
+                }
+                // alpha = min(alpha_max, o G): no gradient through the clamp
+                const bool free = act && q1.w * G < amax;
+                const float dQ = free ? dalpha * (-0.5f * alpha) : 0.f;
+                val[5] = free ? dalpha * G : 0.f;
+                const float ca = q1.x * k2ln2;
+                const float cb = q1.y * ca;
+                const float cc = q1.z * k2ln2 + q1.y * cb;
+                val[2] = dQ * dx * dx;
+                val[3] = dQ * 2.f * dx * dy;
+                val[4] = dQ * dy * dy;
+                val[0] = -2.f * dQ * (ca * dx + cb * dy);
+                val[1] = -2.f * dQ * (cb * dx + cc * dy);
+                val[6] = act ? w * gC0 : 0.f;
+                val[7] = act ? w * gC1 : 0.f;
+                val[8] = act ? w * gC2 : 0.f;
+                val[9] = act ? w * gD : 0.f;
+#pragma unroll
+                for (int m = 0; m < KM; m++)
+                    if (m < k) val[10 + m] = act ? w * sg[m] : 0.f;
+                float* dst = part + (wv * kBwdBatch + j) * NV;
                 if ((any & (any - 1)) == 0) {
                     // one active lane: its values are the wave's sums
                     if (act) {
@@ -298,7 +353,7 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         __syncthreads();
         for (int idx = tid; idx < nb * NV; idx += kBwdThreads) {
             const int j = idx / NV, q = idx - j * NV;
-            const uint32_t e = b.svals[b0 + j];
+            const uint32_t e = s_e[j];
             uint32_t fl[kBwdWaves];
             bool t = false;
 #pragma unroll
@@ -316,6 +371,8 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
             if (q == 0) b.touched[e] = t ? 1 : 0;
         }
         __syncthreads();
+        bend = nend;
+        b0 = nb0;
     }
     for (uint32_t s = maxlast + tid; s < end; s += kBwdThreads) b.touched[b.svals[s]] = 0;
 }
@@ -520,10 +577,10 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
 
 // ------------------------------------------------------------------ launcher
 
-static size_t bwd_lds_bytes(int C, int k, int kpad, bool sem_lds) {
-    size_t b = (size_t)kBwdBatch * (4 * sizeof(float4) + k * sizeof(float) + kpad);
+static size_t bwd_lds_bytes(int C, int k, int kpad) {
+    size_t b = (size_t)kBwdBatch * (4 * sizeof(float4) + sizeof(uint32_t) + k * sizeof(float) + kpad);
     b += (size_t)kBwdWaves * kBwdBatch * (10 + k) * sizeof(float) + kBwdWaves * kBwdBatch * sizeof(uint32_t);
-    if (sem_lds) b += (size_t)acc_floats(C) * sizeof(float);
+    b += (size_t)acc_floats(C) * sizeof(float);
     return b;
 }
 
@@ -546,8 +603,7 @@ sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* w
     b.svals = (const uint32_t*)(ws + P.sorted_vals);
     b.nvals = 10 + P.k;
     b.semgeo = P.cfg.sem_grad_to_geometry;
-    size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad, true);
-    b.sem_in_lds = 1;
+    size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
     if (P.k == 16) {

@@ -5,7 +5,8 @@
 
 namespace sgr {
 
-constexpr int kFwdBatch = 128;     // Gaussians staged per forward batch
+constexpr int kFwdBatch = 128;     // Gaussians staged per forward batch (two culling ballots)
+static_assert(kFwdBatch == 128, "the forward culls a batch with two 64-lane ballots");
 constexpr size_t kMaxLds = 160 * 1024;
 
 // LDS floats of a class-major accumulator tile, rounded up so that what

@@ -47,41 +47,120 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     uint32_t last = start;
     bool done = !inside;
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int wx0 = tx * kTile + (wv & 1) * 8, wy0 = ty * kTile + (wv >> 1) * 8;  // this wave's 8x8 block
 
+    // Staging registers: thread j < kFwdBatch carries list entry j's record
+    // and colour, thread kFwdBatch + j its top-k values and class indices.
+    // The next batch is fetched into them while the current one is composited.
+    constexpr int KM = KT > 0 ? KT : kMaxK;
+    constexpr int KWM = (KM + 3) / 4;
+    float4 p0 = {}, p1 = {}, p2 = {}, pc = {};
+    float psv[KM];
+    uint32_t psi[KWM];
+    auto fetch = [&](uint32_t f0, int fn) {
+        if (tid < kFwdBatch) {
+            if (tid < fn) {
+                const uint32_t g = a.sgp[f0 + tid];
+                const Proj p = a.srec[g];
+                p0 = p.r0;
+                p1 = p.r1;
+                p2 = p.r2;
+                pc = a.scol[g];
+            }
+        } else if (SEM != 0 && tid - kFwdBatch < fn) {
+            const uint32_t g = a.sgp[f0 + tid - kFwdBatch];
+            const float* sv = a.ssv + (size_t)g * k;
+            if constexpr (KT > 0 && (KT & 3) == 0) {
+#pragma unroll
+                for (int m = 0; m < KM; m += 4) {
+                    const float4 v4 = *(const float4*)(sv + m);
+                    psv[m] = v4.x; psv[m + 1] = v4.y; psv[m + 2] = v4.z; psv[m + 3] = v4.w;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < KM; m++)
+                    if (m < k) psv[m] = sv[m];
+            }
+            const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
+#pragma unroll
+            for (int m = 0; m < KWM; m++)
+                if (m < kw) psi[m] = si[m];
+        }
+    };
+
+    if (start < end) fetch(start, (int)min((uint32_t)kFwdBatch, end - start));
     for (uint32_t b0 = start; b0 < end; b0 += kFwdBatch) {
         if (__builtin_amdgcn_readfirstlane(__syncthreads_count(done)) == kBlock) break;
         const int nb = (int)min((uint32_t)kFwdBatch, end - b0);
         if (tid < kFwdBatch) {
             if (tid < nb) {
-                const uint32_t g = a.sgp[b0 + tid];
-                const Proj p = a.srec[g];
-                s_r0[tid] = p.r0;
-                s_r1[tid] = p.r1;
-                s_r2[tid] = p.r2;
-                s_col[tid] = a.scol[g];
+                s_r0[tid] = p0;
+                s_r1[tid] = p1;
+                s_r2[tid] = p2;
+                s_col[tid] = pc;
             }
         } else if (SEM != 0) {
             const int j = tid - kFwdBatch;
             if (j < nb) {
-                const uint32_t g = a.sgp[b0 + j];
-                const float* sv = a.ssv + (size_t)g * k;
-                for (int m = 0; m < k; m++) s_sv[j * k + m] = sv[m];
-                const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
-                for (int m = 0; m < kw; m++) s_si[j * kw + m] = si[m];
+#pragma unroll
+                for (int m = 0; m < KM; m++)
+                    if (m < k) s_sv[j * k + m] = psv[m];
+#pragma unroll
+                for (int m = 0; m < KWM; m++)
+                    if (m < kw) s_si[j * kw + m] = psi[m];
             }
         }
         __syncthreads();
+        if (b0 + kFwdBatch < end) fetch(b0 + kFwdBatch, (int)min((uint32_t)kFwdBatch, end - b0 - kFwdBatch));
+
+        // Entries whose pixel rectangle meets this wave's block, as two
+        // 64-bit masks (entries lane and 64 + lane).
+        bool h0 = false, h1 = false;
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            const int j = half * 64 + lane;
+            if (j < nb) {
+                const float4 q2 = s_r2[j];
+                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+                const bool h = (int)(rx & 0xffffu) <= wx0 + 7 && (int)(rx >> 16) >= wx0 &&
+                               (int)(ry & 0xffffu) <= wy0 + 7 && (int)(ry >> 16) >= wy0;
+                if (half == 0) h0 = h; else h1 = h;
+            }
+        }
+        uint64_t mlo = __ballot(h0), mhi = __ballot(h1);
         if (!done) {
-            // The next Gaussian's record is loaded before this one's
+            auto next = [&]() -> int {
+                if (mlo) {
+                    const int j = __builtin_ctzll(mlo);
+                    mlo &= mlo - 1;
+                    return j;
+                }
+                if (mhi) {
+                    const int j = 64 + __builtin_ctzll(mhi);
+                    mhi &= mhi - 1;
+                    return j;
+                }
+                return -1;
+            };
+            // The next entry's record is loaded before this one's
             // accumulator updates are issued (records never alias the
-            // accumulators), hiding one LDS round trip per Gaussian.
-            float4 n0 = s_r0[0], n1 = s_r1[0], n2 = s_r2[0];
-            for (int j = 0; j < nb; j++) {
+            // accumulators), hiding one LDS round trip per entry.
+            int jn = next();
+            float4 n0 = {}, n1 = {}, n2 = {};
+            if (jn >= 0) {
+                n0 = s_r0[jn];
+                n1 = s_r1[jn];
+                n2 = s_r2[jn];
+            }
+            while (jn >= 0) {
+                const int j = jn;
                 const float4 q0 = n0, q1 = n1, q2 = n2;
-                if (j + 1 < nb) {
-                    n0 = s_r0[j + 1];
-                    n1 = s_r1[j + 1];
-                    n2 = s_r2[j + 1];
+                jn = next();
+                if (jn >= 0) {
+                    n0 = s_r0[jn];
+                    n1 = s_r1[jn];
+                    n2 = s_r2[jn];
                 }
                 const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
                 if (px < (int)(rx & 0xffffu) || px > (int)(rx >> 16) || py < (int)(ry & 0xffffu) ||
