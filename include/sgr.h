@@ -74,7 +74,13 @@ typedef struct {
     int32_t top_k;                /* k, 1..32 */
     int32_t sem_grad_to_geometry; /* 0: semantic channels do not reach alpha (Sec. 3.1) */
     int32_t tile_w, tile_h;       /* 0 or 16 (the only supported tile) */
+    int32_t sem_accumulators;     /* where the forward and scoring kernels keep the per-pixel
+                                     class sums: SGR_ACC_AUTO (LDS when it fits), SGR_ACC_LDS
+                                     or SGR_ACC_REGISTERS (C <= 128).  A speed choice only:
+                                     every output is bitwise the same. */
 } sgr_config;
+
+enum { SGR_ACC_AUTO = 0, SGR_ACC_LDS = 1, SGR_ACC_REGISTERS = 2 };
 
 typedef struct {
     int64_t n;

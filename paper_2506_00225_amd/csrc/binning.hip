@@ -181,7 +181,9 @@ __global__ __launch_bounds__(256) void compact_visible(const uint32_t* __restric
 
 // Gathers the records of visible pairs in front-to-back order g.  Bit 31 of
 // the record's view word flags a Gaussian whose top-k list repeats a class
-// (the forward then adds its values one at a time).
+// (the LDS-accumulator forward then adds its values one at a time).  The
+// top-k values and classes are stored grouped by accumulator block
+// (grouped_pos); the projection backward undoes the grouping.
 template <int KT>
 __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
     const uint32_t g = blockIdx.x * 256u + threadIdx.x;
@@ -198,15 +200,19 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
     const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
     constexpr int KM = KT > 0 ? KT : kMaxK;
     constexpr int KWM = (KM + 3) / 4;
+    // values and class indices (four per word) of the Gaussian's top-k list
     const float* sv = a.sem_val + i * k;
-    float* dv = a.ssv + (size_t)g * k;
+    float vin[KM];
     if constexpr (KT > 0 && (KT & 3) == 0) {
 #pragma unroll
-        for (int m = 0; m < KT; m += 4) *(float4*)(dv + m) = *(const float4*)(sv + m);
+        for (int m = 0; m < KT; m += 4) {
+            const float4 v4 = *(const float4*)(sv + m);
+            vin[m] = v4.x; vin[m + 1] = v4.y; vin[m + 2] = v4.z; vin[m + 3] = v4.w;
+        }
     } else {
-        for (int m = 0; m < k; m++) dv[m] = sv[m];
+#pragma unroll
+        for (int m = 0; m < KM; m++) vin[m] = m < k ? sv[m] : 0.f;
     }
-    // class indices, four per word
     uint32_t words[KWM];
     const uint8_t* si = a.sem_idx + i * k;
     if constexpr (KT > 0 && (KT & 3) == 0) {
@@ -223,22 +229,59 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
         }
     }
     bool bad = false, dup = false;
+    uint32_t cls[KM], blk[KM];
+#pragma unroll
+    for (int m = 0; m < KM; m++) {
+        cls[m] = 0u;
+        if (m < k) {
+            cls[m] = (words[m >> 2] >> (8 * (m & 3))) & 0xffu;
+            if ((int)cls[m] >= a.C) {  // never index past the class accumulators
+                bad = true;
+                cls[m] = 0u;
+            }
+        }
+        blk[m] = cls[m] / kRegBlock;
+    }
+#pragma unroll
+    for (int m = 0; m < KM; m++)
+#pragma unroll
+        for (int q = 0; q < KM; q++)
+            if (q < m && m < k) dup |= cls[q] == cls[m];
+    // store grouped by accumulator block
+    float vout[KM];
+    uint32_t cout[KM];
+#pragma unroll
+    for (int p = 0; p < KM; p++) {
+        vout[p] = 0.f;
+        cout[p] = 0u;
+    }
 #pragma unroll
     for (int m = 0; m < KM; m++) {
         if (m >= k) break;
-        const uint32_t c = (words[m >> 2] >> (8 * (m & 3))) & 0xffu;
-        if ((int)c >= a.C) {  // never index past the class accumulators
-            bad = true;
-            words[m >> 2] &= ~(0xffu << (8 * (m & 3)));
-        }
+        const int pos = grouped_pos<KM>(blk, k, m);
 #pragma unroll
-        for (int q = 0; q < KM; q++)
-            if (q < m) dup |= ((words[q >> 2] >> (8 * (q & 3))) & 0xffu) == ((words[m >> 2] >> (8 * (m & 3))) & 0xffu);
+        for (int p = 0; p < KM; p++)
+            if (p == pos) {
+                vout[p] = vin[m];
+                cout[p] = cls[m];
+            }
+    }
+    float* dv = a.ssv + (size_t)g * k;
+    if constexpr (KT > 0 && (KT & 3) == 0) {
+#pragma unroll
+        for (int m = 0; m < KT; m += 4) *(float4*)(dv + m) = make_float4(vout[m], vout[m + 1], vout[m + 2], vout[m + 3]);
+    } else {
+        for (int m = 0; m < k; m++) dv[m] = vout[m];
     }
     uint32_t* di = (uint32_t*)(a.ssi + (size_t)g * a.kpad);
 #pragma unroll
-    for (int w = 0; w < KWM; w++)
-        if (w < kw) di[w] = words[w];
+    for (int w = 0; w < KWM; w++) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            if (4 * w + b < KM) word |= cout[4 * w + b] << (8 * b);
+        if (w < kw) di[w] = word;
+    }
     if (bad) atomicOr(&a.counters[kStatus], Plan::kBadIndex);
     p.r2.w = __uint_as_float(__float_as_uint(p.r2.w) | (dup ? 0x80000000u : 0u));
     a.srec[g] = p;

@@ -452,8 +452,9 @@ struct ProjBwdArgs {
     const float *means, *scales, *quats, *opacity;
     const ViewDev* views;
     int64_t n;
-    int V, k, NV;
+    int V, k, NV, C;
     float lowpass;
+    const uint8_t* sem_idx;    // [n][k], to undo the block grouping of the semantic values
     const uint32_t* gp_of_lin;
     const float* g2d;
     const uint32_t* counters;
@@ -569,9 +570,24 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
     if (a.d_opacity) a.d_opacity[i] = go;
     if (a.d_rgb) for (int c = 0; c < 3; c++) a.d_rgb[3 * i + c] = grgb[c];
     if (a.d_sem) {
+        // slot values are in grouped order: entry m sits at grouped_pos(m)
+        uint32_t blk[KM];
 #pragma unroll
-        for (int m = 0; m < KM; m++)
-            if (m < k) a.d_sem[i * k + m] = gsem[m];
+        for (int m = 0; m < KM; m++) {
+            uint32_t c = m < k ? (uint32_t)a.sem_idx[i * k + m] : 0u;
+            if ((int)c >= a.C) c = 0u;
+            blk[m] = c / kRegBlock;
+        }
+#pragma unroll
+        for (int m = 0; m < KM; m++) {
+            if (m >= k) break;
+            const int pos = grouped_pos<KM>(blk, k, m);
+            float gv = 0.f;
+#pragma unroll
+            for (int p = 0; p < KM; p++)
+                if (p == pos) gv = gsem[p];
+            a.d_sem[i * k + m] = gv;
+        }
     }
 }
 
@@ -637,7 +653,8 @@ sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const s
     ProjBwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opacity = g->opacity;
     pa.views = (const ViewDev*)(ws + P.views);
-    pa.n = P.n; pa.V = P.V; pa.k = P.k; pa.NV = nvals;
+    pa.n = P.n; pa.V = P.V; pa.k = P.k; pa.NV = nvals; pa.C = P.C;
+    pa.sem_idx = g->sem_idx;
     pa.lowpass = P.cfg.lowpass;
     pa.gp_of_lin = (const uint32_t*)(ws + P.gp_of_lin);
     pa.g2d = (const float*)(ws + P.g2d);

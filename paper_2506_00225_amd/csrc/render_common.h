@@ -13,6 +13,66 @@ constexpr size_t kMaxLds = 160 * 1024;
 // follows it stays 16-byte aligned.
 __host__ __device__ inline int acc_floats(int C) { return (C * kAccStride + 3) & ~3; }
 
+// Semantic accumulators held in registers: NB vectors of 32 classes.  A
+// class index is wave-uniform during a blend (every lane composites the same
+// Gaussian), so an update is a uniform-indexed register read-modify-write.
+typedef float v32f __attribute__((ext_vector_type(32)));
+// References to the kernel's own vector variables (an aggregate of vectors
+// would be placed in scratch memory): blocks past NB are never touched.
+template <int NB>
+struct RegAcc {
+    v32f &a0, &a1, &a2, &a3;
+};
+
+// The entries of block B (classes 32 B .. 32 B + 31) from position m on.
+template <int B, int KM, int KWM>
+__device__ __forceinline__ void acc_run(v32f& acc, const float (&vv)[KM], const uint32_t (&wd)[KWM], int k, float w,
+                                        int& m) {
+    while (m < k) {
+        const uint32_t c = (wd[m >> 2] >> (8 * (m & 3))) & 0xffu;
+        if ((int)(c / kRegBlock) != B) break;
+        acc[c % kRegBlock] = fmaf(vv[m], w, acc[c % kRegBlock]);
+        m++;
+    }
+}
+
+// acc[class] += v_m * w for the k entries of one Gaussian, stored grouped by
+// block (class / 32): the entries of a block are consecutive, so each block
+// is one uniform loop over one register vector.  sv: the k values (LDS),
+// wd: the class bytes, four per word, in scalar registers.
+template <int NB, int KT, int KM, int KWM>
+__device__ __forceinline__ void reg_accumulate(RegAcc<NB>& A, const float* sv, const uint32_t (&wd)[KWM], int k,
+                                               float w) {
+    float vv[KM];
+    if constexpr (KT > 0 && (KT & 3) == 0) {  // 16-byte aligned rows of KT values
+#pragma unroll
+        for (int m = 0; m < KM; m += 4) {
+            const float4 v4 = *(const float4*)(sv + m);
+            vv[m] = v4.x; vv[m + 1] = v4.y; vv[m + 2] = v4.z; vv[m + 3] = v4.w;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < KM; m++) vv[m] = m < k ? sv[m] : 0.f;
+    }
+    // The trip counts are hidden from the optimiser: unrolled, the block
+    // loops' exits would merge copies of whole vectors.
+    int kk = k;
+    asm volatile("" : "+s"(kk));
+    int m = 0;
+    acc_run<0>(A.a0, vv, wd, kk, w, m);
+    if constexpr (NB > 1) acc_run<1>(A.a1, vv, wd, kk, w, m);
+    if constexpr (NB > 2) acc_run<2>(A.a2, vv, wd, kk, w, m);
+    if constexpr (NB > 3) acc_run<3>(A.a3, vv, wd, kk, w, m);
+}
+
+template <int NB>
+__device__ __forceinline__ void reg_zero(RegAcc<NB>& A) {
+    A.a0 = 0.f;
+    if constexpr (NB > 1) A.a1 = 0.f;
+    if constexpr (NB > 2) A.a2 = 0.f;
+    if constexpr (NB > 3) A.a3 = 0.f;
+}
+
 struct MapPtrs {
     float *rgb, *depth, *sil, *sem, *t_final;
     int32_t* n_contrib;

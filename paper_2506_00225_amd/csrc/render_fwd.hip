@@ -7,11 +7,18 @@ namespace sgr {
 
 // Per-tile compositing.  One thread per pixel (256 = 4 wave64).  Batches of
 // the tile's front-to-back list are staged in LDS; every lane reads the
-// same record (an LDS broadcast).  Semantic accumulators live in LDS,
-// class-major with a 257-float stride: the 64 lanes of a wave update 64
-// consecutive floats of one class row, which is conflict-free.
-template <int KT, int SEM>
-__device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float* smem, TileResult& res) {
+// same record (an LDS broadcast).  Semantic accumulators (SEM):
+//   0  none;
+//   1  LDS, class-major with a 257-float stride: the 64 lanes of a wave
+//      update 64 consecutive floats of one class row, conflict-free;
+//   2  the thread's own row of the output map (when LDS is too small);
+//   3  registers, NB vectors of 32 classes (C <= 128): no LDS, so more
+//      waves fit on a CU.
+// Every mode adds a blend's values in the same order with the same fused
+// multiply-add, so they give the same bits.
+template <int KT, int SEM, int NB>
+__device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float* smem, TileResult& res,
+                                               RegAcc<NB>& racc) {
     const int tid = threadIdx.x;
     const int k = KT > 0 ? KT : a.k;
     const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;  // index words per Gaussian
@@ -36,6 +43,7 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
 
     if (SEM == 1)
         for (int i = tid; i < C * kAccStride; i += kBlock) acc[i] = 0.f;
+    if constexpr (SEM == 3) reg_zero(racc);
     float* gacc = nullptr;  // SEM == 2: the thread's own row of the output map
     if (SEM == 2 && inside && a.maps[v].sem) {
         gacc = a.maps[v].sem + ((int64_t)py * vw.width + px) * C;
@@ -55,18 +63,25 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     // The next batch is fetched into them while the current one is composited.
     constexpr int KM = KT > 0 ? KT : kMaxK;
     constexpr int KWM = (KM + 3) / 4;
-    float4 p0 = {}, p1 = {}, p2 = {}, pc = {};
-    float psv[KM];
-    uint32_t psi[KWM];
+    // One register array serves both roles (record: r0, r1, r2, colour as
+    // 16 words; semantics: KM values then KWM index words).
+    constexpr int KSTG = (KM + KWM) > 16 ? (KM + KWM) : 16;
+    uint32_t stg[KSTG];
+#pragma unroll
+    for (int q = 0; q < KSTG; q++) stg[q] = 0u;
     auto fetch = [&](uint32_t f0, int fn) {
         if (tid < kFwdBatch) {
             if (tid < fn) {
                 const uint32_t g = a.sgp[f0 + tid];
-                const Proj p = a.srec[g];
-                p0 = p.r0;
-                p1 = p.r1;
-                p2 = p.r2;
-                pc = a.scol[g];
+                const float4* rp = (const float4*)(a.srec + g);
+                const float4 r[4] = {rp[0], rp[1], rp[2], a.scol[g]};
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    stg[4 * q] = __float_as_uint(r[q].x);
+                    stg[4 * q + 1] = __float_as_uint(r[q].y);
+                    stg[4 * q + 2] = __float_as_uint(r[q].z);
+                    stg[4 * q + 3] = __float_as_uint(r[q].w);
+                }
             }
         } else if (SEM != 0 && tid - kFwdBatch < fn) {
             const uint32_t g = a.sgp[f0 + tid - kFwdBatch];
@@ -75,17 +90,20 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
 #pragma unroll
                 for (int m = 0; m < KM; m += 4) {
                     const float4 v4 = *(const float4*)(sv + m);
-                    psv[m] = v4.x; psv[m + 1] = v4.y; psv[m + 2] = v4.z; psv[m + 3] = v4.w;
+                    stg[m] = __float_as_uint(v4.x);
+                    stg[m + 1] = __float_as_uint(v4.y);
+                    stg[m + 2] = __float_as_uint(v4.z);
+                    stg[m + 3] = __float_as_uint(v4.w);
                 }
             } else {
 #pragma unroll
                 for (int m = 0; m < KM; m++)
-                    if (m < k) psv[m] = sv[m];
+                    if (m < k) stg[m] = __float_as_uint(sv[m]);
             }
             const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
 #pragma unroll
             for (int m = 0; m < KWM; m++)
-                if (m < kw) psi[m] = si[m];
+                if (m < kw) stg[KM + m] = si[m];
         }
     };
 
@@ -95,20 +113,24 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
         const int nb = (int)min((uint32_t)kFwdBatch, end - b0);
         if (tid < kFwdBatch) {
             if (tid < nb) {
-                s_r0[tid] = p0;
-                s_r1[tid] = p1;
-                s_r2[tid] = p2;
-                s_col[tid] = pc;
+                s_r0[tid] = make_float4(__uint_as_float(stg[0]), __uint_as_float(stg[1]), __uint_as_float(stg[2]),
+                                        __uint_as_float(stg[3]));
+                s_r1[tid] = make_float4(__uint_as_float(stg[4]), __uint_as_float(stg[5]), __uint_as_float(stg[6]),
+                                        __uint_as_float(stg[7]));
+                s_r2[tid] = make_float4(__uint_as_float(stg[8]), __uint_as_float(stg[9]), __uint_as_float(stg[10]),
+                                        __uint_as_float(stg[11]));
+                s_col[tid] = make_float4(__uint_as_float(stg[12]), __uint_as_float(stg[13]),
+                                         __uint_as_float(stg[14]), __uint_as_float(stg[15]));
             }
         } else if (SEM != 0) {
             const int j = tid - kFwdBatch;
             if (j < nb) {
 #pragma unroll
                 for (int m = 0; m < KM; m++)
-                    if (m < k) s_sv[j * k + m] = psv[m];
+                    if (m < k) s_sv[j * k + m] = __uint_as_float(stg[m]);
 #pragma unroll
                 for (int m = 0; m < KWM; m++)
-                    if (m < kw) s_si[j * kw + m] = psi[m];
+                    if (m < kw) s_si[j * kw + m] = stg[KM + m];
             }
         }
         __syncthreads();
@@ -129,20 +151,68 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
             }
         }
         uint64_t mlo = __ballot(h0), mhi = __ballot(h1);
-        if (!done) {
-            auto next = [&]() -> int {
-                if (mlo) {
-                    const int j = __builtin_ctzll(mlo);
-                    mlo &= mlo - 1;
-                    return j;
+        auto next = [&]() -> int {
+            if (mlo) {
+                const int j = __builtin_ctzll(mlo);
+                mlo &= mlo - 1;
+                return j;
+            }
+            if (mhi) {
+                const int j = 64 + __builtin_ctzll(mhi);
+                mhi &= mhi - 1;
+                return j;
+            }
+            return -1;
+        };
+        if constexpr (SEM == 3) {
+            // Uniform control flow: every lane takes every entry of the wave's
+            // mask, with w = 0 where it does not blend (a no-op update), so the
+            // register vectors are only ever updated in straight-line code.
+            if (__ballot(!done) == 0) continue;
+            int jn = next();
+            float4 n0 = {}, n1 = {}, n2 = {};
+            if (jn >= 0) {
+                n0 = s_r0[jn];
+                n1 = s_r1[jn];
+                n2 = s_r2[jn];
+            }
+            while (jn >= 0) {
+                const int j = jn;
+                const float4 q0 = n0, q1 = n1, q2 = n2;
+                jn = next();
+                if (jn >= 0) {
+                    n0 = s_r0[jn];
+                    n1 = s_r1[jn];
+                    n2 = s_r2[jn];
                 }
-                if (mhi) {
-                    const int j = 64 + __builtin_ctzll(mhi);
-                    mhi &= mhi - 1;
-                    return j;
-                }
-                return -1;
-            };
+                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+                const bool inr = !done && px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) &&
+                                 py >= (int)(ry & 0xffffu) && py <= (int)(ry >> 16);
+                float G, dx, dy;
+                const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
+                const bool pass = inr && alpha >= amin;
+                const float Tn = T * (1.f - alpha);
+                const bool blend = pass && !(Tn < tmin);
+                done = done || (pass && Tn < tmin);
+                const float w = blend ? alpha * T : 0.f;
+                const float4 col = s_col[j];
+                cr = fmaf(col.x, w, cr);
+                cg = fmaf(col.y, w, cg);
+                cb = fmaf(col.z, w, cb);
+                dd = fmaf(col.w, w, dd);
+                ss += w;
+                const float* sv = s_sv + j * k;
+                const uint32_t* si = s_si + j * kw;
+                uint32_t wd[KWM];
+#pragma unroll
+                for (int q = 0; q < KWM; q++) wd[q] = q < kw ? __builtin_amdgcn_readfirstlane(si[q]) : 0u;
+                reg_accumulate<NB, KT, KM, KWM>(racc, sv, wd, k, w);
+                T = blend ? Tn : T;
+                ncon += blend ? 1 : 0;
+                last = blend ? b0 + j + 1 : last;
+                if (__ballot(!done) == 0) break;
+            }
+        } else if (!done) {
             // The next entry's record is loaded before this one's
             // accumulator updates are issued (records never alias the
             // accumulators), hiding one LDS round trip per entry.
@@ -176,16 +246,17 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                 }
                 const float w = alpha * T;
                 const float4 col = s_col[j];
-                cr += col.x * w;
-                cg += col.y * w;
-                cb += col.z * w;
-                dd += col.w * w;
+                cr = fmaf(col.x, w, cr);
+                cg = fmaf(col.y, w, cg);
+                cb = fmaf(col.z, w, cb);
+                dd = fmaf(col.w, w, dd);
                 ss += w;
                 if (SEM != 0) {
                     const float* sv = s_sv + j * k;
                     const uint32_t* si = s_si + j * kw;
                     const bool dup = (__float_as_uint(q2.w) >> 31) != 0u;
-                    if (KT > 0 && SEM == 1 && !dup) {
+                    if (false) {
+                    } else if (KT > 0 && SEM == 1 && !dup) {
                         // distinct classes: all reads, then all updates
                         constexpr int KK = KT > 0 ? KT : 1;
                         float vals[KK];
@@ -217,8 +288,8 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                                 const int m = mw * 4 + b;
                                 if (m < k) {
                                     const uint32_t cl = (word >> (8 * b)) & 0xffu;
-                                    if (SEM == 1) acc[cl * kAccStride + tid] += sv[m] * w;
-                                    else if (gacc) gacc[cl] += sv[m] * w;
+                                    if (SEM == 1) acc[cl * kAccStride + tid] = fmaf(sv[m], w, acc[cl * kAccStride + tid]);
+                                    else if (gacc) gacc[cl] = fmaf(sv[m], w, gacc[cl]);
                                 }
                             }
                         }
@@ -244,14 +315,48 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     res.s = ss;
 }
 
-template <int KT, int SEM>
+// Classes 32 B .. 32 B + 31 of a wave's 8x8 pixel block to the [H][W][C]
+// map through the wave's 64 x 33 LDS buffer: lane l stores its pixel's 32
+// sums, then each store instruction covers four pixels' runs of 32 classes
+// (16 lanes x 2 floats each) instead of 64 scattered floats.  Same-wave LDS
+// accesses complete in order, so no barrier is needed.
+template <int B>
+__device__ __forceinline__ void write_sem_block(const v32f& acc, float* buf, float* out, const ViewDev& vw, int C,
+                                                bool pairs, int wx0, int wy0, int lane) {
+#pragma unroll
+    for (int c = 0; c < kRegBlock; c++) buf[lane * 33 + c] = acc[c];
+    for (int rr = 0; rr < 16; rr++) {
+        const int p = rr * 4 + (lane >> 4);
+        const int c2 = (lane & 15) * 2;
+        const int cls = B * kRegBlock + c2;
+        const int x = wx0 + (p & 7), y = wy0 + (p >> 3);
+        if (x < vw.width && y < vw.height && cls < C) {
+            float* dst = out + ((int64_t)y * vw.width + x) * C + cls;
+            const float v0 = buf[p * 33 + c2], v1 = buf[p * 33 + c2 + 1];
+            if (cls + 1 < C) {
+                if (pairs) {
+                    *(float2*)dst = make_float2(v0, v1);
+                } else {
+                    dst[0] = v0;
+                    dst[1] = v1;
+                }
+            } else {
+                dst[0] = v0;
+            }
+        }
+    }
+}
+
+template <int KT, int SEM, int NB>
 __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
     extern __shared__ __align__(16) float smem[];
     const int gt = xcd_remap(blockIdx.x, gridDim.x);
     if (gt >= a.num_tiles) return;
     if (a.counters[kStatus] & SGR_ECAPACITY) return;
     TileResult r;
-    composite_tile<KT, SEM>(a, gt, smem, r);
+    v32f acc0, acc1, acc2, acc3;
+    RegAcc<NB> racc{acc0, acc1, acc2, acc3};
+    composite_tile<KT, SEM, NB>(a, gt, smem, r, racc);
     const ViewDev& vw = a.views[r.v];
     if (r.inside) {
         const int64_t pix = (int64_t)r.py * vw.width + r.px;
@@ -284,6 +389,23 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
             }
         }
     }
+    if (SEM == 3) {
+        // Each wave writes its 8x8 block, 32 classes at a time, through a
+        // 64 x 33 LDS transpose: one store then covers four pixels' runs of
+        // 32 classes instead of 64 scattered floats.
+        float* out = a.maps[r.v].sem;
+        if (!out) return;
+        __syncthreads();  // the staging area becomes the transpose buffers
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        float* buf = smem + wv * (64 * 33);
+        const int C = a.C;
+        const bool pairs = (C & 1) == 0 && ((uintptr_t)out & 7u) == 0;  // 8-byte aligned class pairs
+        const int wx0 = r.tx * kTile + (wv & 1) * 8, wy0 = r.ty * kTile + (wv >> 1) * 8;
+        write_sem_block<0>(racc.a0, buf, out, vw, C, pairs, wx0, wy0, lane);
+        if constexpr (NB > 1) write_sem_block<1>(racc.a1, buf, out, vw, C, pairs, wx0, wy0, lane);
+        if constexpr (NB > 2) write_sem_block<2>(racc.a2, buf, out, vw, C, pairs, wx0, wy0, lane);
+        if constexpr (NB > 3) write_sem_block<3>(racc.a3, buf, out, vw, C, pairs, wx0, wy0, lane);
+    }
 }
 
 // ------------------------------------------------------------------ scoring
@@ -297,7 +419,22 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
 // (FP64), so the scores are deterministic.  The loop bounds depend only on
 // blockIdx and the grid, so every lane of every wave takes the same trip
 // count through the barriers.
-template <int KT>
+// Z += x and sxl += x log2 x over classes 32 B .. 32 B + 31 (those < C), with
+// x the class sum clipped to [0.001, 1], in class order.
+template <int B>
+__device__ __forceinline__ void entropy_terms(const v32f& acc, int C, float lg_lo, float& Z, float& sxl) {
+#pragma unroll
+    for (int c = 0; c < kRegBlock; c++) {
+        if (B * kRegBlock + c < C) {
+            const float x = fminf(fmaxf(acc[c], 0.001f), 1.f);
+            const float lx = (x == 0.001f) ? lg_lo : __log2f(x);
+            Z += x;
+            sxl += x * lx;
+        }
+    }
+}
+
+template <int KT, int SEM, int NB>
 __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, ScoreOut so) {
     extern __shared__ __align__(16) float smem[];
     __shared__ double s_h[4];
@@ -316,16 +453,25 @@ __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, Sc
         const int gt = (item & 7) * per + (item >> 3);
         if (gt >= T) continue;
         TileResult r;
-        composite_tile<KT, 1>(a, gt, smem, r);
+        v32f acc0, acc1, acc2, acc3;
+        RegAcc<NB> racc{acc0, acc1, acc2, acc3};
+        composite_tile<KT, SEM, NB>(a, gt, smem, r, racc);
         __syncthreads();
         double h = 0.0;
         if (r.inside) {
             float Z = 0.f, sxl = 0.f;
-            for (int c = 0; c < C; c++) {
-                const float x = fminf(fmaxf(smem[c * kAccStride + tid], 0.001f), 1.f);
-                const float lx = (x == 0.001f) ? lg_lo : __log2f(x);
-                Z += x;
-                sxl += x * lx;
+            if constexpr (SEM == 3) {
+                entropy_terms<0>(racc.a0, C, lg_lo, Z, sxl);
+                if constexpr (NB > 1) entropy_terms<1>(racc.a1, C, lg_lo, Z, sxl);
+                if constexpr (NB > 2) entropy_terms<2>(racc.a2, C, lg_lo, Z, sxl);
+                if constexpr (NB > 3) entropy_terms<3>(racc.a3, C, lg_lo, Z, sxl);
+            } else {
+                for (int c = 0; c < C; c++) {
+                    const float x = fminf(fmaxf(smem[c * kAccStride + tid], 0.001f), 1.f);
+                    const float lx = (x == 0.001f) ? lg_lo : __log2f(x);
+                    Z += x;
+                    sxl += x * lx;
+                }
             }
             h = (double)(ln2 * (__log2f(Z) - sxl / Z));
         }
@@ -426,15 +572,26 @@ static void set_lds(K kernel, size_t bytes) {
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// LDS of a forward launch: the staging area, plus the class-major
+// accumulators (mode 1) or, for mode 3, room for the four waves' 64 x 33
+// transpose buffers that reuse the staging area at the end.
 size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode) {
     size_t b = (size_t)kFwdBatch * (4 * sizeof(float4) + k * sizeof(float) + kpad);
     if (sem_mode == 1) b += (size_t)acc_floats(C) * sizeof(float);
+    if (sem_mode == 3) b = std::max(b, (size_t)4 * 64 * 33 * sizeof(float));
     return b;
 }
 
+// 0: no semantics; 1: LDS accumulators; 2: accumulate into the output map;
+// 3: register accumulators.  Automatic placement prefers LDS, which measures
+// faster on gfx950 at C = 102 (a register update costs four VALU operations
+// and a scalar index decode against two VALU and two LDS operations).
 static int sem_mode_for(const Plan& P, bool want_sem) {
     if (!want_sem) return 0;
-    return fwd_lds_bytes(P.C, P.k, P.kpad, 1) <= device_max_lds() ? 1 : 2;
+    const int acc = P.cfg.sem_accumulators;
+    if (acc == SGR_ACC_REGISTERS) return 3;
+    if (fwd_lds_bytes(P.C, P.k, P.kpad, 1) <= device_max_lds()) return 1;
+    return (acc == SGR_ACC_AUTO && P.C <= kMaxRegC) ? 3 : 2;
 }
 
 TileArgs make_tile_args(const Plan& P, char* ws) {
@@ -461,18 +618,21 @@ TileArgs make_tile_args(const Plan& P, char* ws) {
     return a;
 }
 
+template <int KT, int SEM, int NB>
+static void fwd_launch(const TileArgs& a, unsigned grid, size_t lds, hipStream_t st) {
+    set_lds(render_fwd_kernel<KT, SEM, NB>, lds);
+    render_fwd_kernel<KT, SEM, NB><<<grid, kBlock, lds, st>>>(a);
+}
+
 template <int KT>
-static void fwd_dispatch_sem(int sem, const TileArgs& a, unsigned grid, size_t lds, hipStream_t st) {
-    if (sem == 0) {
-        set_lds(render_fwd_kernel<KT, 0>, lds);
-        render_fwd_kernel<KT, 0><<<grid, kBlock, lds, st>>>(a);
-    } else if (sem == 1) {
-        set_lds(render_fwd_kernel<KT, 1>, lds);
-        render_fwd_kernel<KT, 1><<<grid, kBlock, lds, st>>>(a);
-    } else {
-        set_lds(render_fwd_kernel<KT, 2>, lds);
-        render_fwd_kernel<KT, 2><<<grid, kBlock, lds, st>>>(a);
-    }
+static void fwd_dispatch_sem(int sem, int nb, const TileArgs& a, unsigned grid, size_t lds, hipStream_t st) {
+    if (sem == 0) fwd_launch<KT, 0, 1>(a, grid, lds, st);
+    else if (sem == 1) fwd_launch<KT, 1, 1>(a, grid, lds, st);
+    else if (sem == 2) fwd_launch<KT, 2, 1>(a, grid, lds, st);
+    else if (nb == 1) fwd_launch<KT, 3, 1>(a, grid, lds, st);
+    else if (nb == 2) fwd_launch<KT, 3, 2>(a, grid, lds, st);
+    else if (nb == 3) fwd_launch<KT, 3, 3>(a, grid, lds, st);
+    else fwd_launch<KT, 3, 4>(a, grid, lds, st);
 }
 
 sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStream_t st) {
@@ -486,11 +646,32 @@ sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStrea
     upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
     a.maps = (const MapPtrs*)(ws + P.map_table);
     const int sem = sem_mode_for(P, want_sem);
+    const int nb = (P.C + kRegBlock - 1) / kRegBlock;
     const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, sem);
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
-    if (P.k == 16) fwd_dispatch_sem<16>(sem, a, grid, lds, st);
-    else if (P.k == 3) fwd_dispatch_sem<3>(sem, a, grid, lds, st);
-    else fwd_dispatch_sem<0>(sem, a, grid, lds, st);
+    if (P.k == 16) fwd_dispatch_sem<16>(sem, nb, a, grid, lds, st);
+    else if (P.k == 3) fwd_dispatch_sem<3>(sem, nb, a, grid, lds, st);
+    else fwd_dispatch_sem<0>(sem, nb, a, grid, lds, st);
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+// A persistent grid of as many workgroups as fit on the device at once.
+template <int KT, int SEM, int NB>
+static sgr_status score_launch(const Plan& P, const TileArgs& a, const ScoreOut& so, size_t lds, hipStream_t st) {
+    set_lds(score_persistent_kernel<KT, SEM, NB>, lds);
+    static int per_cu = 0;  // per instantiation; the dynamic LDS size is fixed by C and k
+    static size_t per_cu_lds = 0;
+    if (per_cu == 0 || per_cu_lds != lds) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, score_persistent_kernel<KT, SEM, NB>, kBlock, lds) !=
+            hipSuccess)
+            return SGR_EHIP;
+        per_cu = std::max(1, n);
+        per_cu_lds = lds;
+    }
+    const int64_t want = std::min<int64_t>(P.num_tiles, (int64_t)device_cu_count() * per_cu);
+    const unsigned grid = (unsigned)(div_up(want, 8) * 8);
+    score_persistent_kernel<KT, SEM, NB><<<grid, kBlock, lds, st>>>(a, so);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }
 
@@ -501,19 +682,22 @@ sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, c
     so.tile_e = (uint32_t*)(ws + P.tile_part + sizeof(double) * P.num_tiles);
     so.n_empty = n_empty;
     so.entropy_sum = entropy_sum;
-    const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, 1);
+    const int sem = sem_mode_for(P, true) == 3 ? 3 : 1;
+    const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, sem == 3 ? 0 : 1);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
-    const int per_cu = std::max<int>(1, (int)(device_max_lds() / (lds + 4096)));
-    const int64_t want = std::min<int64_t>(P.num_tiles, (int64_t)device_cu_count() * per_cu);
-    const unsigned grid = (unsigned)(div_up(want, 8) * 8);
+    const int nb = (P.C + kRegBlock - 1) / kRegBlock;
     if (P.k == 16) {
-        set_lds(score_persistent_kernel<16>, lds);
-        score_persistent_kernel<16><<<grid, kBlock, lds, st>>>(a, so);
-    } else {
-        set_lds(score_persistent_kernel<0>, lds);
-        score_persistent_kernel<0><<<grid, kBlock, lds, st>>>(a, so);
+        if (sem == 1) return score_launch<16, 1, 1>(P, a, so, lds, st);
+        if (nb == 1) return score_launch<16, 3, 1>(P, a, so, lds, st);
+        if (nb == 2) return score_launch<16, 3, 2>(P, a, so, lds, st);
+        if (nb == 3) return score_launch<16, 3, 3>(P, a, so, lds, st);
+        return score_launch<16, 3, 4>(P, a, so, lds, st);
     }
-    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+    if (sem == 1) return score_launch<0, 1, 1>(P, a, so, lds, st);
+    if (nb == 1) return score_launch<0, 3, 1>(P, a, so, lds, st);
+    if (nb == 2) return score_launch<0, 3, 2>(P, a, so, lds, st);
+    if (nb == 3) return score_launch<0, 3, 3>(P, a, so, lds, st);
+    return score_launch<0, 3, 4>(P, a, so, lds, st);
 }
 
 sgr_status launch_score_maps(const float* sem, const int32_t* n_contrib, int W, int H, int C, uint32_t* n_empty,

@@ -14,6 +14,21 @@ constexpr int kMaxK = 32;          // top-k limit
 constexpr int kMaxC = 256;         // class limit (u8 indices)
 constexpr int kAccStride = 257;    // LDS class-major stride: conflict-free for consecutive pixels
 constexpr uint32_t kInvalid = 0xffffffffu;
+constexpr int kRegBlock = 32;      // classes per register accumulator vector
+constexpr int kMaxRegC = 128;      // classes that fit the register accumulators (4 vectors)
+
+// Top-k entries are stored grouped by accumulator block (class / 32), in
+// their original order inside a block, so a compositing kernel can walk a
+// Gaussian's classes one register vector at a time.  grouped_pos gives the
+// stored position of entry m; blk[] holds class / 32 of every entry.
+template <int KM>
+__device__ __forceinline__ int grouped_pos(const uint32_t (&blk)[KM], int k, int m) {
+    int p = 0;
+#pragma unroll
+    for (int q = 0; q < KM; q++)
+        if (q < k) p += (blk[q] < blk[m] || (blk[q] == blk[m] && q < m)) ? 1 : 0;
+    return p;
+}
 
 // counters[] slots at the start of the workspace
 enum Counter : int {

@@ -17,11 +17,14 @@ from . import _lib as L
 DEFAULTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, z_near=0.2, lowpass=0.3)
 
 
-def make_config(num_classes: int, top_k: int, sem_grad_to_geometry: int = 0, **kw) -> L.sgr_config:
+def make_config(num_classes: int, top_k: int, sem_grad_to_geometry: int = 0, sem_accumulators: int = 0,
+                **kw) -> L.sgr_config:
+    """sem_accumulators: 0 automatic, 1 LDS, 2 registers (C <= 128); the
+    choice changes speed only, not the bits of any output."""
     d = dict(DEFAULTS)
     d.update(kw)
     return L.sgr_config(d["alpha_min"], d["alpha_max"], d["t_min"], d["z_near"], d["lowpass"], int(num_classes),
-                        int(top_k), int(sem_grad_to_geometry), 16, 16)
+                        int(top_k), int(sem_grad_to_geometry), 16, 16, int(sem_accumulators))
 
 
 def camera_array(cams):

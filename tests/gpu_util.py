@@ -8,9 +8,9 @@ from paper_2506_00225_amd import Frame, Gaussians, make_config
 LN2 = 0.6931471805599453
 
 
-def frame_for(sc, cams=None, cap=None, semgeo=0, lowpass=None):
+def frame_for(sc, cams=None, cap=None, semgeo=0, lowpass=None, acc=0):
     kw = {} if lowpass is None else {"lowpass": lowpass}
-    cfg = make_config(sc.num_classes, sc.k, sem_grad_to_geometry=semgeo, **kw)
+    cfg = make_config(sc.num_classes, sc.k, sem_grad_to_geometry=semgeo, sem_accumulators=acc, **kw)
     cams = sc.cameras if cams is None else cams
     return Frame(sc.n, cams, cfg, key_capacity=cap, device="cuda")
 

@@ -96,6 +96,19 @@ def test_unsupported_tile(L):
     assert e.value.status == L.SGR_EUNSUPPORTED
 
 
+def test_accumulator_placement_validated(L):
+    cfg = _cfg(C=130, k=3)
+    cfg.sem_accumulators = L.SGR_ACC_REGISTERS  # 130 classes exceed the register accumulators
+    with pytest.raises(L.SgrError) as e:
+        L.sgr_workspace_layout(10, _cams(_cam()), 1, cfg, 100)
+    assert e.value.status == L.SGR_EUNSUPPORTED
+    cfg.sem_accumulators = 3
+    assert L.sgr_workspace_size(10, _cams(_cam()), 1, cfg, 100) == 0
+    for acc in (L.SGR_ACC_AUTO, L.SGR_ACC_LDS):
+        cfg.sem_accumulators = acc
+        assert L.sgr_workspace_size(10, _cams(_cam()), 1, cfg, 100) > 0
+
+
 def test_calls_validate_before_any_device_work(L):
     """Bad workspace or pointers come back as SGR_EINVAL from the host layer
     (these calls never reach HIP, so they run without a GPU)."""

@@ -339,16 +339,60 @@ def test_score_views_vs_oracle_and_plain_path():
         assert abs(float(ph[0]) - hs[v]) <= 1e-9 * P
 
 
-def test_duplicate_top_k_classes_add():
+@pytest.mark.parametrize("acc", [1, 2])
+def test_duplicate_top_k_classes_add(acc):
     """Repeated class indices within a Gaussian's top-k add (Eq. 3 with
-    p_{i,m} the sum of its entries); checked against the oracle."""
-    _say("duplicate classes")
+    p_{i,m} the sum of its entries); checked against the oracle with the
+    class sums in LDS (1) and in registers (2)."""
+    _say("duplicate classes", acc)
     sc = scenes.tiny_scene(seed=9)
     rng = np.random.default_rng(3)
     dup = rng.random(sc.n) < 0.3
     sc.sem_idx[dup, 1] = sc.sem_idx[dup, 0]
-    _, got, _, want = _forward_case(sc)
+    fr = U.frame_for(sc, acc=acc)
+    g = Gaussians.from_scene(sc)
+    fr.prepare(g)
+    maps = fr.forward(g)
+    torch.cuda.synchronize()
+    got = {k: fr.split(v)[0].cpu().numpy() for k, v in maps.items()}
+    _, want = O.forward(O.scene_arrays(sc), sc.cameras[0], U.oracle_cfg(), sc.num_classes)
     U.compare_maps(got, want, want["flags"])
+
+
+@pytest.mark.parametrize("case", ["tiny_c16", "room_c102", "tiny_c110"])
+def test_accumulator_placements_give_identical_bits(case):
+    """Class sums in LDS and in registers (the autotuner's choice) give the
+    same bits for maps, gradients and scores (C = 110 fills the fourth
+    register vector almost to the end)."""
+    _say("accumulators", case)
+    if case == "tiny_c16":
+        sc = scenes.tiny_scene(seed=11)
+    elif case == "tiny_c110":
+        sc = scenes.tiny_scene(seed=12, num_classes=110, k=16)
+    else:
+        sc = _room_crop(n=60_000, w=400, h=300)
+    g = Gaussians.from_scene(sc)
+    cam = sc.cameras[0]
+    P = cam.width * cam.height
+    rng = np.random.default_rng(5)
+    dl = {k: torch.from_numpy(v).cuda().reshape(P, -1).squeeze(-1).contiguous()
+          for k, v in _grad_maps(rng, cam.height, cam.width, sc.num_classes).items()}
+    modes = [0, 1, 2]
+    res = []
+    for acc in modes:
+        fr = U.frame_for(sc, acc=acc)
+        fr.prepare(g)
+        maps = {k: v.clone() for k, v in fr.forward(g).items()}
+        grads = {k: v.clone() for k, v in fr.backward(g, dict(dl)).items()}
+        ne, hs = fr.score(g)
+        torch.cuda.synchronize()
+        res.append((maps, grads, ne.clone(), hs.clone()))
+    for other in res[1:]:
+        for k in res[0][0]:
+            assert torch.equal(res[0][0][k], other[0][k]), k
+        for k in res[0][1]:
+            assert torch.equal(res[0][1][k], other[1][k]), k
+        assert torch.equal(res[0][2], other[2]) and torch.equal(res[0][3], other[3])
 
 
 def test_out_of_range_class_index_reported():
