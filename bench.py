@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--score-n", type=int, default=500_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-score", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain streaming kernel over this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -69,7 +70,7 @@ class Timer:
 
 
 def mapping_bench(args, torch, out):
-    from paper_2506_00225_amd import Frame, FusedAdam, Gaussians, make_config, mapping_loss_grad, scenes
+    from paper_2506_00225_amd import Frame, FusedAdam, Gaussians, autotune, make_config, mapping_loss_grad, scenes
 
     log("generating room scene", args.n)
     sc = scenes.room_scene(n=args.n)
@@ -84,6 +85,11 @@ def mapping_bench(args, torch, out):
     st, nvis, nkeys = fr.status()
     fr.key_capacity = int(nkeys * 1.5) + 4096
     fr._alloc()
+    fr.prepare(g, check=True)
+    if not args.no_tune:
+        rep = autotune.tune_mapping(fr, g, reps=3)
+        out["autotune_mapping"] = rep
+        log("autotune mapping", json.dumps(rep["candidates"]))
     dev = g.means.device
     t_rgb = torch.from_numpy(sc.targets["rgb"]).to(dev).reshape(P, 3)
     t_depth = torch.from_numpy(sc.targets["depth"]).to(dev).reshape(P)
@@ -208,7 +214,7 @@ def roofline(out):
 
 
 def score_bench(args, torch, out):
-    from paper_2506_00225_amd import Frame, Gaussians, make_config, scenes, score_maps
+    from paper_2506_00225_amd import Frame, Gaussians, autotune, make_config, scenes, score_maps
 
     log("generating candidate scene", args.score_n, args.score_views)
     sc = scenes.candidate_scene(n=args.score_n, nviews=args.score_views)
@@ -219,6 +225,10 @@ def score_bench(args, torch, out):
     _, _, nk = fr.status()
     fr.key_capacity = int(nk * 1.3) + 4096
     fr._alloc()
+    if not args.no_tune:
+        rep = autotune.tune_score(fr, g, reps=2)
+        out["autotune_score"] = rep
+        log("autotune score", json.dumps(rep["candidates"]))
     ne = torch.empty(fr.V, dtype=torch.int32, device="cuda")
     hs = torch.empty(fr.V, dtype=torch.float64, device="cuda")
     reps = 10
@@ -353,6 +363,9 @@ def main():
                 "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views"):
         if key in out:
             line[key] = out[key]
+    tuned = {k: out[k]["chosen"] for k in ("autotune_mapping", "autotune_score") if k in out and "chosen" in out[k]}
+    if tuned:
+        line["autotune"] = tuned
     print(json.dumps(line), flush=True)
 
 

@@ -78,9 +78,15 @@ typedef struct {
                                      class sums: SGR_ACC_AUTO (LDS when it fits), SGR_ACC_LDS
                                      or SGR_ACC_REGISTERS (C <= 128).  A speed choice only:
                                      every output is bitwise the same. */
+    int32_t tile_order;           /* which tile a workgroup takes: SGR_TILES_AUTO or
+                                     SGR_TILES_XCD (each of the 8 XCDs walks one contiguous
+                                     run of tiles, sharing its L2) or SGR_TILES_LINEAR. */
+    int32_t score_workgroups;     /* workgroups of the persistent scoring launch; 0 = as many
+                                     as are resident at once.  Speed only. */
 } sgr_config;
 
 enum { SGR_ACC_AUTO = 0, SGR_ACC_LDS = 1, SGR_ACC_REGISTERS = 2 };
+enum { SGR_TILES_AUTO = 0, SGR_TILES_XCD = 1, SGR_TILES_LINEAR = 2 };
 
 typedef struct {
     int64_t n;

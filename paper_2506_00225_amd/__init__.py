@@ -6,10 +6,10 @@ semantics, its backward pass, and batched view scoring) runs in the HIP
 library libsgr.so behind the C ABI of include/sgr.h; this package only
 marshals arguments and takes device memory and streams from PyTorch.
 """
-from . import _lib
+from . import _lib, autotune
 from ._lib import SgrError
 from .rasterizer import (FusedAdam, Frame, Gaussians, camera_array, make_config, mapping_loss_grad, render,
                          score_maps)
 
-__all__ = ["FusedAdam", "Frame", "Gaussians", "SgrError", "camera_array", "make_config", "mapping_loss_grad", "render",
-           "score_maps", "_lib"]
+__all__ = ["FusedAdam", "Frame", "Gaussians", "SgrError", "autotune", "camera_array", "make_config",
+           "mapping_loss_grad", "render", "score_maps", "_lib"]

@@ -28,10 +28,12 @@ class sgr_config(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
                 ("z_near", ctypes.c_float), ("lowpass", ctypes.c_float), ("num_classes", ctypes.c_int32),
                 ("top_k", ctypes.c_int32), ("sem_grad_to_geometry", ctypes.c_int32), ("tile_w", ctypes.c_int32),
-                ("tile_h", ctypes.c_int32), ("sem_accumulators", ctypes.c_int32)]
+                ("tile_h", ctypes.c_int32), ("sem_accumulators", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("score_workgroups", ctypes.c_int32)]
 
 
 SGR_ACC_AUTO, SGR_ACC_LDS, SGR_ACC_REGISTERS = 0, 1, 2
+SGR_TILES_AUTO, SGR_TILES_XCD, SGR_TILES_LINEAR = 0, 1, 2
 
 
 class sgr_gaussians(ctypes.Structure):

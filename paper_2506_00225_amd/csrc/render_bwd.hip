@@ -106,7 +106,7 @@ template <int KT>
 __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     extern __shared__ __align__(16) float smem[];
     const TileArgs& a = b.t;
-    const int gt = xcd_remap(blockIdx.x, gridDim.x);
+    const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
     if (gt >= a.num_tiles) return;
     if (a.counters[kStatus] & SGR_ECAPACITY) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;

@@ -97,6 +97,7 @@ struct TileArgs {
     float* pix_T;
     uint32_t* pix_last;
     float alpha_min, alpha_max, t_min;
+    int linear_tiles;  // 1: workgroup i takes tile i; 0: XCD-contiguous runs
     const MapPtrs* maps;
 };
 

@@ -350,7 +350,7 @@ __device__ __forceinline__ void write_sem_block(const v32f& acc, float* buf, flo
 template <int KT, int SEM, int NB>
 __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
     extern __shared__ __align__(16) float smem[];
-    const int gt = xcd_remap(blockIdx.x, gridDim.x);
+    const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
     if (gt >= a.num_tiles) return;
     if (a.counters[kStatus] & SGR_ECAPACITY) return;
     TileResult r;
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, Sc
     const int G = (int)gridDim.x;       // a multiple of 8
     const int items = ok ? per * 8 : 0;
     for (int item = (int)blockIdx.x; item < items; item += G) {
-        const int gt = (item & 7) * per + (item >> 3);
+        const int gt = a.linear_tiles ? item : (item & 7) * per + (item >> 3);
         if (gt >= T) continue;
         TileResult r;
         v32f acc0, acc1, acc2, acc3;
@@ -615,6 +615,7 @@ TileArgs make_tile_args(const Plan& P, char* ws) {
     a.alpha_min = P.cfg.alpha_min;
     a.alpha_max = P.cfg.alpha_max;
     a.t_min = P.cfg.t_min;
+    a.linear_tiles = P.cfg.tile_order == SGR_TILES_LINEAR ? 1 : 0;
     return a;
 }
 
@@ -669,7 +670,8 @@ static sgr_status score_launch(const Plan& P, const TileArgs& a, const ScoreOut&
         per_cu = std::max(1, n);
         per_cu_lds = lds;
     }
-    const int64_t want = std::min<int64_t>(P.num_tiles, (int64_t)device_cu_count() * per_cu);
+    const int64_t resident = (int64_t)device_cu_count() * per_cu;
+    const int64_t want = std::min<int64_t>(P.num_tiles, P.cfg.score_workgroups > 0 ? P.cfg.score_workgroups : resident);
     const unsigned grid = (unsigned)(div_up(want, 8) * 8);
     score_persistent_kernel<KT, SEM, NB><<<grid, kBlock, lds, st>>>(a, so);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;

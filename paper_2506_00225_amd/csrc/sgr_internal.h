@@ -75,5 +75,6 @@ __device__ inline int xcd_remap(int bid, int grid8) {
     const int per = grid8 >> 3;
     return (bid & 7) * per + (bid >> 3);
 }
+__device__ inline int tile_of_block(int bid, int grid8, int linear) { return linear ? bid : xcd_remap(bid, grid8); }
 
 }  // namespace sgr

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from oracle import oracle as O
-from paper_2506_00225_amd import Frame, Gaussians, make_config, render, scenes, score_maps
+from paper_2506_00225_amd import Frame, Gaussians, autotune, make_config, render, scenes, score_maps
 
 import gpu_util as U
 
@@ -500,3 +500,30 @@ def test_score_views_graph_replay_matches_eager():
         torch.cuda.synchronize()
     st, _, _ = fr.status()
     assert st == 0
+
+
+def test_autotuner_choices_keep_outputs():
+    """The autotuner times every candidate on the frame's own data, checks
+    that all candidates give the same bits, and leaves the fastest in the
+    config; the tuned frame reproduces the default frame's outputs."""
+    _say("autotune")
+    autotune.clear_cache()
+    sc = scenes.candidate_scene(n=30_000, nviews=4)
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc)
+    fr.prepare(g)
+    rep = autotune.tune_mapping(fr, g, reps=1)
+    assert len(rep["candidates"]) == 4 and rep["chosen"] in rep["candidates"]
+    rep2 = autotune.tune_score(fr, g, reps=1, workgroups=(0, 64))
+    assert len(rep2["candidates"]) == 8
+    assert autotune.tune_score(fr, g)["cached"] == (fr.cfg.sem_accumulators, fr.cfg.tile_order,
+                                                    fr.cfg.score_workgroups)
+    ref = U.frame_for(sc)
+    ref.prepare(g)
+    fr.prepare(g)
+    a, b = ref.forward(g), fr.forward(g)
+    sa, sb = ref.score(g), fr.score(g)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    assert torch.equal(sa[0], sb[0]) and torch.equal(sa[1], sb[1])
