@@ -70,7 +70,7 @@ class Timer:
 
 
 def mapping_bench(args, torch, out):
-    from paper_2506_00225_amd import Frame, FusedAdam, Gaussians, autotune, make_config, mapping_loss_grad, scenes
+    from paper_2506_00225_amd import Frame, FusedAdam, Gaussians, autotune, loss_config, make_config, scenes
 
     log("generating room scene", args.n)
     sc = scenes.room_scene(n=args.n)
@@ -94,10 +94,8 @@ def mapping_bench(args, torch, out):
     t_rgb = torch.from_numpy(sc.targets["rgb"]).to(dev).reshape(P, 3)
     t_depth = torch.from_numpy(sc.targets["depth"]).to(dev).reshape(P)
     label = torch.from_numpy(sc.targets["label"]).to(dev).reshape(P).int().contiguous()
-    maps = fr.alloc_maps()
     grads_in = {"rgb": torch.empty(P, 3, device=dev), "depth": torch.empty(P, device=dev),
                 "sil": torch.empty(P, device=dev), "sem": torch.empty(P, C, device=dev)}
-    scratch = torch.empty(P, device=dev)
     gout = {nm: torch.empty_like(getattr(g, nm)) for nm in ("means", "scales", "quats", "opacity", "rgb", "sem_val")}
     inf = float("inf")
     opt = FusedAdam([(g.means, gout["means"], -inf, inf), (g.scales, gout["scales"], -inf, inf),
@@ -106,11 +104,12 @@ def mapping_bench(args, torch, out):
                     lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
     blends = torch.zeros(args.steps + args.warmup, dtype=torch.int64, device=dev)
 
-    def loss_grad():
-        # mapping loss (Sec. 3.1 silhouette-masked depth + 0.5 colour L1) + L1(S, 1) + cross-entropy
-        mapping_loss_grad(maps, t_rgb, t_depth, label, C, out=grads_in, scratch=scratch)
+    targets = {"rgb": t_rgb, "depth": t_depth, "label": label}
+    lcfg = loss_config()  # Sec. 3.1 masked depth + 0.5 colour L1, |S - 1|, cross-entropy
+    ncon = {"n_contrib": torch.empty(P, dtype=torch.int32, device=dev)}
+    losses = torch.zeros(args.steps + args.warmup, dtype=torch.float64, device=dev)
 
-    names = ["s0", "proj", "bin", "fwd", "loss", "bwd_tiles", "bwd_gather", "adam"]
+    names = ["s0", "proj", "bin", "fwd", "bwd_tiles", "bwd_gather", "adam"]
     tm = Timer(torch, names)
 
     def step(i, timed):
@@ -120,17 +119,16 @@ def mapping_bench(args, torch, out):
         mk("proj")
         fr.bin(g)
         mk("bin")
-        fr.forward(g, maps)
+        _, loss = fr.forward_loss(g, targets, lcfg, maps=ncon, grads=grads_in)  # forward + fused loss gradient
         mk("fwd")
-        blends[i].copy_(maps["n_contrib"].sum(dtype=torch.int64))
-        loss_grad()
-        mk("loss")
         fr.backward_tiles(g, grads_in)
         mk("bwd_tiles")
         fr.backward_gather(g, gout)
         mk("bwd_gather")
         opt.step()
         mk("adam")
+        blends[i].copy_(ncon["n_contrib"].sum(dtype=torch.int64))
+        losses[i].copy_(loss[0])
 
     log("warmup", args.warmup)
     for i in range(args.warmup):
@@ -153,7 +151,8 @@ def mapping_bench(args, torch, out):
     B = blends[args.warmup:].double().mean().item()
     fwd_bwd_ms = stage["proj"] + stage["bin"] + stage["fwd"] + stage["bwd"]
     out.update(dict(step_ms=step_ms, wall_ms=wall * 1e3 / args.steps, stage_ms=stage, blends=B, nvis=nvis, keys=nkeys,
-                    fwd_bwd_ms=fwd_bwd_ms, pixels=P, C=C, k=k, n=sc.n))
+                    fwd_bwd_ms=fwd_bwd_ms, pixels=P, C=C, k=k, n=sc.n,
+                    loss_first_last=[float(losses[args.warmup]), float(losses[-1])]))
     log("stages ms", json.dumps({k_: round(v, 4) for k_, v in stage.items()}), "K", nkeys, "Nv", nvis, "B", B)
     return sc
 
@@ -197,8 +196,9 @@ def roofline(out):
     alg = {
         "proj": 44 * n + 8 * n + 12 * Nv,
         "bin": 12 * K * 3 + 8 * Nv,
-        # read records once, sorted ids once; write maps and the two per-pixel words
-        "fwd": rec * Nv + 4 * K + P * (5 + C) * 4 + 8 * P,
+        # forward with the fused loss: read records and sorted ids once and the targets (rgb, depth,
+        # label); write dL/dmaps, n_contrib and the two per-pixel words
+        "fwd": rec * Nv + 4 * K + 20 * P + P * (5 + C) * 4 + 12 * P,
         # read dL/dmaps, the per-pixel words, sorted ids and records once; write 2D gradients once
         "bwd_tiles": P * (5 + C) * 4 + 8 * P + 4 * K + rec * Nv + g2d * Nv,
         # read 2D gradients and parameters once; write per-Gaussian gradients once
@@ -358,6 +358,7 @@ def main():
         "blends_per_s_fwd_bwd": round(out["blends"] / (out["fwd_bwd_ms"] * 1e-3), 1),
         "blends_per_step": out["blends"], "keys": out["keys"], "visible": out["nvis"],
         "stage_ms": {k_: round(v, 4) for k_, v in out["stage_ms"].items()},
+        "loss_first_last": out["loss_first_last"],
         "roofline": roof,
         "cpu_baseline": cpu,
     }

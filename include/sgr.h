@@ -224,6 +224,48 @@ sgr_status sgr_render_backward_gather(const sgr_gaussians *g, const sgr_camera *
                                       const sgr_config *cfg, int64_t key_capacity, const sgr_grads *out,
                                       void *workspace, size_t workspace_bytes, void *stream);
 
+/* Targets and gradient outputs of one view for sgr_render_forward_loss.
+ * Any target may be NULL to drop its term; any output may be NULL. */
+typedef struct {
+    const float *rgb;      /* [H][W][3] target colour */
+    const float *depth;    /* [H][W] target depth */
+    const int32_t *label;  /* [H][W] class labels: cross-entropy term */
+    const float *sem;      /* [H][W][C] pseudo-ground-truth class distribution: the
+                              Hellinger + cosine term (used instead of label if both) */
+    float *g_rgb, *g_depth, *g_sil, *g_sem;  /* dL/d(map), same layouts as sgr_maps */
+} sgr_loss_view;
+
+/* Weights of the per-keyframe mapping loss (defaults in brackets). */
+typedef struct {
+    float w_depth, w_rgb, w_sil, w_sem;  /* [1, 0.5, 1, 1] */
+    float sil_thresh;                    /* [0.99] colour and depth count where S > this */
+    float ce_floor;                      /* [1e-6] cross-entropy uses ln max(P_label, floor) */
+    float lambda_hd, lambda_cos;         /* [0.8, 0.2] Hellinger and cosine weights */
+    float entropy_tau;                   /* [<= 0: ln k] supervise pixels whose target entropy is below */
+    float sqrt_eps;                      /* [1e-8] inside the Hellinger square roots */
+} sgr_loss_config;
+
+/*
+ * sgr_render_forward_loss -- sgr_render_forward with the mapping loss fused
+ * into its epilogue, where each tile's per-pixel class sums are still in
+ * LDS.  Per view, with P pixels:
+ *   L = (1/P) sum_p [ m (w_depth |D - D*| + w_rgb sum_ch |C - C*|)
+ *                     + w_sil |S - 1| + w_sem L_sem ],   m = [S > sil_thresh]
+ * (the silhouette-masked depth and colour L1 of Sec. 3.1; m is not
+ * differentiated).  L_sem is the semantic loss of Sec. 3.1: with a dense
+ * target g, M_H (lambda_hd D_HD(g, P) + lambda_cos (1 - cos(g, P))) with the
+ * entropy mask M_H = [H(g) < tau] and D_HD the Hellinger distance; with
+ * labels, -ln max(P_label, ce_floor).  Writes dL/d(map) for every view
+ * (ready for sgr_render_backward) and loss[v] (device, double).  `out` may
+ * be NULL or name any subset of the maps to write as well.  The per-pixel
+ * class sums never go to HBM unless out[v].sem asks for them.  Needs the
+ * LDS class-sum placement (C <= 141): otherwise SGR_EUNSUPPORTED.
+ */
+sgr_status sgr_render_forward_loss(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views,
+                                   const sgr_config *cfg, int64_t key_capacity, const sgr_maps *out,
+                                   const sgr_loss_view *lv, const sgr_loss_config *lc, double *loss,
+                                   void *workspace, size_t workspace_bytes, void *stream);
+
 /*
  * sgr_score_views -- Sec. 3.2, Eq. 4-6: for each of num_views candidate
  * views (sizes may differ), render the silhouette and semantics without

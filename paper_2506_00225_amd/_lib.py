@@ -53,6 +53,16 @@ class sgr_grads(ctypes.Structure):
     _fields_ = [("means", P), ("scales", P), ("quats", P), ("opacity", P), ("rgb", P), ("sem_val", P)]
 
 
+class sgr_loss_view(ctypes.Structure):
+    _fields_ = [("rgb", P), ("depth", P), ("label", P), ("sem", P), ("g_rgb", P), ("g_depth", P), ("g_sil", P),
+                ("g_sem", P)]
+
+
+class sgr_loss_config(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_float) for name in ("w_depth", "w_rgb", "w_sil", "w_sem", "sil_thresh", "ce_floor",
+                                                     "lambda_hd", "lambda_cos", "entropy_tau", "sqrt_eps")]
+
+
 class sgr_adam_segment(ctypes.Structure):
     _fields_ = [("p", P), ("g", P), ("m", P), ("v", P), ("n", ctypes.c_int64), ("lo", ctypes.c_float),
                 ("hi", ctypes.c_float)]
@@ -70,6 +80,7 @@ class sgr_layout(ctypes.Structure):
 
 EXPORTS = (
     "sgr_workspace_size", "sgr_workspace_layout", "sgr_project", "sgr_bin", "sgr_render_forward",
+    "sgr_render_forward_loss",
     "sgr_render_backward", "sgr_render_backward_tiles", "sgr_render_backward_gather", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
     "sgr_read_status", "sgr_status_string", "sgr_mapping_loss_grad", "sgr_adam_step",
 )
@@ -99,6 +110,9 @@ def lib():
     L.sgr_bin.restype = i32
     L.sgr_render_forward.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_maps), P, sz, P]
     L.sgr_render_forward.restype = i32
+    L.sgr_render_forward_loss.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_maps),
+                                          ctypes.POINTER(sgr_loss_view), ctypes.POINTER(sgr_loss_config), P, P, sz, P]
+    L.sgr_render_forward_loss.restype = i32
     L.sgr_render_backward.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_map_grads),
                                       ctypes.POINTER(sgr_grads), P, sz, P]
     L.sgr_render_backward.restype = i32
@@ -163,6 +177,12 @@ def sgr_bin(g, cams, num_views, cfg, key_capacity, d_num_keys, workspace, worksp
 def sgr_render_forward(g, cams, num_views, cfg, key_capacity, maps, workspace, workspace_bytes, stream):
     return lib().sgr_render_forward(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, maps,
                                     workspace, workspace_bytes, stream)
+
+
+def sgr_render_forward_loss(g, cams, num_views, cfg, key_capacity, maps, views, loss_cfg, loss, workspace,
+                            workspace_bytes, stream):
+    return lib().sgr_render_forward_loss(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, maps,
+                                         views, ctypes.byref(loss_cfg), loss, workspace, workspace_bytes, stream)
 
 
 def sgr_render_backward(g, cams, num_views, cfg, key_capacity, dl, grads, workspace, workspace_bytes, stream):

@@ -81,6 +81,7 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     P->views = take(sizeof(ViewDev) * V);
     P->map_table = take(sizeof(MapPtrs) * V);
     P->grad_table = take(sizeof(GradPtrs) * V);
+    P->loss_table = take(sizeof(LossPtrs) * V);
     P->count = take(4 * vns);
     P->zbits = take(4 * vns);
     P->gp_of_lin = take(4 * vns);
@@ -261,6 +262,21 @@ sgr_status sgr_render_forward(const sgr_gaussians* g, const sgr_camera* cams, in
     sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
     if (s != SGR_OK) return s;
     return launch_forward(P, out, (char*)workspace, (hipStream_t)stream);
+}
+
+sgr_status sgr_render_forward_loss(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
+                                   const sgr_config* cfg, int64_t key_capacity, const sgr_maps* out,
+                                   const sgr_loss_view* lv, const sgr_loss_config* lc, double* loss, void* workspace,
+                                   size_t workspace_bytes, void* stream) {
+    if (!lv || !lc || !loss) return SGR_EINVAL;
+    const float w[] = {lc->w_depth, lc->w_rgb, lc->w_sil, lc->w_sem, lc->lambda_hd, lc->lambda_cos, lc->sqrt_eps};
+    for (float x : w)
+        if (!(x >= 0.f) || !std::isfinite(x)) return SGR_EINVAL;
+    if (!std::isfinite(lc->sil_thresh) || !(lc->ce_floor > 0.f) || !std::isfinite(lc->entropy_tau)) return SGR_EINVAL;
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    return launch_forward_loss(P, out, lv, lc, loss, (char*)workspace, (hipStream_t)stream);
 }
 
 sgr_status sgr_render_backward(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,

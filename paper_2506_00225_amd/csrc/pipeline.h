@@ -32,7 +32,7 @@ struct Plan {
     size_t pix_T = 0, pix_last = 0;
     size_t slots = 0, touched = 0, g2d = 0;
     size_t tile_part = 0;
-    size_t map_table = 0, grad_table = 0;
+    size_t map_table = 0, grad_table = 0, loss_table = 0;
     size_t total = 0;
 };
 
@@ -78,6 +78,8 @@ sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* w
 sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const sgr_grads* out, char* ws,
                                   hipStream_t st);
 sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, char* ws, hipStream_t st);
+sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_loss_view* lv, const sgr_loss_config* lc,
+                               double* loss, char* ws, hipStream_t st);
 sgr_status launch_score_maps(const float* sem, const int32_t* n_contrib, int W, int H, int C, uint32_t* n_empty,
                              double* entropy_sum, char* scratch, hipStream_t st);
 size_t score_maps_scratch_bytes(int W, int H);

@@ -78,6 +78,19 @@ struct MapPtrs {
     int32_t* n_contrib;
 };
 
+struct LossPtrs {  // one view's loss targets and gradient outputs
+    const float *rgb, *depth;
+    const int32_t* label;
+    const float* sem;
+    float *g_rgb, *g_depth, *g_sil, *g_sem;
+};
+
+struct LossK {  // fused-loss kernel arguments
+    const LossPtrs* views;
+    float w_depth, w_rgb, w_sil, w_sem, sil_thresh, ce_floor, lambda_hd, lambda_cos, tau, sqrt_eps;
+    double* tile_loss;  // [num_tiles]
+};
+
 struct GradPtrs {
     const float *rgb, *depth, *sil, *sem;
 };

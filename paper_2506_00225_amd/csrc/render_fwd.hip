@@ -315,6 +315,131 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     res.s = ss;
 }
 
+// Writes the tile's class-major LDS columns (one per pixel, stride 257) as
+// [H][W][C] rows: each tile row is one contiguous run of 16 C floats.
+__device__ __forceinline__ void write_rows_from_lds(const float* smem, float* out, const ViewDev& vw, int C, int tx,
+                                                    int ty) {
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
+    const int row_elems = kTile * C;
+    const int dl = kBlock / C, dc = kBlock % C;
+    for (int row = 0; row < hrows; row++) {
+        float* dst = out + ((int64_t)(y0 + row) * vw.width + x0) * C;
+        int lx = threadIdx.x / C, c = threadIdx.x % C;
+        for (int e = threadIdx.x; e < row_elems; e += kBlock) {
+            if (lx < wcols) dst[e] = smem[c * kAccStride + slot_of(lx, row)];
+            lx += dl;
+            c += dc;
+            if (c >= C) { c -= C; lx++; }
+        }
+    }
+}
+
+__device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+// The mapping loss of one pixel and its gradient with respect to the maps
+// (Sec. 3.1), fused after the tile's compositing.  Geometry: the
+// silhouette-masked depth and colour L1 and |S - 1|.  Semantics (LDS class
+// sums, SEM == 1): each thread turns its own class column into dL/dP, from
+// a dense target g (entropy mask, Hellinger + cosine) or a label
+// (cross-entropy).  The tile's summed loss goes to tile_loss[gt].
+template <int SEM>
+__device__ __forceinline__ void loss_epilogue(const TileArgs& a, const LossK& lk, const TileResult& r,
+                                              const ViewDev& vw, int gt, float* smem) {
+    __shared__ double s_part[kBlock / 64];
+    const int tid = threadIdx.x;
+    const LossPtrs& L = lk.views[r.v];
+    const float inv_p = 1.f / ((float)vw.width * (float)vw.height);
+    const int64_t pix = (int64_t)r.py * vw.width + r.px;
+    double lpx = 0.0;
+    if (r.inside) {
+        const float m = r.s > lk.sil_thresh ? 1.f : 0.f;
+        float lg = 0.f;
+        if (L.depth) {
+            const float rd = r.d - L.depth[pix];
+            lg += m * lk.w_depth * fabsf(rd);
+            if (L.g_depth) L.g_depth[pix] = m * lk.w_depth * sgnf(rd) * inv_p;
+        } else if (L.g_depth) {
+            L.g_depth[pix] = 0.f;
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            if (L.rgb) {
+                const float rc = r.c[ch] - L.rgb[3 * pix + ch];
+                lg += m * lk.w_rgb * fabsf(rc);
+                if (L.g_rgb) L.g_rgb[3 * pix + ch] = m * lk.w_rgb * sgnf(rc) * inv_p;
+            } else if (L.g_rgb) {
+                L.g_rgb[3 * pix + ch] = 0.f;
+            }
+        }
+        const float rs = r.s - 1.f;
+        lg += lk.w_sil * fabsf(rs);
+        if (L.g_sil) L.g_sil[pix] = lk.w_sil * sgnf(rs) * inv_p;
+        lpx = (double)lg;
+    }
+    if constexpr (SEM == 1) {
+        const int C = a.C;
+        __syncthreads();  // class sums final
+        if (a.maps[r.v].sem) {
+            write_rows_from_lds(smem, a.maps[r.v].sem, vw, C, r.tx, r.ty);
+            __syncthreads();  // every column read before it is overwritten
+        }
+        float* col = smem + tid;  // this pixel's classes, stride kAccStride
+        if (r.inside && L.sem) {
+            const float* g = L.sem + pix * C;
+            const float e = lk.sqrt_eps;
+            float H = 0.f, gg = 0.f, qq = 0.f, gq = 0.f, dd = 0.f;
+            for (int c = 0; c < C; c++) {
+                const float gc = g[c], qc = col[c * kAccStride];
+                if (gc > 0.f) H -= gc * logf(gc);
+                gg += gc * gc;
+                qq += qc * qc;
+                gq += gc * qc;
+                const float d = sqrtf(gc + e) - sqrtf(qc + e);
+                dd += d * d;
+            }
+            if (H < lk.tau && gg > 0.f && qq > 0.f) {
+                const float ng = sqrtf(gg), nq = sqrtf(qq), root = sqrtf(dd);
+                const float cosv = gq / (ng * nq);
+                const float kSqrt2 = 1.41421356237309504880f;
+                lpx += (double)(lk.w_sem * (lk.lambda_hd * root / kSqrt2 + lk.lambda_cos * (1.f - cosv)));
+                const float s = lk.w_sem * inv_p;
+                const float a_hd = root > 0.f ? -lk.lambda_hd / (2.f * kSqrt2 * root) : 0.f;
+                const float a_g = -lk.lambda_cos / (ng * nq), a_q = lk.lambda_cos * cosv / (nq * nq);
+                for (int c = 0; c < C; c++) {
+                    const float gc = g[c], qc = col[c * kAccStride];
+                    const float sq = sqrtf(qc + e);
+                    const float d = sqrtf(gc + e) - sq;
+                    col[c * kAccStride] = s * (a_hd * d / sq + a_g * gc + a_q * qc);
+                }
+            } else {
+                for (int c = 0; c < C; c++) col[c * kAccStride] = 0.f;
+            }
+        } else if (r.inside && L.label) {
+            const int lab = L.label[pix];
+            float gl = 0.f;
+            if (lab >= 0 && lab < C) {
+                const float q = col[lab * kAccStride];
+                lpx -= (double)(lk.w_sem * logf(fmaxf(q, lk.ce_floor)));
+                gl = q > lk.ce_floor ? -lk.w_sem * inv_p / q : 0.f;
+            } else {
+                atomicOr(&a.counters[kStatus], Plan::kBadIndex);
+            }
+            for (int c = 0; c < C; c++) col[c * kAccStride] = 0.f;
+            if (lab >= 0 && lab < C) col[lab * kAccStride] = gl;
+        } else {
+            for (int c = 0; c < C; c++) col[c * kAccStride] = 0.f;
+        }
+        __syncthreads();
+        if (L.g_sem) write_rows_from_lds(smem, L.g_sem, vw, C, r.tx, r.ty);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lpx += __shfl_xor(lpx, o, 64);
+    if ((tid & 63) == 0) s_part[tid >> 6] = lpx;
+    __syncthreads();
+    if (tid == 0) lk.tile_loss[gt] = ((s_part[0] + s_part[1]) + s_part[2]) + s_part[3];
+}
+
 // Classes 32 B .. 32 B + 31 of a wave's 8x8 pixel block to the [H][W][C]
 // map through the wave's 64 x 33 LDS buffer: lane l stores its pixel's 32
 // sums, then each store instruction covers four pixels' runs of 32 classes
@@ -347,8 +472,8 @@ __device__ __forceinline__ void write_sem_block(const v32f& acc, float* buf, flo
     }
 }
 
-template <int KT, int SEM, int NB>
-__global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
+template <int KT, int SEM, int NB, bool LOSS>
+__global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk) {
     extern __shared__ __align__(16) float smem[];
     const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
     if (gt >= a.num_tiles) return;
@@ -369,25 +494,15 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a) {
         a.pix_T[vw.pix_off + pix] = r.T;
         a.pix_last[vw.pix_off + pix] = r.last;
     }
+    if constexpr (LOSS) {
+        loss_epilogue<SEM>(a, lk, r, vw, gt, smem);
+        return;
+    }
     if (SEM == 1) {
         float* out = a.maps[r.v].sem;
         if (!out) return;
         __syncthreads();
-        const int C = a.C;
-        const int x0 = r.tx * kTile, y0 = r.ty * kTile;
-        const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
-        const int row_elems = kTile * C;
-        const int dl = kBlock / C, dc = kBlock % C;
-        for (int row = 0; row < hrows; row++) {
-            float* dst = out + ((int64_t)(y0 + row) * vw.width + x0) * C;
-            int lx = threadIdx.x / C, c = threadIdx.x % C;
-            for (int e = threadIdx.x; e < row_elems; e += kBlock) {
-                if (lx < wcols) dst[e] = smem[c * kAccStride + slot_of(lx, row)];
-                lx += dl;
-                c += dc;
-                if (c >= C) { c -= C; lx++; }
-            }
-        }
+        write_rows_from_lds(smem, out, vw, a.C, r.tx, r.ty);
     }
     if (SEM == 3) {
         // Each wave writes its 8x8 block, 32 classes at a time, through a
@@ -619,10 +734,10 @@ TileArgs make_tile_args(const Plan& P, char* ws) {
     return a;
 }
 
-template <int KT, int SEM, int NB>
-static void fwd_launch(const TileArgs& a, unsigned grid, size_t lds, hipStream_t st) {
-    set_lds(render_fwd_kernel<KT, SEM, NB>, lds);
-    render_fwd_kernel<KT, SEM, NB><<<grid, kBlock, lds, st>>>(a);
+template <int KT, int SEM, int NB, bool LOSS = false>
+static void fwd_launch(const TileArgs& a, unsigned grid, size_t lds, hipStream_t st, const LossK& lk = LossK{}) {
+    set_lds(render_fwd_kernel<KT, SEM, NB, LOSS>, lds);
+    render_fwd_kernel<KT, SEM, NB, LOSS><<<grid, kBlock, lds, st>>>(a, lk);
 }
 
 template <int KT>
@@ -674,6 +789,65 @@ static sgr_status score_launch(const Plan& P, const TileArgs& a, const ScoreOut&
     const int64_t want = std::min<int64_t>(P.num_tiles, P.cfg.score_workgroups > 0 ? P.cfg.score_workgroups : resident);
     const unsigned grid = (unsigned)(div_up(want, 8) * 8);
     score_persistent_kernel<KT, SEM, NB><<<grid, kBlock, lds, st>>>(a, so);
+    return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
+}
+
+// Per-view loss: the view's tile slots summed in a fixed order, over P.
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const ViewDev* views, const double* tile_loss,
+                                                          const uint32_t* counters, double* loss) {
+    __shared__ double s_part[4];
+    const ViewDev& vw = views[blockIdx.x];
+    const bool ok = !(counters[kStatus] & SGR_ECAPACITY);
+    const int nt = vw.tiles_x * vw.tiles_y;
+    double s = 0.0;
+    if (ok)
+        for (int t = threadIdx.x; t < nt; t += 256) s += tile_loss[vw.tile_off + t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        loss[blockIdx.x] = ok ? (((s_part[0] + s_part[1]) + s_part[2]) + s_part[3]) / ((double)vw.width * vw.height)
+                              : 0.0;
+}
+
+sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_loss_view* lv, const sgr_loss_config* lc,
+                               double* loss, char* ws, hipStream_t st) {
+    TileArgs a = make_tile_args(P, ws);
+    bool want_sem = false;
+    std::vector<MapPtrs> mp(P.V);
+    std::vector<LossPtrs> lp(P.V);
+    for (int v = 0; v < P.V; v++) {
+        if (out) mp[v] = MapPtrs{out[v].rgb, out[v].depth, out[v].sil, out[v].sem, out[v].t_final, out[v].n_contrib};
+        else mp[v] = MapPtrs{};
+        lp[v] = LossPtrs{lv[v].rgb, lv[v].depth, lv[v].label, lv[v].sem,
+                         lv[v].g_rgb, lv[v].g_depth, lv[v].g_sil, lv[v].g_sem};
+        want_sem |= mp[v].sem != nullptr || lv[v].label != nullptr || lv[v].sem != nullptr || lv[v].g_sem != nullptr;
+    }
+    upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
+    upload_bytes(ws + P.loss_table, lp.data(), sizeof(LossPtrs) * P.V, st);
+    a.maps = (const MapPtrs*)(ws + P.map_table);
+    LossK lk;
+    lk.views = (const LossPtrs*)(ws + P.loss_table);
+    lk.w_depth = lc->w_depth; lk.w_rgb = lc->w_rgb; lk.w_sil = lc->w_sil; lk.w_sem = lc->w_sem;
+    lk.sil_thresh = lc->sil_thresh; lk.ce_floor = lc->ce_floor;
+    lk.lambda_hd = lc->lambda_hd; lk.lambda_cos = lc->lambda_cos;
+    lk.tau = lc->entropy_tau > 0.f ? lc->entropy_tau : logf((float)P.k);
+    lk.sqrt_eps = lc->sqrt_eps;
+    lk.tile_loss = (double*)(ws + P.tile_part);
+    const int sem = want_sem ? 1 : 0;
+    const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, sem);
+    if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
+    const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
+    if (P.k == 16) {
+        if (sem) fwd_launch<16, 1, 1, true>(a, grid, lds, st, lk); else fwd_launch<16, 0, 1, true>(a, grid, lds, st, lk);
+    } else if (P.k == 3) {
+        if (sem) fwd_launch<3, 1, 1, true>(a, grid, lds, st, lk); else fwd_launch<3, 0, 1, true>(a, grid, lds, st, lk);
+    } else {
+        if (sem) fwd_launch<0, 1, 1, true>(a, grid, lds, st, lk); else fwd_launch<0, 0, 1, true>(a, grid, lds, st, lk);
+    }
+    loss_reduce_kernel<<<P.V, 256, 0, st>>>((const ViewDev*)(ws + P.views), lk.tile_loss,
+                                            (const uint32_t*)(ws + P.counters), loss);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }
 

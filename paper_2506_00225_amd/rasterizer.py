@@ -174,6 +174,54 @@ class Frame:
                 "sgr_render_forward")
         return maps
 
+    def forward_loss(self, g: Gaussians, targets, loss_cfg=None, maps=None, grads=None):
+        """Forward render with the mapping loss fused into the same launch.
+
+        targets: one dict per view (or one dict for a single view) with
+        "rgb" [P,3], "depth" [P] and optionally "label" [P] (int32,
+        cross-entropy) or "sem" [P,C] (pseudo-ground-truth distribution:
+        entropy-masked Hellinger + cosine), all flat over the view's pixels.
+        loss_cfg: an sgr_loss_config (loss_config() defaults if None).
+        maps: optional dict of map tensors to write as well (any subset).
+        Returns (grads, loss) with grads flat over all views like
+        alloc_maps(), ready for backward(), and loss a float64 [V] tensor."""
+        targets = [targets] if isinstance(targets, dict) else list(targets)
+        if len(targets) != self.V:
+            raise ValueError("one target dict per view")
+        C = self.cfg.num_classes
+        dev = self.device
+        P = self.pix_off[-1]
+        if grads is None:
+            grads = {"rgb": torch.empty((P, 3), device=dev), "depth": torch.empty(P, device=dev),
+                     "sil": torch.empty(P, device=dev), "sem": torch.empty((P, C), device=dev)}
+        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C, "t_final": 1, "n_contrib": 1}
+        arr = None
+        if maps is not None:
+            ptrs = {key: self._view_ptrs(maps.get(key), cols[key], 4) for key in cols}
+            arr = (L.sgr_maps * self.V)()
+            for v in range(self.V):
+                arr[v] = L.sgr_maps(ptrs["rgb"][v], ptrs["depth"][v], ptrs["sil"][v], ptrs["sem"][v],
+                                    ptrs["t_final"][v], ptrs["n_contrib"][v])
+        gp = {key: self._view_ptrs(grads.get(key), cols[key], 4) for key in ("rgb", "depth", "sil", "sem")}
+        keep = []
+        lv = (L.sgr_loss_view * self.V)()
+        for v, t in enumerate(targets):
+            tp = {}
+            for key, dt in (("rgb", torch.float32), ("depth", torch.float32), ("label", torch.int32),
+                            ("sem", torch.float32)):
+                x = t.get(key)
+                if x is not None:
+                    x = x.to(device=dev, dtype=dt).contiguous()
+                    keep.append(x)
+                tp[key] = _ptr(x)
+            lv[v] = L.sgr_loss_view(tp["rgb"], tp["depth"], tp["label"], tp["sem"], gp["rgb"][v], gp["depth"][v],
+                                    gp["sil"][v], gp["sem"][v])
+        loss = torch.empty(self.V, dtype=torch.float64, device=dev)
+        lc = loss_cfg if loss_cfg is not None else loss_config()
+        L.check(L.sgr_render_forward_loss(g.c_struct(), *self._args(), arr, lv, lc, _ptr(loss), _ptr(self.ws),
+                                          self.ws.numel(), self.stream), "sgr_render_forward_loss")
+        return grads, loss
+
     def _map_grads(self, grads: dict):
         C = self.cfg.num_classes
         cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C}
@@ -301,6 +349,13 @@ def render(g: Gaussians, frame: Frame, check: bool = True):
 
 
 MAPPING_LOSS_WEIGHTS = (1.0, 0.5, 1.0, 1.0, 0.99)  # depth, colour, silhouette, cross-entropy, mask threshold
+
+
+def loss_config(w_depth=1.0, w_rgb=0.5, w_sil=1.0, w_sem=1.0, sil_thresh=0.99, ce_floor=1e-6, lambda_hd=0.8,
+                lambda_cos=0.2, entropy_tau=0.0, sqrt_eps=1e-8) -> L.sgr_loss_config:
+    """Weights of the fused mapping loss (entropy_tau <= 0 means ln k)."""
+    return L.sgr_loss_config(w_depth, w_rgb, w_sil, w_sem, sil_thresh, ce_floor, lambda_hd, lambda_cos, entropy_tau,
+                             sqrt_eps)
 
 
 def mapping_loss_grad(maps: dict, t_rgb, t_depth, label, num_classes: int, out: dict | None = None,

@@ -131,6 +131,17 @@ def test_calls_validate_before_any_device_work(L):
     assert L.sgr_score_views(g, cams, 1, cfg, 100, None, None, addr, size, None) == L.SGR_EINVAL
     assert L.sgr_score_maps(None, None, 4, 4, 16, None, None, None, 0, None) == L.SGR_EINVAL
     assert L.sgr_score_maps_workspace_size(0, 4) == 0
+    # fused forward + loss: missing views, config or loss output; negative weights
+    lv = (L.sgr_loss_view * 1)()
+    lc = L.sgr_loss_config(1.0, 0.5, 1.0, 1.0, 0.99, 1e-6, 0.8, 0.2, 0.0, 1e-8)
+    out = np.zeros(1, np.float64).ctypes.data
+    assert L.sgr_render_forward_loss(g, cams, 1, cfg, 100, None, None, lc, out, addr, size, None) == L.SGR_EINVAL
+    assert L.sgr_render_forward_loss(g, cams, 1, cfg, 100, None, lv, lc, None, addr, size, None) == L.SGR_EINVAL
+    bad = L.sgr_loss_config(1.0, -0.5, 1.0, 1.0, 0.99, 1e-6, 0.8, 0.2, 0.0, 1e-8)
+    assert L.sgr_render_forward_loss(g, cams, 1, cfg, 100, None, lv, bad, out, addr, size, None) == L.SGR_EINVAL
+    bad = L.sgr_loss_config(1.0, 0.5, 1.0, 1.0, 0.99, 0.0, 0.8, 0.2, 0.0, 1e-8)
+    assert L.sgr_render_forward_loss(g, cams, 1, cfg, 100, None, lv, bad, out, addr, size, None) == L.SGR_EINVAL
+    assert L.sgr_render_forward_loss(g, cams, 1, cfg, 100, None, lv, lc, out, addr, size - 1, None) == L.SGR_EINVAL
 
 
 def test_status_strings(L):

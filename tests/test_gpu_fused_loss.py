@@ -1,0 +1,129 @@
+"""The mapping loss fused into the forward launch (sgr_render_forward_loss),
+against the FP64 loss oracle evaluated on the same rendered maps, and
+against the unfused path (forward, loss-gradient kernel, backward)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import loss as OL
+from paper_2506_00225_amd import Gaussians, loss_config, mapping_loss_grad, scenes
+
+import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _scene(n=60_000, w=400, h=300):
+    sc = scenes.room_scene(seed=4, n=n, targets=False)
+    cam = sc.cameras[0]
+    sc.cameras = [scenes.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx - (cam.width - w) / 2,
+                                cam.cy - (cam.height - h) / 2, w, h)]
+    return sc
+
+
+def _targets(rng, P, C, kind, k):
+    t = {"rgb": rng.random((P, 3)).astype(np.float32), "depth": (rng.random(P) * 4.5 + 0.5).astype(np.float32)}
+    if kind == "label":
+        t["label"] = rng.integers(0, C, size=P).astype(np.int32)
+    elif kind == "sem":
+        # pseudo-ground truth: sharp for most pixels (entropy below ln k), flat for the rest
+        conc = np.where(rng.random(P) < 0.8, 0.05, 5.0)[:, None]
+        t["sem"] = np.stack([rng.dirichlet(np.ones(C) * c) for c in conc[:, 0]]).astype(np.float32)
+    return t
+
+
+@pytest.mark.parametrize("kind", ["label", "sem", "none"])
+def test_fused_loss_matches_oracle_on_rendered_maps(kind):
+    _say("fused loss vs oracle", kind)
+    sc = _scene()
+    cam = sc.cameras[0]
+    P, C, k = cam.width * cam.height, sc.num_classes, sc.k
+    rng = np.random.default_rng(7)
+    tg = _targets(rng, P, C, kind, k)
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc)
+    fr.prepare(g)
+    maps = fr.alloc_maps()
+    grads, loss = fr.forward_loss(g, {kk: torch.from_numpy(v) for kk, v in tg.items()}, maps=maps)
+    torch.cuda.synchronize()
+    hw = (cam.height, cam.width)
+    m = {"rgb": U.to_np(maps["rgb"]).reshape(*hw, 3), "depth": U.to_np(maps["depth"]).reshape(hw),
+         "sil": U.to_np(maps["sil"]).reshape(hw), "sem": U.to_np(maps["sem"]).reshape(*hw, C)}
+    t = {"rgb": tg["rgb"].reshape(*hw, 3), "depth": tg["depth"].reshape(hw)}
+    if kind == "label":
+        t["label"] = tg["label"].reshape(hw)
+    if kind == "sem":
+        t["sem"] = tg["sem"].reshape(*hw, C)
+    want_loss, want, flags = OL.mapping_loss(m, t, C, k)
+    assert float(loss[0]) == pytest.approx(want_loss, rel=1e-5)
+    ok = ~flags
+    for key, ch in (("rgb", 3), ("depth", 1), ("sil", 1), ("sem", C)):
+        got = U.to_np(grads[key]).reshape(*hw, ch) if ch > 1 else U.to_np(grads[key]).reshape(hw)
+        w = want[key]
+        if ch > 1:
+            got, w = got[ok], w[ok]
+        else:
+            got, w = got[ok], w[ok]
+        scale = np.abs(w).max() + 1e-30
+        assert np.allclose(got, w, rtol=1e-3, atol=1e-5 * scale), key
+    print("flagged", int(flags.sum()), "of", P, flush=True)
+
+
+def test_fused_loss_equals_unfused_cross_entropy_path():
+    """Fused forward+loss then backward gives the gradients of forward,
+    the separate loss-gradient kernel, and backward."""
+    _say("fused vs unfused")
+    sc = _scene(n=40_000, w=320, h=240)
+    cam = sc.cameras[0]
+    P, C = cam.width * cam.height, sc.num_classes
+    rng = np.random.default_rng(8)
+    tg = _targets(rng, P, C, "label", sc.k)
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc)
+    fr.prepare(g)
+    maps = fr.forward(g)
+    dl = mapping_loss_grad(maps, torch.from_numpy(tg["rgb"]).cuda(), torch.from_numpy(tg["depth"]).cuda(),
+                           torch.from_numpy(tg["label"]).cuda(), C)
+    ref = {kk: v.clone() for kk, v in fr.backward(g, dict(dl)).items()}
+    fgr, loss = fr.forward_loss(g, {kk: torch.from_numpy(v) for kk, v in tg.items()})
+    for key in ("rgb", "depth", "sil", "sem"):
+        assert torch.allclose(fgr[key], dl[key], rtol=1e-6, atol=0), key
+    got = fr.backward(g, dict(fgr))
+    torch.cuda.synchronize()
+    for key in ref:
+        assert torch.allclose(got[key], ref[key], rtol=1e-5, atol=1e-12), key
+
+
+def test_fused_loss_per_view_values_multiview():
+    """Two views of different sizes in one launch: each view's loss and
+    gradients equal those of the view rendered alone."""
+    _say("fused multiview")
+    sc = _scene(n=30_000, w=256, h=192)
+    cam = sc.cameras[0]
+    cam2 = scenes.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx + 30, cam.cy - 10, 200, 150)
+    cams = [cam, cam2]
+    rng = np.random.default_rng(9)
+    tgs = [_targets(rng, c.width * c.height, sc.num_classes, "sem", sc.k) for c in cams]
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc, cams=cams)
+    fr.prepare(g)
+    grads, loss = fr.forward_loss(g, [{kk: torch.from_numpy(v) for kk, v in t.items()} for t in tgs])
+    torch.cuda.synchronize()
+    for v, c in enumerate(cams):
+        f1 = U.frame_for(sc, cams=[c])
+        f1.prepare(g)
+        g1, l1 = f1.forward_loss(g, {kk: torch.from_numpy(x) for kk, x in tgs[v].items()})
+        torch.cuda.synchronize()
+        assert float(l1[0]) == float(loss[v])
+        for key in g1:
+            assert torch.equal(fr.split(grads[key])[v].reshape(-1), g1[key].reshape(-1)), (v, key)
