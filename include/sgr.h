@@ -108,9 +108,14 @@ typedef struct {
 } sgr_maps;
 
 /* Per-view incoming gradients dL/d(map) for sgr_render_backward.  A NULL
- * pointer means a zero gradient for that map. */
+ * pointer means a zero gradient for that map.  The semantic gradient is
+ * either dense (sem, [H][W][C]) or, when sem is NULL, one class per pixel:
+ * dL/dP is sem_at_label[p] at class sem_label[p] and zero elsewhere (the
+ * shape of a cross-entropy gradient; a label outside [0, C) has none). */
 typedef struct {
     const float *rgb, *depth, *sil, *sem;
+    const int32_t *sem_label;    /* [H][W] */
+    const float *sem_at_label;   /* [H][W] */
 } sgr_map_grads;
 
 /* Gradient outputs (same layouts as sgr_gaussians), overwritten, summed over
@@ -233,6 +238,9 @@ typedef struct {
     const float *sem;      /* [H][W][C] pseudo-ground-truth class distribution: the
                               Hellinger + cosine term (used instead of label if both) */
     float *g_rgb, *g_depth, *g_sil, *g_sem;  /* dL/d(map), same layouts as sgr_maps */
+    float *g_sem_at_label;                   /* [H][W]: with a label target, dL/dP at the label
+                                                (zero at every other class), the sparse form
+                                                sgr_map_grads takes; 0 where the label is invalid */
 } sgr_loss_view;
 
 /* Weights of the per-keyframe mapping loss (defaults in brackets). */

@@ -46,7 +46,7 @@ class sgr_maps(ctypes.Structure):
 
 
 class sgr_map_grads(ctypes.Structure):
-    _fields_ = [("rgb", P), ("depth", P), ("sil", P), ("sem", P)]
+    _fields_ = [("rgb", P), ("depth", P), ("sil", P), ("sem", P), ("sem_label", P), ("sem_at_label", P)]
 
 
 class sgr_grads(ctypes.Structure):
@@ -55,7 +55,7 @@ class sgr_grads(ctypes.Structure):
 
 class sgr_loss_view(ctypes.Structure):
     _fields_ = [("rgb", P), ("depth", P), ("label", P), ("sem", P), ("g_rgb", P), ("g_depth", P), ("g_sil", P),
-                ("g_sem", P)]
+                ("g_sem", P), ("g_sem_at_label", P)]
 
 
 class sgr_loss_config(ctypes.Structure):

@@ -102,7 +102,10 @@ __device__ __forceinline__ int transposed_value_index(int lane) {
 
 // Per-key value layout: 0,1 mean2d; 2,3,4 conic (a, b, c); 5 opacity;
 // 6,7,8 rgb; 9 depth; 10.. semantic values.
-template <int KT>
+// SPARSE: no view has a dense dL/dsem; each pixel's semantic gradient is one
+// (class, value) pair (or none), held in registers instead of a 257-float
+// LDS column per class, which leaves room for more workgroups per CU.
+template <int KT, bool SPARSE>
 __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
     extern __shared__ __align__(16) float smem[];
     const TileArgs& a = b.t;
@@ -121,8 +124,8 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
 
     constexpr int KM = KT > 0 ? KT : kMaxK;  // register bound on k
     constexpr int KWM = (KM + 3) / 4;         // ... and on the index words
-    float* gp = smem;  // [C][257] dL/dsem of the tile's pixels, column = owning thread
-    float4* s_r0 = (float4*)(smem + acc_floats(C));
+    float* gp = smem;  // [C][257] dL/dsem of the tile's pixels, column = owning thread (dense mode)
+    float4* s_r0 = (float4*)(smem + (SPARSE ? 0 : acc_floats(C)));
     float4* s_r1 = s_r0 + kBwdBatch;
     float4* s_r2 = s_r1 + kBwdBatch;
     float4* s_col = s_r2 + kBwdBatch;
@@ -154,18 +157,29 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         if (gr.depth) gD = gr.depth[pix];
         if (gr.sil) gS = gr.sil[pix];
     }
+    int lab = -1;  // sparse semantic gradient of this pixel: gl at class lab
+    float gl = 0.f;
+    if (inside && gr.sem_label && !gr.sem) {
+        lab = gr.sem_label[pix];
+        gl = gr.sem_at_label ? gr.sem_at_label[pix] : 0.f;
+    }
     if (tid == 0) s_maxlast = start;
-    {
+    if constexpr (!SPARSE) {
         const int x0 = tx * kTile, y0 = ty * kTile;
         const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
         const int row_elems = kTile * C;
         const int dl = kBwdThreads / C, dc = kBwdThreads % C;
         for (int row = 0; row < kTile; row++) {
-            const float* src = gr.sem ? gr.sem + ((int64_t)(y0 + row) * vw.width + x0) * C : nullptr;
+            const int64_t rowpix = (int64_t)(y0 + row) * vw.width + x0;
+            const float* src = gr.sem ? gr.sem + rowpix * C : nullptr;
             int cx = tid / C, c = tid % C;
             for (int e = tid; e < row_elems; e += kBwdThreads) {
                 float val = 0.f;
-                if (src && row < hrows && cx < wcols) val = src[e];
+                if (row < hrows && cx < wcols) {
+                    if (src) val = src[e];
+                    else if (gr.sem_label && gr.sem_label[rowpix + cx] == c)
+                        val = gr.sem_at_label ? gr.sem_at_label[rowpix + cx] : 0.f;
+                }
                 gp[c * kAccStride + slot_of(cx, row)] = val;
                 cx += dl;
                 c += dc;
@@ -290,7 +304,9 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
                         for (int bb = 0; bb < 4; bb++) {
                             const int m = mw * 4 + bb;
                             if (m < k) {
-                                sg[m] = gp[((word >> (8 * bb)) & 0xffu) * kAccStride + tid];
+                                const uint32_t cls = (word >> (8 * bb)) & 0xffu;
+                                if constexpr (SPARSE) sg[m] = (int)cls == lab ? gl : 0.f;
+                                else sg[m] = gp[cls * kAccStride + tid];
                                 es += sv[m] * sg[m];
                             }
                         }
@@ -593,10 +609,10 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
 
 // ------------------------------------------------------------------ launcher
 
-static size_t bwd_lds_bytes(int C, int k, int kpad) {
+static size_t bwd_lds_bytes(int C, int k, int kpad, bool sparse) {
     size_t b = (size_t)kBwdBatch * (4 * sizeof(float4) + sizeof(uint32_t) + k * sizeof(float) + kpad);
     b += (size_t)kBwdWaves * kBwdBatch * (10 + k) * sizeof(float) + kBwdWaves * kBwdBatch * sizeof(uint32_t);
-    b += (size_t)acc_floats(C) * sizeof(float);
+    if (!sparse) b += (size_t)acc_floats(C) * sizeof(float);
     return b;
 }
 
@@ -606,12 +622,22 @@ static void set_lds_b(K kernel, size_t bytes) {
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <int KT, bool SPARSE>
+static void bwd_launch(const BwdArgs& b, unsigned grid, size_t lds, hipStream_t st) {
+    set_lds_b(render_bwd_kernel<KT, SPARSE>, lds);
+    render_bwd_kernel<KT, SPARSE><<<grid, kBwdThreads, lds, st>>>(b);
+}
+
 sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* ws, hipStream_t st) {
     BwdArgs b;
     memset(&b, 0, sizeof(b));
     b.t = make_tile_args(P, ws);
     std::vector<GradPtrs> gpt(P.V);
-    for (int v = 0; v < P.V; v++) gpt[v] = GradPtrs{dL[v].rgb, dL[v].depth, dL[v].sil, dL[v].sem};
+    bool sparse = true;  // no view carries a dense semantic gradient
+    for (int v = 0; v < P.V; v++) {
+        gpt[v] = GradPtrs{dL[v].rgb, dL[v].depth, dL[v].sil, dL[v].sem, dL[v].sem_label, dL[v].sem_at_label};
+        sparse &= dL[v].sem == nullptr;
+    }
     upload_bytes(ws + P.grad_table, gpt.data(), sizeof(GradPtrs) * P.V, st);
     b.grads = (const GradPtrs*)(ws + P.grad_table);
     b.slots = (float*)(ws + P.slots);
@@ -619,18 +645,15 @@ sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* w
     b.svals = (const uint32_t*)(ws + P.sorted_vals);
     b.nvals = 10 + P.k;
     b.semgeo = P.cfg.sem_grad_to_geometry;
-    size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad);
+    const size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad, sparse);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
     if (P.k == 16) {
-        set_lds_b(render_bwd_kernel<16>, lds);
-        render_bwd_kernel<16><<<grid, kBwdThreads, lds, st>>>(b);
+        if (sparse) bwd_launch<16, true>(b, grid, lds, st); else bwd_launch<16, false>(b, grid, lds, st);
     } else if (P.k == 3) {
-        set_lds_b(render_bwd_kernel<3>, lds);
-        render_bwd_kernel<3><<<grid, kBwdThreads, lds, st>>>(b);
+        if (sparse) bwd_launch<3, true>(b, grid, lds, st); else bwd_launch<3, false>(b, grid, lds, st);
     } else {
-        set_lds_b(render_bwd_kernel<0>, lds);
-        render_bwd_kernel<0><<<grid, kBwdThreads, lds, st>>>(b);
+        if (sparse) bwd_launch<0, true>(b, grid, lds, st); else bwd_launch<0, false>(b, grid, lds, st);
     }
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }

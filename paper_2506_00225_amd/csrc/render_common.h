@@ -82,7 +82,7 @@ struct LossPtrs {  // one view's loss targets and gradient outputs
     const float *rgb, *depth;
     const int32_t* label;
     const float* sem;
-    float *g_rgb, *g_depth, *g_sil, *g_sem;
+    float *g_rgb, *g_depth, *g_sil, *g_sem, *g_sem_at_label;
 };
 
 struct LossK {  // fused-loss kernel arguments
@@ -93,6 +93,8 @@ struct LossK {  // fused-loss kernel arguments
 
 struct GradPtrs {
     const float *rgb, *depth, *sil, *sem;
+    const int32_t* sem_label;  // sparse semantic gradient (when sem is NULL)
+    const float* sem_at_label;
 };
 
 struct TileArgs {

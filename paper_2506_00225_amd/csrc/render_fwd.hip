@@ -386,6 +386,7 @@ __device__ __forceinline__ void loss_epilogue(const TileArgs& a, const LossK& lk
         }
         float* col = smem + tid;  // this pixel's classes, stride kAccStride
         if (r.inside && L.sem) {
+            if (L.g_sem_at_label) L.g_sem_at_label[pix] = 0.f;  // dense target: no single-class form
             const float* g = L.sem + pix * C;
             const float e = lk.sqrt_eps;
             float H = 0.f, gg = 0.f, qq = 0.f, gq = 0.f, dd = 0.f;
@@ -425,10 +426,15 @@ __device__ __forceinline__ void loss_epilogue(const TileArgs& a, const LossK& lk
             } else {
                 atomicOr(&a.counters[kStatus], Plan::kBadIndex);
             }
-            for (int c = 0; c < C; c++) col[c * kAccStride] = 0.f;
-            if (lab >= 0 && lab < C) col[lab * kAccStride] = gl;
+            if (L.g_sem_at_label) L.g_sem_at_label[pix] = gl;
+            if (L.g_sem) {
+                for (int c = 0; c < C; c++) col[c * kAccStride] = 0.f;
+                if (lab >= 0 && lab < C) col[lab * kAccStride] = gl;
+            }
         } else {
-            for (int c = 0; c < C; c++) col[c * kAccStride] = 0.f;
+            if (r.inside && L.g_sem_at_label) L.g_sem_at_label[pix] = 0.f;
+            if (L.g_sem)
+                for (int c = 0; c < C; c++) col[c * kAccStride] = 0.f;
         }
         __syncthreads();
         if (L.g_sem) write_rows_from_lds(smem, L.g_sem, vw, C, r.tx, r.ty);
@@ -821,8 +827,9 @@ sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_los
         if (out) mp[v] = MapPtrs{out[v].rgb, out[v].depth, out[v].sil, out[v].sem, out[v].t_final, out[v].n_contrib};
         else mp[v] = MapPtrs{};
         lp[v] = LossPtrs{lv[v].rgb, lv[v].depth, lv[v].label, lv[v].sem,
-                         lv[v].g_rgb, lv[v].g_depth, lv[v].g_sil, lv[v].g_sem};
-        want_sem |= mp[v].sem != nullptr || lv[v].label != nullptr || lv[v].sem != nullptr || lv[v].g_sem != nullptr;
+                         lv[v].g_rgb, lv[v].g_depth, lv[v].g_sil, lv[v].g_sem, lv[v].g_sem_at_label};
+        want_sem |= mp[v].sem != nullptr || lv[v].label != nullptr || lv[v].sem != nullptr || lv[v].g_sem != nullptr ||
+                    lv[v].g_sem_at_label != nullptr;
     }
     upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
     upload_bytes(ws + P.loss_table, lp.data(), sizeof(LossPtrs) * P.V, st);

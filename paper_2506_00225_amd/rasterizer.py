@@ -174,7 +174,7 @@ class Frame:
                 "sgr_render_forward")
         return maps
 
-    def forward_loss(self, g: Gaussians, targets, loss_cfg=None, maps=None, grads=None):
+    def forward_loss(self, g: Gaussians, targets, loss_cfg=None, maps=None, grads=None, sparse_sem=False):
         """Forward render with the mapping loss fused into the same launch.
 
         targets: one dict per view (or one dict for a single view) with
@@ -184,7 +184,10 @@ class Frame:
         loss_cfg: an sgr_loss_config (loss_config() defaults if None).
         maps: optional dict of map tensors to write as well (any subset).
         Returns (grads, loss) with grads flat over all views like
-        alloc_maps(), ready for backward(), and loss a float64 [V] tensor."""
+        alloc_maps(), ready for backward(), and loss a float64 [V] tensor.
+        With sparse_sem (cross-entropy targets), the semantic gradient comes
+        back as "sem_label" / "sem_at_label", one class per pixel, instead
+        of a dense [P, C] map."""
         targets = [targets] if isinstance(targets, dict) else list(targets)
         if len(targets) != self.V:
             raise ValueError("one target dict per view")
@@ -193,7 +196,14 @@ class Frame:
         P = self.pix_off[-1]
         if grads is None:
             grads = {"rgb": torch.empty((P, 3), device=dev), "depth": torch.empty(P, device=dev),
-                     "sil": torch.empty(P, device=dev), "sem": torch.empty((P, C), device=dev)}
+                     "sil": torch.empty(P, device=dev)}
+            if sparse_sem:
+                grads["sem_at_label"] = torch.empty(P, device=dev)
+                grads["sem_label"] = torch.cat([
+                    (t["label"].to(device=dev, dtype=torch.int32).reshape(-1) if t.get("label") is not None else
+                     torch.full((self.pix[v],), -1, dtype=torch.int32, device=dev)) for v, t in enumerate(targets)])
+            else:
+                grads["sem"] = torch.empty((P, C), device=dev)
         cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C, "t_final": 1, "n_contrib": 1}
         arr = None
         if maps is not None:
@@ -203,6 +213,7 @@ class Frame:
                 arr[v] = L.sgr_maps(ptrs["rgb"][v], ptrs["depth"][v], ptrs["sil"][v], ptrs["sem"][v],
                                     ptrs["t_final"][v], ptrs["n_contrib"][v])
         gp = {key: self._view_ptrs(grads.get(key), cols[key], 4) for key in ("rgb", "depth", "sil", "sem")}
+        gp["sem_at_label"] = self._view_ptrs(grads.get("sem_at_label"), 1, 4)
         keep = []
         lv = (L.sgr_loss_view * self.V)()
         for v, t in enumerate(targets):
@@ -215,7 +226,7 @@ class Frame:
                     keep.append(x)
                 tp[key] = _ptr(x)
             lv[v] = L.sgr_loss_view(tp["rgb"], tp["depth"], tp["label"], tp["sem"], gp["rgb"][v], gp["depth"][v],
-                                    gp["sil"][v], gp["sem"][v])
+                                    gp["sil"][v], gp["sem"][v], gp["sem_at_label"][v])
         loss = torch.empty(self.V, dtype=torch.float64, device=dev)
         lc = loss_cfg if loss_cfg is not None else loss_config()
         L.check(L.sgr_render_forward_loss(g.c_struct(), *self._args(), arr, lv, lc, _ptr(loss), _ptr(self.ws),
@@ -223,20 +234,25 @@ class Frame:
         return grads, loss
 
     def _map_grads(self, grads: dict):
+        """sgr_map_grads per view from flat tensors; "sem" is the dense
+        [P, C] gradient, or "sem_label" [P] (int32) with "sem_at_label" [P]
+        give it as one class per pixel."""
         C = self.cfg.num_classes
-        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C}
+        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C, "sem_label": 1, "sem_at_label": 1}
         gp = {}
         for key in cols:
             t = grads.get(key)
             if t is not None:
+                want = torch.int32 if key == "sem_label" else torch.float32
                 t = t.contiguous()
-                if t.dtype != torch.float32:
-                    t = t.float()
+                if t.dtype != want:
+                    t = t.to(want)
                 grads[key] = t
             gp[key] = self._view_ptrs(t, cols[key], 4)
         arr = (L.sgr_map_grads * self.V)()
         for v in range(self.V):
-            arr[v] = L.sgr_map_grads(gp["rgb"][v], gp["depth"][v], gp["sil"][v], gp["sem"][v])
+            arr[v] = L.sgr_map_grads(gp["rgb"][v], gp["depth"][v], gp["sil"][v], gp["sem"][v], gp["sem_label"][v],
+                                     gp["sem_at_label"][v])
         return arr
 
     @staticmethod

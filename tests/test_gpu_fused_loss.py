@@ -127,3 +127,46 @@ def test_fused_loss_per_view_values_multiview():
         assert float(l1[0]) == float(loss[v])
         for key in g1:
             assert torch.equal(fr.split(grads[key])[v].reshape(-1), g1[key].reshape(-1)), (v, key)
+
+
+def test_sparse_semantic_gradient_equals_dense():
+    """One (class, value) per pixel in registers gives the bits of the same
+    gradient written out densely and staged in LDS; the fused loss's sparse
+    output gives the bits of its dense output."""
+    _say("sparse semantic gradient")
+    sc = _scene(n=50_000, w=320, h=240)
+    cam = sc.cameras[0]
+    P, C = cam.width * cam.height, sc.num_classes
+    rng = np.random.default_rng(10)
+    g = Gaussians.from_scene(sc)
+    for semgeo in (0, 1):
+        fr = U.frame_for(sc, semgeo=semgeo)
+        fr.prepare(g)
+        fr.forward(g)
+        lab = rng.integers(-1, C, size=P).astype(np.int32)  # -1: no semantic gradient at that pixel
+        val = rng.standard_normal(P).astype(np.float32)
+        dense = np.zeros((P, C), np.float32)
+        ok = lab >= 0
+        dense[np.nonzero(ok)[0], lab[ok]] = val[ok]
+        base = {"rgb": torch.randn(P, 3, device="cuda"), "depth": torch.randn(P, device="cuda"),
+                "sil": torch.randn(P, device="cuda")}
+        gd = {k: v.clone() for k, v in fr.backward(g, dict(base, sem=torch.from_numpy(dense).cuda())).items()}
+        gs = fr.backward(g, dict(base, sem_label=torch.from_numpy(lab).cuda(), sem_at_label=torch.from_numpy(val).cuda()))
+        torch.cuda.synchronize()
+        for k in gd:
+            assert torch.equal(gd[k], gs[k]), (semgeo, k)
+    # fused loss: sparse output == dense output, and the backward agrees bitwise
+    tg = _targets(rng, P, C, "label", sc.k)
+    fr = U.frame_for(sc)
+    fr.prepare(g)
+    tt = {kk: torch.from_numpy(v) for kk, v in tg.items()}
+    gdn, l1 = fr.forward_loss(g, tt)
+    ref = {k: v.clone() for k, v in fr.backward(g, dict(gdn)).items()}
+    gsp, l2 = fr.forward_loss(g, tt, sparse_sem=True)
+    got = fr.backward(g, dict(gsp))
+    torch.cuda.synchronize()
+    assert float(l1[0]) == float(l2[0])
+    lab = torch.from_numpy(tg["label"]).cuda().long()
+    assert torch.equal(gdn["sem"].gather(1, lab[:, None])[:, 0], gsp["sem_at_label"])
+    for k in ref:
+        assert torch.equal(ref[k], got[k]), k
