@@ -163,7 +163,7 @@ def mapping_bench(args, torch, out):
     return sc
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_bwd_kernel_1M_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_kernels_1M_traffic.json")
 KERNEL_SOURCES = {"bwd_tiles": ("render_bwd.hip", "render_common.h", "pipeline.h", "sgr_internal.h"),
                   "fwd": ("render_fwd.hip", "render_common.h", "pipeline.h", "sgr_internal.h")}
 
