@@ -342,6 +342,74 @@ typedef struct {
 sgr_status sgr_adam_step(const sgr_adam_segment *segments, int32_t num_segments, float lr, float beta1, float beta2,
                          float eps, int32_t step, void *stream);
 
+/* ------------------------------------------------------------------ planning
+ * Next-best-view selection (Sec. 3.2): candidate poses from the newly
+ * observed voxels of the exploration map, their scores (sgr_score_poses,
+ * Eq. 4-6) and the overall criterion with motion cost (Eq. 7). */
+
+/* Exploration map: nx*ny*nz voxels of edge `voxel` from `origin`, one byte
+ * per voxel (x fastest); 1 marks an observed free voxel. */
+typedef struct {
+    int32_t nx, ny, nz;
+    float voxel;
+    float origin[3];
+} sgr_grid;
+
+/* One sampling stage (coarse: step 1, 5 directions, one height; fine: step
+ * 0.5, 15 directions, several heights). */
+typedef struct {
+    float step;          /* v1: spacing of candidate positions, rounded to whole voxels */
+    int32_t directions;  /* v2: viewing directions per position (Fibonacci lattice on the sphere) */
+    float z_min, z_max;  /* heights of the position layers (equal: one layer) */
+} sgr_sampling;
+
+/* Workspace bytes of sgr_generate_candidates for this grid and stage. */
+size_t sgr_candidates_workspace_size(const sgr_grid *grid, const sgr_sampling *s);
+
+/*
+ * sgr_generate_candidates -- candidate poses (Sec. 3.2, exploration
+ * strategy).  Positions are the centres of voxels that are free in
+ * free_now and not in free_before (NULL: nothing was free), on a lattice of
+ * round(step / voxel) voxels in x and y and on the layers
+ * i0, i0 + s, ... whose centre height lies in [z_min - voxel/2,
+ * z_max + voxel/2); order z, y, x.  Each position takes the `directions`
+ * Fibonacci-lattice directions d_j, z_j = 1 - (2j+1)/n, azimuth j pi
+ * (3 - sqrt 5); candidate v = position * directions + j.  Poses: 12 floats,
+ * world-to-camera R (rows right, down, forward = d_j, with up +z, or +x
+ * when |d_j . z| > 0.99) then t = -R p.  positions: [V][3].  The total V is
+ * written to *d_count (device int64); entries past `capacity` are not
+ * written.  All pointers are device pointers.
+ */
+sgr_status sgr_generate_candidates(const sgr_grid *grid, const uint8_t *free_now, const uint8_t *free_before,
+                                   const sgr_sampling *s, int64_t capacity, float *poses, float *positions,
+                                   int64_t *d_count, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * sgr_score_poses -- sgr_score_views for num_views cameras that share the
+ * intrinsics and size of `intrinsics` (host; its R and t are ignored) and
+ * take their R and t from the device array poses[num_views][12] (as written
+ * by sgr_generate_candidates), so a planning step needs no host copy of
+ * the poses.  Same workspace as sgr_score_views for these sizes.
+ */
+sgr_status sgr_score_poses(const sgr_gaussians *g, const sgr_camera *intrinsics, int32_t num_views, const float *poses,
+                           const sgr_config *cfg, int64_t key_capacity, uint32_t *n_empty, double *entropy_sum,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * sgr_combine_scores -- Eq. 5-7 over the candidate pool, in double
+ * precision: I_geo = N_S / sum N_S (Eq. 5: softmax of log N_S), I_sem =
+ * softmax of the entropy sums (Eq. 6), I = (1 - softmax(l)) I_geo I_sem with
+ * l the distance from `current` (host, 3 floats) to each candidate position
+ * (Eq. 7).  Candidates with N_S < prune_fraction * pixels are flagged in
+ * pruned[]; *best is the unpruned candidate with the largest I (the first
+ * on ties) or -1.  score: [V] double, pruned: [V] bytes, best: one int32;
+ * device pointers.  If every N_S is 0, I_geo is 0.  One workgroup, fixed
+ * reduction order: the result is reproducible bit for bit.
+ */
+sgr_status sgr_combine_scores(int32_t num_views, const uint32_t *n_empty, const double *entropy_sum,
+                              const float *positions, const float *current, int64_t pixels, float prune_fraction,
+                              double *score, uint8_t *pruned, int32_t *best, void *stream);
+
 /* Synchronises `stream` and reads the status word, the visible-pair count
  * and the key count of the workspace (host outputs; any may be NULL). */
 sgr_status sgr_read_status(const void *workspace, void *stream, int64_t *num_visible, int64_t *num_keys);

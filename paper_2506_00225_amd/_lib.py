@@ -71,6 +71,16 @@ class sgr_adam_segment(ctypes.Structure):
 SGR_MAX_ADAM_SEGMENTS = 8
 
 
+class sgr_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("voxel", ctypes.c_float),
+                ("origin", ctypes.c_float * 3)]
+
+
+class sgr_sampling(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_float), ("directions", ctypes.c_int32), ("z_min", ctypes.c_float),
+                ("z_max", ctypes.c_float)]
+
+
 class sgr_layout(ctypes.Structure):
     _fields_ = [(name, ctypes.c_size_t) for name in (
         "total_bytes", "counters", "views", "proj_count", "proj_zbits", "order", "sorted_rec", "sorted_keys",
@@ -83,6 +93,7 @@ EXPORTS = (
     "sgr_render_forward_loss",
     "sgr_render_backward", "sgr_render_backward_tiles", "sgr_render_backward_gather", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
     "sgr_read_status", "sgr_status_string", "sgr_mapping_loss_grad", "sgr_adam_step",
+    "sgr_candidates_workspace_size", "sgr_generate_candidates", "sgr_score_poses", "sgr_combine_scores",
 )
 
 _lib = None
@@ -133,6 +144,15 @@ def lib():
     L.sgr_adam_step.argtypes = [ctypes.POINTER(sgr_adam_segment), i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, i32, P]
     L.sgr_adam_step.restype = i32
+    grid_p, samp_p = ctypes.POINTER(sgr_grid), ctypes.POINTER(sgr_sampling)
+    L.sgr_candidates_workspace_size.argtypes = [grid_p, samp_p]
+    L.sgr_candidates_workspace_size.restype = sz
+    L.sgr_generate_candidates.argtypes = [grid_p, P, P, samp_p, i64, P, P, P, P, sz, P]
+    L.sgr_generate_candidates.restype = i32
+    L.sgr_score_poses.argtypes = [g_p, cam_p, i32, P, cfg_p, i64, P, P, P, sz, P]
+    L.sgr_score_poses.restype = i32
+    L.sgr_combine_scores.argtypes = [i32, P, P, P, ctypes.POINTER(ctypes.c_float), i64, ctypes.c_float, P, P, P, P]
+    L.sgr_combine_scores.restype = i32
     L.sgr_status_string.argtypes = [i32]
     L.sgr_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -234,3 +254,26 @@ def sgr_mapping_loss_grad(rgb, depth, sil, sem, t_rgb, t_depth, label, num_pixel
 
 def sgr_adam_step(segments, num_segments, lr, beta1, beta2, eps, step, stream):
     return lib().sgr_adam_step(segments, num_segments, lr, beta1, beta2, eps, step, stream)
+
+
+def sgr_candidates_workspace_size(grid, sampling):
+    return lib().sgr_candidates_workspace_size(ctypes.byref(grid), ctypes.byref(sampling))
+
+
+def sgr_generate_candidates(grid, free_now, free_before, sampling, capacity, poses, positions, d_count, workspace,
+                            workspace_bytes, stream):
+    return lib().sgr_generate_candidates(ctypes.byref(grid), free_now, free_before, ctypes.byref(sampling), capacity,
+                                         poses, positions, d_count, workspace, workspace_bytes, stream)
+
+
+def sgr_score_poses(g, intrinsics, num_views, poses, cfg, key_capacity, n_empty, entropy_sum, workspace,
+                    workspace_bytes, stream):
+    return lib().sgr_score_poses(ctypes.byref(g), intrinsics, num_views, poses, ctypes.byref(cfg), key_capacity,
+                                 n_empty, entropy_sum, workspace, workspace_bytes, stream)
+
+
+def sgr_combine_scores(num_views, n_empty, entropy_sum, positions, current, pixels, prune_fraction, score, pruned, best,
+                       stream):
+    cur = (ctypes.c_float * 3)(*[float(x) for x in current])
+    return lib().sgr_combine_scores(num_views, n_empty, entropy_sum, positions, cur, pixels, prune_fraction, score,
+                                    pruned, best, stream)

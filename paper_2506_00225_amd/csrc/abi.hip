@@ -323,6 +323,24 @@ sgr_status sgr_score_views(const sgr_gaussians* g, const sgr_camera* cams, int32
     return launch_score(P, n_empty, entropy_sum, (char*)workspace, st);
 }
 
+sgr_status sgr_score_poses(const sgr_gaussians* g, const sgr_camera* intrinsics, int32_t num_views, const float* poses,
+                           const sgr_config* cfg, int64_t key_capacity, uint32_t* n_empty, double* entropy_sum,
+                           void* workspace, size_t workspace_bytes, void* stream) {
+    if (!intrinsics || !poses || !n_empty || !entropy_sum || num_views < 1) return SGR_EINVAL;
+    std::vector<sgr_camera> cams((size_t)num_views, *intrinsics);
+    for (sgr_camera& c : cams) {  // placeholders until the device poses are copied in
+        for (int i = 0; i < 9; i++) c.R[i] = (i % 4 == 0) ? 1.f : 0.f;
+        for (int i = 0; i < 3; i++) c.t[i] = 0.f;
+    }
+    Plan P;
+    sgr_status s = prepare(g, cams.data(), num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = launch_project(P, g, (char*)workspace, st, poses)) != SGR_OK) return s;
+    if ((s = launch_bin(P, (char*)workspace, nullptr, st)) != SGR_OK) return s;
+    return launch_score(P, n_empty, entropy_sum, (char*)workspace, st);
+}
+
 size_t sgr_score_maps_workspace_size(int32_t width, int32_t height) {
     if (width < 1 || height < 1) return 0;
     return score_maps_scratch_bytes(width, height);

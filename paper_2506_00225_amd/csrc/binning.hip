@@ -257,8 +257,7 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
     }
 #pragma unroll
     for (int m = 0; m < KM; m++) {
-        if (m >= k) break;
-        const int pos = grouped_pos<KM>(blk, k, m);
+        const int pos = m < k ? grouped_pos<KM>(blk, k, m) : -1;
 #pragma unroll
         for (int p = 0; p < KM; p++)
             if (p == pos) {
@@ -356,7 +355,15 @@ __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ 
 
 // --------------------------------------------------------------- launchers
 
-sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st) {
+// R and t of view v from poses[v][12] (R row-major, then t).
+__global__ __launch_bounds__(256) void set_view_poses(ViewDev* views, const float* __restrict__ poses, int V) {
+    const int v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= V) return;
+    for (int c = 0; c < 9; c++) views[v].R[c] = poses[12 * v + c];
+    for (int c = 0; c < 3; c++) views[v].t[c] = poses[12 * v + 9 + c];
+}
+
+sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st, const float* d_poses) {
     ViewDev* views = (ViewDev*)(ws + P.views);
     uint32_t* counters = (uint32_t*)(ws + P.counters);
     // camera table, as kernel arguments
@@ -368,6 +375,7 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
         for (int j = 0; j < ch.count; j++) ch.v[j] = P.view_table[first + j];
         upload_views<<<1, kViewChunk, 0, st>>>(ch, views);
     }
+    if (d_poses) set_view_poses<<<(unsigned)div_up(P.V, 256), 256, 0, st>>>(views, d_poses, P.V);
     {
         const int64_t nthreads = std::max<int64_t>(P.num_tiles, kNumCounters);
         init_frame<<<(unsigned)div_up(nthreads, 256), 256, 0, st>>>(counters, (uint2*)(ws + P.ranges), P.num_tiles);

@@ -71,7 +71,8 @@ struct KeyArgs {
     uint32_t *keys, *owner;
 };
 
-sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st);
+sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st,
+                          const float* d_poses = nullptr);
 sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t st);
 sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStream_t st);
 sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* ws, hipStream_t st);

@@ -596,13 +596,14 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
         }
 #pragma unroll
         for (int m = 0; m < KM; m++) {
-            if (m >= k) break;
-            const int pos = grouped_pos<KM>(blk, k, m);
-            float gv = 0.f;
+            if (m < k) {
+                const int pos = grouped_pos<KM>(blk, k, m);
+                float gv = 0.f;
 #pragma unroll
-            for (int p = 0; p < KM; p++)
-                if (p == pos) gv = gsem[p];
-            a.d_sem[i * k + m] = gv;
+                for (int p = 0; p < KM; p++)
+                    if (p == pos) gv = gsem[p];
+                a.d_sem[i * k + m] = gv;
+            }
         }
     }
 }

@@ -160,3 +160,32 @@ def test_capacity_needed_exceeds_small_capacity_per_oracle():
     pr = O.project(sc.means, sc.scales, sc.quats, sc.opacity, sc.cameras[0], O.config_array())
     keys, _, _ = O.reference_keys([pr], sc.cameras)
     assert len(keys) > 1000
+
+
+def test_planning_calls_validate_on_the_host(L):
+    grid = L.sgr_grid(40, 32, 12, 0.25, (ctypes.c_float * 3)(0.0, 0.0, 0.0))
+    samp = L.sgr_sampling(1.0, 5, 1.5, 1.5)
+    size = L.sgr_candidates_workspace_size(grid, samp)
+    assert size > 0 and size % 256 == 0
+    for bad_grid, bad_samp in ((L.sgr_grid(0, 32, 12, 0.25, (ctypes.c_float * 3)()), samp),
+                               (L.sgr_grid(40, 32, 12, 0.0, (ctypes.c_float * 3)()), samp),
+                               (grid, L.sgr_sampling(0.0, 5, 1.5, 1.5)),
+                               (grid, L.sgr_sampling(1.0, 0, 1.5, 1.5)),
+                               (grid, L.sgr_sampling(1.0, 5, 2.0, 1.0))):
+        assert L.sgr_candidates_workspace_size(bad_grid, bad_samp) == 0
+    buf = (ctypes.c_uint8 * (size + 512))()
+    addr = (ctypes.addressof(buf) + 255) // 256 * 256
+    cnt = np.zeros(1, np.int64).ctypes.data
+    # missing grid bytes / count, workspace too small
+    assert L.sgr_generate_candidates(grid, None, None, samp, 0, None, None, cnt, addr, size, None) == L.SGR_EINVAL
+    assert L.sgr_generate_candidates(grid, addr, None, samp, 0, None, None, None, addr, size, None) == L.SGR_EINVAL
+    assert L.sgr_generate_candidates(grid, addr, None, samp, 0, None, None, cnt, addr, size - 1, None) == L.SGR_EINVAL
+    assert L.sgr_generate_candidates(grid, addr, None, samp, 4, None, None, cnt, addr, size, None) == L.SGR_EINVAL
+    p = np.zeros(16, np.float64).ctypes.data
+    assert L.sgr_combine_scores(0, p, p, p, (0, 0, 0), 100, 0.005, p, p, p, None) == L.SGR_EINVAL
+    assert L.sgr_combine_scores(2, p, p, p, (0, 0, 0), 0, 0.005, p, p, p, None) == L.SGR_EINVAL
+    assert L.sgr_combine_scores(2, p, p, p, (0, 0, float("nan")), 100, 0.005, p, p, p, None) == L.SGR_EINVAL
+    assert L.sgr_combine_scores(2, None, p, p, (0, 0, 0), 100, 0.005, p, p, p, None) == L.SGR_EINVAL
+    g = L.sgr_gaussians(10, p, p, p, p, p, p, p)
+    assert L.sgr_score_poses(g, None, 2, p, _cfg(), 100, p, p, addr, size, None) == L.SGR_EINVAL
+    assert L.sgr_score_poses(g, _cams(_cam()), 2, None, _cfg(), 100, p, p, addr, size, None) == L.SGR_EINVAL
