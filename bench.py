@@ -298,6 +298,45 @@ def score_bench(args, torch, out):
     log("scoring batched", batched_ms, "ms plain", plain_ms, "ms")
 
 
+def plan_bench(args, torch, out):
+    """Next-best-view planning steps (Sec. 3.2) on the candidate-scene
+    Gaussians: candidates from the newly observed voxels of a synthetic
+    exploration map (10 x 8 x 3 m at 0.25 m; free within 2 m of (5, 4, 1.5)
+    before, within 4 m now for the coarse stage, 2.5 -> 3 m for the fine
+    stage), scored at 320 x 240 (fx = 160) and combined (Eq. 7)."""
+    import numpy as np_
+    from paper_2506_00225_amd import Gaussians, make_config, scenes
+    from paper_2506_00225_amd.planner import COARSE, FINE, Grid, Planner, sampling
+
+    sc = scenes.candidate_scene(n=args.score_n, nviews=1)
+    g = Gaussians.from_scene(sc)
+    vox, dims = 0.25, (40, 32, 12)
+    z, y, x = np_.meshgrid(np_.arange(dims[2]), np_.arange(dims[1]), np_.arange(dims[0]), indexing="ij")
+    centre = (np_.stack([x, y, z], -1) + 0.5) * vox
+    dist = np_.linalg.norm(centre - np_.array([5.0, 4.0, 1.5]), axis=-1).reshape(-1)
+    ball = lambda r: torch.from_numpy((dist <= r).astype(np_.uint8)).cuda()
+    intr = scenes.Camera(np_.eye(3, dtype=np_.float32), np_.zeros(3, np_.float32), 160.0, 160.0, 160.0, 120.0,
+                         320, 240)
+    pl = Planner(Grid(dims, vox, (0.0, 0.0, 0.0)), intr, make_config(sc.num_classes, sc.k), capacity=4096)
+    res = {}
+    for name, st, (r0, r1), zr in (("coarse", COARSE, (2.0, 4.0), (1.5, 1.5)),
+                                   ("fine", FINE, (2.5, 3.0), (0.5, 2.5))):
+        now, before = ball(r1), ball(r0)
+        samp = sampling(st["step"], st["directions"], *zr)
+        o = pl.step(g, now, before, samp, (5.0, 4.0, 1.5))  # warm-up, sizes the buffers
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            o = pl.step(g, now, before, samp, (5.0, 4.0, 1.5))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[name] = {"candidates": o["V"], "ms": round(ms, 3), "candidates_per_s": round(o["V"] / (ms * 1e-3), 1),
+                     "pruned": int(o["pruned"].sum()), "best": int(o["best"][0])}
+        log("plan", name, json.dumps(res[name]))
+    out["plan"] = res
+
+
 def cpu_baseline(sc, rows=None):
     """The FP64 oracle (as it stands) on the same keyframe and the same 1M
     Gaussians: projection of all Gaussians, forward render and analytic
@@ -345,6 +384,7 @@ def main():
     sc = mapping_bench(args, torch, out)
     if not args.no_score:
         score_bench(args, torch, out)
+        plan_bench(args, torch, out)
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         src = torch.ones(n, device="cuda")
@@ -376,7 +416,7 @@ def main():
     }
     for key in ("views_per_s_batched", "views_per_s_graph", "views_per_s_plain", "score_batched_ms", "score_graph_ms",
                 "score_graph_equal", "score_plain_ms",
-                "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views"):
+                "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views", "plan"):
         if key in out:
             line[key] = out[key]
     tuned = {k: out[k]["chosen"] for k in ("autotune_mapping", "autotune_score") if k in out and "chosen" in out[k]}

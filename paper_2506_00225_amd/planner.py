@@ -10,8 +10,9 @@
 3. sgr_combine_scores: the overall criterion with motion cost (Eq. 7),
    pruning, and the best candidate.
 
-The only host round trip is the candidate count after step 1, which sizes
-the scoring launch.
+Host round trips: the candidate count after step 1, which sizes the
+scoring launches, and a status read after each scoring launch of at most
+`chunk` views (it grows the key capacity when needed).
 """
 from __future__ import annotations
 
@@ -47,7 +48,8 @@ class Planner:
     """Holds the device buffers of a planning step for one grid, image size
     and config; buffers grow with the candidate count."""
 
-    def __init__(self, grid: Grid, intrinsics, cfg: L.sgr_config, capacity: int = 4096, device="cuda"):
+    def __init__(self, grid: Grid, intrinsics, cfg: L.sgr_config, capacity: int = 4096, device="cuda",
+                 chunk: int = 128):
         self.grid = grid
         self.cfg = cfg
         self.device = torch.device(device)
@@ -56,6 +58,7 @@ class Planner:
         self.intr[0] = L.sgr_camera((ctypes.c_float * 9)(1, 0, 0, 0, 1, 0, 0, 0, 1), (ctypes.c_float * 3)(0, 0, 0),
                                     float(c.fx), float(c.fy), float(c.cx), float(c.cy), int(c.width), int(c.height))
         self.pixels = int(c.width) * int(c.height)
+        self.chunk = int(chunk)  # views per scoring launch: bounds the per-(view, Gaussian) workspace
         self.count = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.key_capacity = 0
         self._grow(capacity)
@@ -97,25 +100,31 @@ class Planner:
         return V
 
     def score_views(self, g: Gaussians, V: int):
-        """Empty-pixel counts and entropy sums of the first V candidates."""
+        """Empty-pixel counts and entropy sums of the first V candidates, in
+        launches of at most `chunk` views."""
+        for v0 in range(0, V, self.chunk):
+            self._score_chunk(g, v0, min(self.chunk, V - v0))
+        return self.n_empty[:V], self.entropy[:V]
+
+    def _score_chunk(self, g: Gaussians, v0: int, nv: int):
         cams = self.intr
         for _ in range(3):
             cap = self.key_capacity or max(1 << 16, 4 * g.n)
-            size = L.sgr_workspace_size(g.n, _repeat(cams, V), V, self.cfg, cap)
+            size = L.sgr_workspace_size(g.n, _repeat(cams, nv), nv, self.cfg, cap)
             if size == 0:
                 raise L.SgrError(L.SGR_EINVAL, "sgr_workspace_size")
             if self.score_ws is None or self.score_ws.numel() < size:
                 self.score_ws = torch.empty(size, dtype=torch.uint8, device=self.device)
-            L.check(L.sgr_score_poses(g.c_struct(), cams, V, _ptr(self.poses), self.cfg, cap, _ptr(self.n_empty),
-                                      _ptr(self.entropy), _ptr(self.score_ws), self.score_ws.numel(), self.stream),
-                    "sgr_score_poses")
+            L.check(L.sgr_score_poses(g.c_struct(), cams, nv, _ptr(self.poses[v0:]), self.cfg, cap,
+                                      _ptr(self.n_empty[v0:]), _ptr(self.entropy[v0:]), _ptr(self.score_ws),
+                                      self.score_ws.numel(), self.stream), "sgr_score_poses")
             st, _, nk = L.sgr_read_status(_ptr(self.score_ws), self.stream)
             if st == L.SGR_ECAPACITY:
                 self.key_capacity = int(nk * 1.25) + 4096
                 continue
             L.check(st, "device status")
             self.key_capacity = cap
-            return self.n_empty[:V], self.entropy[:V]
+            return
         raise L.SgrError(L.SGR_ECAPACITY, "sgr_score_poses")
 
     def combine(self, V: int, current, prune_fraction: float = 0.005):
