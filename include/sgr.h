@@ -191,6 +191,18 @@ sgr_status sgr_render_forward(const sgr_gaussians *g, const sgr_camera *cams, in
                               void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * sgr_render_forward_dense -- sgr_render_forward with a dense semantic
+ * distribution per Gaussian: dense_sem[n][C] (device) takes the place of the
+ * top-k lists in Eq. 3, so every blend updates all C class sums.  It is the
+ * dense representation the sparse one is measured against (supplement
+ * S.2.2's runtime comparison).  Follows sgr_project and sgr_bin on the same
+ * workspace; g's top-k arrays are read by those calls only.
+ */
+sgr_status sgr_render_forward_dense(const sgr_gaussians *g, const float *dense_sem, const sgr_camera *cams,
+                                    int32_t num_views, const sgr_config *cfg, int64_t key_capacity,
+                                    const sgr_maps *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * sgr_render_backward -- gradient of sum_views sum_p <dL[v](p), maps[v](p)>
  * with respect to means, scales, quats, opacity, rgb and sem_val, walking
  * each pixel's blended list back to front from the saved final

@@ -90,7 +90,7 @@ class sgr_layout(ctypes.Structure):
 
 EXPORTS = (
     "sgr_workspace_size", "sgr_workspace_layout", "sgr_project", "sgr_bin", "sgr_render_forward",
-    "sgr_render_forward_loss",
+    "sgr_render_forward_loss", "sgr_render_forward_dense",
     "sgr_render_backward", "sgr_render_backward_tiles", "sgr_render_backward_gather", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
     "sgr_read_status", "sgr_status_string", "sgr_mapping_loss_grad", "sgr_adam_step",
     "sgr_candidates_workspace_size", "sgr_generate_candidates", "sgr_score_poses", "sgr_combine_scores",
@@ -124,6 +124,8 @@ def lib():
     L.sgr_render_forward_loss.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_maps),
                                           ctypes.POINTER(sgr_loss_view), ctypes.POINTER(sgr_loss_config), P, P, sz, P]
     L.sgr_render_forward_loss.restype = i32
+    L.sgr_render_forward_dense.argtypes = [g_p, P, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_maps), P, sz, P]
+    L.sgr_render_forward_dense.restype = i32
     L.sgr_render_backward.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_map_grads),
                                       ctypes.POINTER(sgr_grads), P, sz, P]
     L.sgr_render_backward.restype = i32
@@ -203,6 +205,12 @@ def sgr_render_forward_loss(g, cams, num_views, cfg, key_capacity, maps, views, 
                             workspace_bytes, stream):
     return lib().sgr_render_forward_loss(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity, maps,
                                          views, ctypes.byref(loss_cfg), loss, workspace, workspace_bytes, stream)
+
+
+def sgr_render_forward_dense(g, dense_sem, cams, num_views, cfg, key_capacity, maps, workspace, workspace_bytes,
+                             stream):
+    return lib().sgr_render_forward_dense(ctypes.byref(g), dense_sem, cams, num_views, ctypes.byref(cfg),
+                                          key_capacity, maps, workspace, workspace_bytes, stream)
 
 
 def sgr_render_backward(g, cams, num_views, cfg, key_capacity, dl, grads, workspace, workspace_bytes, stream):

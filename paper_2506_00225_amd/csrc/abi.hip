@@ -264,6 +264,16 @@ sgr_status sgr_render_forward(const sgr_gaussians* g, const sgr_camera* cams, in
     return launch_forward(P, out, (char*)workspace, (hipStream_t)stream);
 }
 
+sgr_status sgr_render_forward_dense(const sgr_gaussians* g, const float* dense_sem, const sgr_camera* cams,
+                                    int32_t num_views, const sgr_config* cfg, int64_t key_capacity,
+                                    const sgr_maps* out, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!out || !dense_sem) return SGR_EINVAL;
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    return launch_forward_dense(P, dense_sem, out, (char*)workspace, (hipStream_t)stream);
+}
+
 sgr_status sgr_render_forward_loss(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
                                    const sgr_config* cfg, int64_t key_capacity, const sgr_maps* out,
                                    const sgr_loss_view* lv, const sgr_loss_config* lc, double* loss, void* workspace,

@@ -79,6 +79,7 @@ sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* w
 sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const sgr_grads* out, char* ws,
                                   hipStream_t st);
 sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, char* ws, hipStream_t st);
+sgr_status launch_forward_dense(const Plan& P, const float* dense, const sgr_maps* out, char* ws, hipStream_t st);
 sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_loss_view* lv, const sgr_loss_config* lc,
                                double* loss, char* ws, hipStream_t st);
 sgr_status launch_score_maps(const float* sem, const int32_t* n_contrib, int W, int H, int C, uint32_t* n_empty,

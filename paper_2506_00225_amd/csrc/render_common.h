@@ -169,6 +169,26 @@ __device__ __forceinline__ float eval_alpha(const float4& q0, const float4& q1, 
     return fminf(amax, q1.w * g);
 }
 
+// Writes the tile's class-major LDS columns (one per pixel, stride 257) as
+// [H][W][C] rows: each tile row is one contiguous run of 16 C floats.
+__device__ __forceinline__ void write_rows_from_lds(const float* smem, float* out, const ViewDev& vw, int C, int tx,
+                                                    int ty) {
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
+    const int row_elems = kTile * C;
+    const int dl = kBlock / C, dc = kBlock % C;
+    for (int row = 0; row < hrows; row++) {
+        float* dst = out + ((int64_t)(y0 + row) * vw.width + x0) * C;
+        int lx = threadIdx.x / C, c = threadIdx.x % C;
+        for (int e = threadIdx.x; e < row_elems; e += kBlock) {
+            if (lx < wcols) dst[e] = smem[c * kAccStride + slot_of(lx, row)];
+            lx += dl;
+            c += dc;
+            if (c >= C) { c -= C; lx++; }
+        }
+    }
+}
+
 TileArgs make_tile_args(const Plan& P, char* ws);
 size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode);
 int device_cu_count();

@@ -315,26 +315,6 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     res.s = ss;
 }
 
-// Writes the tile's class-major LDS columns (one per pixel, stride 257) as
-// [H][W][C] rows: each tile row is one contiguous run of 16 C floats.
-__device__ __forceinline__ void write_rows_from_lds(const float* smem, float* out, const ViewDev& vw, int C, int tx,
-                                                    int ty) {
-    const int x0 = tx * kTile, y0 = ty * kTile;
-    const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
-    const int row_elems = kTile * C;
-    const int dl = kBlock / C, dc = kBlock % C;
-    for (int row = 0; row < hrows; row++) {
-        float* dst = out + ((int64_t)(y0 + row) * vw.width + x0) * C;
-        int lx = threadIdx.x / C, c = threadIdx.x % C;
-        for (int e = threadIdx.x; e < row_elems; e += kBlock) {
-            if (lx < wcols) dst[e] = smem[c * kAccStride + slot_of(lx, row)];
-            lx += dl;
-            c += dc;
-            if (c >= C) { c -= C; lx++; }
-        }
-    }
-}
-
 __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
 // The mapping loss of one pixel and its gradient with respect to the maps

@@ -174,6 +174,24 @@ class Frame:
                 "sgr_render_forward")
         return maps
 
+    def forward_dense(self, g: Gaussians, dense_sem: torch.Tensor, maps=None):
+        """Forward with a dense [n, C] semantic distribution per Gaussian
+        (all classes blended) instead of the top-k lists; after prepare()."""
+        maps = maps if maps is not None else self.alloc_maps()
+        dense_sem = dense_sem.to(device=self.device, dtype=torch.float32).contiguous()
+        C = self.cfg.num_classes
+        if dense_sem.shape != (self.n, C):
+            raise ValueError(f"dense_sem must be [{self.n}, {C}]")
+        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C, "t_final": 1, "n_contrib": 1}
+        ptrs = {key: self._view_ptrs(maps.get(key), cols[key], 4) for key in cols}
+        arr = (L.sgr_maps * self.V)()
+        for v in range(self.V):
+            arr[v] = L.sgr_maps(ptrs["rgb"][v], ptrs["depth"][v], ptrs["sil"][v], ptrs["sem"][v],
+                                ptrs["t_final"][v], ptrs["n_contrib"][v])
+        L.check(L.sgr_render_forward_dense(g.c_struct(), _ptr(dense_sem), *self._args(), arr, _ptr(self.ws),
+                                           self.ws.numel(), self.stream), "sgr_render_forward_dense")
+        return maps
+
     def forward_loss(self, g: Gaussians, targets, loss_cfg=None, maps=None, grads=None, sparse_sem=False):
         """Forward render with the mapping loss fused into the same launch.
 

@@ -1,0 +1,57 @@
+"""The dense-semantics forward (every Gaussian carries all C classes)
+against the oracle, and against the top-k forward on the same distributions."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2506_00225_amd import Gaussians, scenes
+
+import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_dense_forward_matches_oracle():
+    print("[case] dense vs oracle", flush=True)
+    sc = scenes.tiny_scene(seed=13)
+    C = sc.num_classes
+    rng = np.random.default_rng(4)
+    dense = rng.dirichlet(np.ones(C), size=sc.n).astype(np.float32)
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc)
+    fr.prepare(g)
+    maps = fr.forward_dense(g, torch.from_numpy(dense))
+    torch.cuda.synchronize()
+    got = {k: fr.split(v)[0].cpu().numpy() for k, v in maps.items()}
+    # the oracle with every class listed: k = C, indices 0..C-1, values the dense rows
+    arrays = (sc.means, sc.scales, sc.quats, sc.opacity, sc.rgb, dense,
+              np.tile(np.arange(C, dtype=np.uint8), (sc.n, 1)))
+    _, want = O.forward(arrays, sc.cameras[0], U.oracle_cfg(), C)
+    U.compare_maps(got, want, want["flags"])
+
+
+def test_dense_forward_equals_top_k_forward_on_sparse_rows():
+    """Dense rows that are zero outside each Gaussian's top-k give the bits
+    of the top-k forward (adding v * w = 0 leaves a class sum unchanged)."""
+    print("[case] dense vs sparse", flush=True)
+    sc = scenes.room_scene(seed=2, n=60_000, targets=False)
+    cam = sc.cameras[0]
+    sc.cameras = [scenes.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx - 400, cam.cy - 190, 400, 300)]
+    C = sc.num_classes
+    dense = np.zeros((sc.n, C), np.float32)
+    np.put_along_axis(dense, sc.sem_idx.astype(np.int64), sc.sem_val, axis=1)
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc)
+    fr.prepare(g)
+    a = {k: v.clone() for k, v in fr.forward(g).items()}
+    b = fr.forward_dense(g, torch.from_numpy(dense))
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
