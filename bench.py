@@ -337,6 +337,41 @@ def plan_bench(args, torch, out):
     out["plan"] = res
 
 
+def dense_bench(args, torch, out):
+    """Dense vs top-k semantic rendering (supplement S.2.2's comparison): one
+    forward at 600 x 340 of a room with about 204k Gaussians in view, C = 102,
+    with the top-k lists (k = 16) and with a dense 102-class row per Gaussian."""
+    from paper_2506_00225_amd import Frame, Gaussians, make_config, scenes
+
+    sc = scenes.room_scene(seed=5, n=730_000, targets=False)
+    cam = sc.cameras[0]
+    half = scenes.Camera(cam.R, cam.t, cam.fx / 2, cam.fy / 2, cam.cx / 2, cam.cy / 2, cam.width // 2,
+                         cam.height // 2)
+    g = Gaussians.from_scene(sc)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    dense = torch.rand((sc.n, sc.num_classes), generator=gen, device="cuda")
+    dense /= dense.sum(1, keepdim=True)
+    fr = Frame(sc.n, [half], make_config(sc.num_classes, sc.k))
+    fr.prepare(g, check=True)
+    _, nvis, _ = fr.status()
+    maps = fr.alloc_maps()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"width": half.width, "height": half.height, "gaussians": sc.n, "visible": nvis, "classes": sc.num_classes}
+    for name, fn in (("sparse_top16_ms", lambda: fr.forward(g, maps)),
+                     ("dense_ms", lambda: fr.forward_dense(g, dense, maps))):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = round(e0.elapsed_time(e1) / 10, 4)
+    res["dense_over_sparse"] = round(res["dense_ms"] / res["sparse_top16_ms"], 2)
+    log("dense vs sparse", json.dumps(res))
+    out["dense_vs_sparse"] = res
+
+
 def cpu_baseline(sc, rows=None):
     """The FP64 oracle (as it stands) on the same keyframe and the same 1M
     Gaussians: projection of all Gaussians, forward render and analytic
@@ -385,6 +420,7 @@ def main():
     if not args.no_score:
         score_bench(args, torch, out)
         plan_bench(args, torch, out)
+        dense_bench(args, torch, out)
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         src = torch.ones(n, device="cuda")
@@ -416,7 +452,7 @@ def main():
     }
     for key in ("views_per_s_batched", "views_per_s_graph", "views_per_s_plain", "score_batched_ms", "score_graph_ms",
                 "score_graph_equal", "score_plain_ms",
-                "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views", "plan"):
+                "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views", "plan", "dense_vs_sparse"):
         if key in out:
             line[key] = out[key]
     tuned = {k: out[k]["chosen"] for k in ("autotune_mapping", "autotune_score") if k in out and "chosen" in out[k]}
