@@ -354,6 +354,31 @@ typedef struct {
 sgr_status sgr_adam_step(const sgr_adam_segment *segments, int32_t num_segments, float lr, float beta1, float beta2,
                          float eps, int32_t step, void *stream);
 
+/* ------------------------------------------------------------------ sparse semantic state
+ * Sec. 3.1, sparse semantic representation: a Gaussian keeps the top-k
+ * classes of the distribution it is initialised from; later observations
+ * update the kept values with the indices fixed. */
+
+/*
+ * sgr_topk_select -- for Gaussian i, the k classes with the highest
+ * probability in row pixel[i] of dist ([rows][num_classes], device; pixel
+ * NULL: row i), in decreasing order, equal values keeping the smaller class
+ * first and NaN counting as -inf.  Writes sem_idx[n][k] and sem_val[n][k]
+ * (the probabilities, -inf stored as 0; with renormalize != 0 divided by
+ * their sum).  k <= num_classes <= 256, k <= 32.
+ */
+sgr_status sgr_topk_select(const float *dist, const int64_t *pixel, int64_t n, int32_t num_classes, int32_t k,
+                           int32_t renormalize, uint8_t *sem_idx, float *sem_val, void *stream);
+
+/*
+ * sgr_topk_update -- fixed-index update of the kept values toward a new
+ * observation: sem_val[i][m] = (1 - rate) sem_val[i][m]
+ * + rate * dist[pixel[i]][sem_idx[i][m]] (an index >= num_classes reads 0).
+ * 0 <= rate <= 1.
+ */
+sgr_status sgr_topk_update(const float *dist, const int64_t *pixel, int64_t n, int32_t num_classes, int32_t k,
+                           const uint8_t *sem_idx, float rate, float *sem_val, void *stream);
+
 /* ------------------------------------------------------------------ planning
  * Next-best-view selection (Sec. 3.2): candidate poses from the newly
  * observed voxels of the exploration map, their scores (sgr_score_poses,

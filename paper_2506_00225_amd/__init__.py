@@ -9,7 +9,7 @@ marshals arguments and takes device memory and streams from PyTorch.
 from . import _lib, autotune
 from ._lib import SgrError
 from .rasterizer import (FusedAdam, Frame, Gaussians, camera_array, loss_config, make_config, mapping_loss_grad,
-                         render, score_maps)
+                         render, score_maps, topk_select, topk_update)
 
 __all__ = ["FusedAdam", "Frame", "Gaussians", "SgrError", "autotune", "camera_array", "loss_config", "make_config",
-           "mapping_loss_grad", "render", "score_maps", "_lib"]
+           "mapping_loss_grad", "render", "score_maps", "topk_select", "topk_update", "_lib"]

@@ -94,6 +94,7 @@ EXPORTS = (
     "sgr_render_backward", "sgr_render_backward_tiles", "sgr_render_backward_gather", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
     "sgr_read_status", "sgr_status_string", "sgr_mapping_loss_grad", "sgr_adam_step",
     "sgr_candidates_workspace_size", "sgr_generate_candidates", "sgr_score_poses", "sgr_combine_scores",
+    "sgr_topk_select", "sgr_topk_update",
 )
 
 _lib = None
@@ -155,6 +156,10 @@ def lib():
     L.sgr_score_poses.restype = i32
     L.sgr_combine_scores.argtypes = [i32, P, P, P, ctypes.POINTER(ctypes.c_float), i64, ctypes.c_float, P, P, P, P]
     L.sgr_combine_scores.restype = i32
+    L.sgr_topk_select.argtypes = [P, P, i64, i32, i32, i32, P, P, P]
+    L.sgr_topk_select.restype = i32
+    L.sgr_topk_update.argtypes = [P, P, i64, i32, i32, P, ctypes.c_float, P, P]
+    L.sgr_topk_update.restype = i32
     L.sgr_status_string.argtypes = [i32]
     L.sgr_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -285,3 +290,11 @@ def sgr_combine_scores(num_views, n_empty, entropy_sum, positions, current, pixe
     cur = (ctypes.c_float * 3)(*[float(x) for x in current])
     return lib().sgr_combine_scores(num_views, n_empty, entropy_sum, positions, cur, pixels, prune_fraction, score,
                                     pruned, best, stream)
+
+
+def sgr_topk_select(dist, pixel, n, num_classes, k, renormalize, sem_idx, sem_val, stream):
+    return lib().sgr_topk_select(dist, pixel, n, num_classes, k, renormalize, sem_idx, sem_val, stream)
+
+
+def sgr_topk_update(dist, pixel, n, num_classes, k, sem_idx, rate, sem_val, stream):
+    return lib().sgr_topk_update(dist, pixel, n, num_classes, k, sem_idx, rate, sem_val, stream)

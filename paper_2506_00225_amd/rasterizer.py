@@ -432,3 +432,35 @@ class FusedAdam:
         stream = ctypes.c_void_p(torch.cuda.current_stream(self.m[0].device).cuda_stream)
         L.check(L.sgr_adam_step(self.segs, len(self.groups), self.lr, self.b1, self.b2, self.eps, self.t, stream),
                 "sgr_adam_step")
+
+
+def topk_select(dist: torch.Tensor, k: int, pixel: torch.Tensor | None = None, renormalize: bool = False):
+    """Top-k (class, probability) of each row of dist [rows, C] (or of rows
+    pixel[i]): new Gaussians' sparse semantics.  Returns (sem_idx uint8
+    [n, k], sem_val float32 [n, k])."""
+    dist = dist.to(torch.float32).contiguous()
+    C = int(dist.shape[-1])
+    dist2 = dist.reshape(-1, C)
+    if pixel is not None:
+        pixel = pixel.to(device=dist.device, dtype=torch.int64).contiguous()
+    n = int(pixel.numel()) if pixel is not None else int(dist2.shape[0])
+    idx = torch.empty((n, k), dtype=torch.uint8, device=dist.device)
+    val = torch.empty((n, k), dtype=torch.float32, device=dist.device)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dist.device).cuda_stream)
+    L.check(L.sgr_topk_select(_ptr(dist2), _ptr(pixel), n, C, int(k), int(bool(renormalize)), _ptr(idx), _ptr(val),
+                              stream), "sgr_topk_select")
+    return idx, val
+
+
+def topk_update(dist: torch.Tensor, sem_idx: torch.Tensor, sem_val: torch.Tensor, rate: float,
+                pixel: torch.Tensor | None = None):
+    """In place: sem_val <- (1 - rate) sem_val + rate * dist[row][sem_idx]."""
+    dist = dist.to(torch.float32).contiguous()
+    C = int(dist.shape[-1])
+    if pixel is not None:
+        pixel = pixel.to(device=dist.device, dtype=torch.int64).contiguous()
+    n, k = int(sem_idx.shape[0]), int(sem_idx.shape[1])
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dist.device).cuda_stream)
+    L.check(L.sgr_topk_update(_ptr(dist.reshape(-1, C)), _ptr(pixel), n, C, k, _ptr(sem_idx.contiguous()),
+                              float(rate), _ptr(sem_val), stream), "sgr_topk_update")
+    return sem_val
