@@ -106,12 +106,8 @@ def mapping_bench(args, torch, out):
     ncon = {"n_contrib": torch.empty(P, dtype=torch.int32, device=dev)}
     losses = torch.zeros(args.steps + args.warmup, dtype=torch.float64, device=dev)
 
-    if not args.no_tune:
-        gen = torch.Generator(device=dev).manual_seed(0)
-        tg = {"rgb": torch.randn(P, 3, generator=gen, device=dev), "depth": torch.randn(P, generator=gen, device=dev),
-              "sil": torch.randn(P, generator=gen, device=dev), "sem_label": label,
-              "sem_at_label": torch.randn(P, generator=gen, device=dev)}
-        rep = autotune.tune_mapping(fr, g, grads=tg, reps=3)
+    if not args.no_tune:  # times the fused forward + loss and the backward, as the step runs them
+        rep = autotune.tune_mapping(fr, g, reps=3, targets=targets, loss_cfg=lcfg)
         out["autotune_mapping"] = rep
         log("autotune mapping", json.dumps(rep["candidates"]))
 

@@ -83,6 +83,12 @@ typedef struct {
                                      run of tiles, sharing its L2) or SGR_TILES_LINEAR. */
     int32_t score_workgroups;     /* workgroups of the persistent scoring launch; 0 = as many
                                      as are resident at once.  Speed only. */
+    int32_t sem_passes;           /* LDS class sums only: 0 = automatic, or 1..4 class ranges
+                                     composited one after another (a tile's geometry is
+                                     recomposited per range; a workgroup needs 1/passes of the
+                                     class-sum LDS, so more fit on a CU).  Speed only.  The fused
+                                     loss uses one pass whenever a view has a dense semantic
+                                     target or asks for the dense semantic gradient. */
 } sgr_config;
 
 enum { SGR_ACC_AUTO = 0, SGR_ACC_LDS = 1, SGR_ACC_REGISTERS = 2 };

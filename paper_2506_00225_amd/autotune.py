@@ -5,7 +5,10 @@ The knobs live in `sgr_config` and are read by the library on every call:
 * ``sem_accumulators``: per-pixel class sums in LDS or in registers (C <= 128);
 * ``tile_order``: XCD-contiguous runs of tiles (each XCD's L2 sees
   neighbouring tiles, which share Gaussians) or plain linear order;
-* ``score_workgroups``: size of the persistent scoring grid.
+* ``score_workgroups``: size of the persistent scoring grid;
+* ``sem_passes``: with the class sums in LDS, how many class ranges a tile
+  is composited in (1/passes of the LDS each, so more workgroups share a CU,
+  against recompositing the geometry once per range).
 
 Every candidate is run on the caller's own frame and data, timed with HIP
 events on the current stream, and its outputs are compared bit for bit with
@@ -32,12 +35,16 @@ def _shape_key(frame, what: str):
     return (what, frame.n, int(frame.cfg.num_classes), int(frame.cfg.top_k), tuple(frame.sizes))
 
 
+KNOBS = ("sem_accumulators", "tile_order", "score_workgroups", "sem_passes")
+
+
 def _knobs(cfg):
-    return (int(cfg.sem_accumulators), int(cfg.tile_order), int(cfg.score_workgroups))
+    return tuple(int(getattr(cfg, k)) for k in KNOBS)
 
 
 def _set(cfg, knobs):
-    cfg.sem_accumulators, cfg.tile_order, cfg.score_workgroups = knobs
+    for k, v in zip(KNOBS, knobs):
+        setattr(cfg, k, v)
 
 
 def _time(fn, reps: int) -> float:
@@ -66,58 +73,84 @@ def _search(frame, candidates, run, reps: int, what: str):
     try:
         for knobs in candidates:
             _set(frame.cfg, knobs)
-            outs = _snapshot(run())
+            try:
+                outs = _snapshot(run())
+            except L.SgrError as e:  # e.g. the class sums of one pass exceed the LDS
+                if e.status != L.SGR_EUNSUPPORTED:
+                    raise
+                continue
             if ref is None:
                 ref = outs
             elif not _same(ref, outs):
                 raise RuntimeError(f"autotune({what}): candidate {knobs} changed the outputs")
             ms = _time(run, reps)
-            report.append({"sem_accumulators": knobs[0], "tile_order": knobs[1], "score_workgroups": knobs[2],
-                           "ms": round(ms, 4)})
+            report.append(dict(zip(KNOBS, knobs), ms=round(ms, 4)))
             if best is None or ms < best[1]:
                 best = (knobs, ms, len(report) - 1)
     except Exception:
         _set(frame.cfg, original)
         raise
+    if best is None:
+        _set(frame.cfg, original)
+        raise L.SgrError(L.SGR_EUNSUPPORTED, f"autotune({what}): no candidate runs")
     _set(frame.cfg, best[0])
     _CACHE[_shape_key(frame, what)] = best[0]
     return {"what": what, "chosen": report[best[2]], "candidates": report}
 
 
-def _acc_choices(cfg):
-    return [L.SGR_ACC_LDS] + ([L.SGR_ACC_REGISTERS] if cfg.num_classes <= 128 else [])
+def _placements(cfg):
+    """(sem_accumulators, sem_passes) pairs: LDS in 1..3 class ranges, and
+    registers when C <= 128."""
+    out = [(L.SGR_ACC_LDS, p) for p in (1, 2, 3)]
+    return out + ([(L.SGR_ACC_REGISTERS, 0)] if cfg.num_classes <= 128 else [])
 
 
-def tune_mapping(frame, g, grads: dict | None = None, reps: int = 5):
-    """Chooses accumulator placement and tile order for forward + backward
-    of `frame` on Gaussians `g` (already projected and binned).  `grads`
-    are the incoming map gradients (random ones if None).  Returns a report."""
-    key = _shape_key(frame, "mapping")
+def tune_mapping(frame, g, grads: dict | None = None, reps: int = 5, targets=None, loss_cfg=None):
+    """Chooses accumulator placement, class passes and tile order for the
+    mapping pass of `frame` on Gaussians `g` (already projected and binned).
+    With `targets` (as for Frame.forward_loss) the timed pass is what a
+    mapping iteration runs: the fused forward + loss, then the backward of
+    its gradients (one class per pixel when every target is a label map).
+    Otherwise it is forward, then backward of `grads` (random if None).
+    Returns a report."""
+    what = "mapping" if targets is None else "mapping_loss"
+    key = _shape_key(frame, what)
     if key in _CACHE:
         _set(frame.cfg, _CACHE[key])
-        return {"what": "mapping", "cached": _CACHE[key]}
-    maps = frame.alloc_maps()
-    if grads is None:
-        gen = torch.Generator(device=frame.device).manual_seed(0)
-        grads = {k: torch.randn(maps[k].shape, generator=gen, device=frame.device)
-                 for k in ("rgb", "depth", "sil", "sem")}
+        return {"what": what, "cached": _CACHE[key]}
     out = {name: torch.empty_like(getattr(g, name)) for name in
            ("means", "scales", "quats", "opacity", "rgb", "sem_val")}
+    if targets is not None:
+        tl = [targets] if isinstance(targets, dict) else list(targets)
+        sparse = all(t.get("label") is not None and t.get("sem") is None for t in tl)
+        buf = {}
 
-    def run():
-        frame.forward(g, maps)
-        frame.backward(g, dict(grads), out)
-        return list(maps.values()) + list(out.values())
+        def run():
+            gr, loss = frame.forward_loss(g, targets, loss_cfg, grads=buf.get("g"), sparse_sem=sparse)
+            buf["g"] = gr
+            frame.backward(g, dict(gr), out)
+            return [loss] + list(gr.values()) + list(out.values())
+    else:
+        maps = frame.alloc_maps()
+        if grads is None:
+            gen = torch.Generator(device=frame.device).manual_seed(0)
+            grads = {k: torch.randn(maps[k].shape, generator=gen, device=frame.device)
+                     for k in ("rgb", "depth", "sil", "sem")}
+
+        def run():
+            frame.forward(g, maps)
+            frame.backward(g, dict(grads), out)
+            return list(maps.values()) + list(out.values())
 
     sw = int(frame.cfg.score_workgroups)
-    cands = [(acc, order, sw) for acc, order in itertools.product(_acc_choices(frame.cfg),
-                                                                   (L.SGR_TILES_XCD, L.SGR_TILES_LINEAR))]
-    return _search(frame, cands, run, reps, "mapping")
+    cands = [(acc, order, sw, passes) for (acc, passes), order in
+             itertools.product(_placements(frame.cfg), (L.SGR_TILES_XCD, L.SGR_TILES_LINEAR))]
+    return _search(frame, cands, run, reps, what)
 
 
 def tune_score(frame, g, reps: int = 3, workgroups=(0, 512, 1024, 2048)):
-    """Chooses accumulator placement, tile order and the persistent grid
-    for `frame.score(g)`.  Returns a report."""
+    """Chooses accumulator placement, class passes, tile order and the
+    persistent grid for `frame.score(g)`.  Returns a report."""
     key = _shape_key(frame, "score")
     if key in _CACHE:
         _set(frame.cfg, _CACHE[key])
@@ -129,7 +162,8 @@ def tune_score(frame, g, reps: int = 3, workgroups=(0, 512, 1024, 2048)):
         frame.score(g, ne, hs)
         return [ne, hs]
 
-    cands = list(itertools.product(_acc_choices(frame.cfg), (L.SGR_TILES_XCD, L.SGR_TILES_LINEAR), workgroups))
+    cands = [(acc, order, wg, passes) for (acc, passes), order, wg in
+             itertools.product(_placements(frame.cfg), (L.SGR_TILES_XCD, L.SGR_TILES_LINEAR), workgroups)]
     return _search(frame, cands, run, reps, "score")
 
 

@@ -33,6 +33,7 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     if (cfg->sem_accumulators == SGR_ACC_REGISTERS && cfg->num_classes > kMaxRegC) return SGR_EUNSUPPORTED;
     if (cfg->tile_order < SGR_TILES_AUTO || cfg->tile_order > SGR_TILES_LINEAR || cfg->score_workgroups < 0)
         return SGR_EINVAL;
+    if (cfg->sem_passes < 0 || cfg->sem_passes > kMaxPasses) return SGR_EINVAL;
     const int64_t vn = n * (int64_t)V;
     if (vn >= (int64_t)1 << 31 || cap >= (int64_t)1 << 31) return SGR_EINVAL;
     P->n = n;

@@ -5,6 +5,26 @@
 
 namespace sgr {
 
+// Classes [lo, lo + cnt) of the tile's pixels from LDS rows (stride 257)
+// into the [H][W][C] map: each pixel's run of cnt classes is contiguous.
+__device__ __forceinline__ void write_rows_range(const float* smem, float* out, const ViewDev& vw, int C, int lo,
+                                                 int cnt, int tx, int ty) {
+    const int x0 = tx * kTile, y0 = ty * kTile;
+    const int wcols = min(kTile, vw.width - x0), hrows = min(kTile, vw.height - y0);
+    const int row_elems = kTile * cnt;
+    const int dl = kBlock / cnt, dc = kBlock % cnt;
+    for (int row = 0; row < hrows; row++) {
+        float* dst = out + ((int64_t)(y0 + row) * vw.width + x0) * C + lo;
+        int lx = threadIdx.x / cnt, c = threadIdx.x % cnt;
+        for (int e = threadIdx.x; e < row_elems; e += kBlock) {
+            if (lx < wcols) dst[lx * C + c] = smem[c * kAccStride + slot_of(lx, row)];
+            lx += dl;
+            c += dc;
+            if (c >= cnt) { c -= cnt; lx++; }
+        }
+    }
+}
+
 // Per-tile compositing.  One thread per pixel (256 = 4 wave64).  Batches of
 // the tile's front-to-back list are staged in LDS; every lane reads the
 // same record (an LDS broadcast).  Semantic accumulators (SEM):
@@ -16,15 +36,25 @@ namespace sgr {
 //      waves fit on a CU.
 // Every mode adds a blend's values in the same order with the same fused
 // multiply-add, so they give the same bits.
-template <int KT, int SEM, int NB>
+//
+// NPASS > 1 (SEM == 1): the LDS holds `rows` class rows and this call
+// accumulates only classes [lo, lo + cnt); the caller walks the tile once
+// per class range.  Half the LDS per workgroup lets two workgroups share a
+// CU, at the price of recompositing the geometry in every pass.
+template <int KT, int SEM, int NB, int NPASS = 1>
 __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float* smem, TileResult& res,
-                                               RegAcc<NB>& racc) {
+                                               RegAcc<NB>& racc, int lo = 0, int cnt = 0, int rows = 0) {
     const int tid = threadIdx.x;
     const int k = KT > 0 ? KT : a.k;
     const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;  // index words per Gaussian
     const int C = a.C;
-    float* acc = smem;                                   // [C][257] when SEM == 1
-    float* bat = smem + (SEM == 1 ? acc_floats(C) : 0);
+    if constexpr (NPASS == 1) {
+        lo = 0;
+        cnt = C;
+        rows = C;
+    }
+    float* acc = smem;                                   // [rows][257] when SEM == 1
+    float* bat = smem + (SEM == 1 ? acc_floats(rows) : 0);
     float4* s_r0 = (float4*)bat;
     float4* s_r1 = s_r0 + kFwdBatch;
     float4* s_r2 = s_r1 + kFwdBatch;
@@ -42,7 +72,7 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     const uint32_t start = rg.x, end = rg.y;
 
     if (SEM == 1)
-        for (int i = tid; i < C * kAccStride; i += kBlock) acc[i] = 0.f;
+        for (int i = tid; i < cnt * kAccStride; i += kBlock) acc[i] = 0.f;
     if constexpr (SEM == 3) reg_zero(racc);
     float* gacc = nullptr;  // SEM == 2: the thread's own row of the output map
     if (SEM == 2 && inside && a.maps[v].sem) {
@@ -271,13 +301,31 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
 #pragma unroll
                             for (int m = 0; m < KK; m++) vals[m] = sv[m];
                         }
+                        if constexpr (NPASS == 1) {
 #pragma unroll
-                        for (int m = 0; m < KK; m++) cls[m] = ((si[m >> 2] >> (8 * (m & 3))) & 0xffu) * kAccStride + tid;
-                        float cur[KK];
+                            for (int m = 0; m < KK; m++)
+                                cls[m] = ((si[m >> 2] >> (8 * (m & 3))) & 0xffu) * kAccStride + tid;
+                            float cur[KK];
 #pragma unroll
-                        for (int m = 0; m < KK; m++) cur[m] = acc[cls[m]];
+                            for (int m = 0; m < KK; m++) cur[m] = acc[cls[m]];
 #pragma unroll
-                        for (int m = 0; m < KK; m++) acc[cls[m]] = fmaf(vals[m], w, cur[m]);
+                            for (int m = 0; m < KK; m++) acc[cls[m]] = fmaf(vals[m], w, cur[m]);
+                        } else {
+                            bool mine[KK];  // class in this pass's range (wave-uniform)
+#pragma unroll
+                            for (int m = 0; m < KK; m++) {
+                                const uint32_t rel = ((si[m >> 2] >> (8 * (m & 3))) & 0xffu) - (uint32_t)lo;
+                                mine[m] = rel < (uint32_t)cnt;
+                                cls[m] = rel * kAccStride + tid;
+                            }
+                            float cur[KK];
+#pragma unroll
+                            for (int m = 0; m < KK; m++)
+                                if (mine[m]) cur[m] = acc[cls[m]];
+#pragma unroll
+                            for (int m = 0; m < KK; m++)
+                                if (mine[m]) acc[cls[m]] = fmaf(vals[m], w, cur[m]);
+                        }
                     } else {
 #pragma unroll
                         for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
@@ -288,8 +336,13 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                                 const int m = mw * 4 + b;
                                 if (m < k) {
                                     const uint32_t cl = (word >> (8 * b)) & 0xffu;
-                                    if (SEM == 1) acc[cl * kAccStride + tid] = fmaf(sv[m], w, acc[cl * kAccStride + tid]);
-                                    else if (gacc) gacc[cl] = fmaf(sv[m], w, gacc[cl]);
+                                    if (SEM == 1) {
+                                        const uint32_t rel = cl - (uint32_t)lo;
+                                        if (NPASS == 1 || rel < (uint32_t)cnt)
+                                            acc[rel * kAccStride + tid] = fmaf(sv[m], w, acc[rel * kAccStride + tid]);
+                                    } else if (gacc) {
+                                        gacc[cl] = fmaf(sv[m], w, gacc[cl]);
+                                    }
                                 }
                             }
                         }
@@ -323,9 +376,10 @@ __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f
 // sums, SEM == 1): each thread turns its own class column into dL/dP, from
 // a dense target g (entropy mask, Hellinger + cosine) or a label
 // (cross-entropy).  The tile's summed loss goes to tile_loss[gt].
-template <int SEM>
+template <int SEM, int NPASS = 1>
 __device__ __forceinline__ void loss_epilogue(const TileArgs& a, const LossK& lk, const TileResult& r,
-                                              const ViewDev& vw, int gt, float* smem) {
+                                              const ViewDev& vw, int gt, float* smem, int lab = -1,
+                                              float q_label = 0.f) {
     __shared__ double s_part[kBlock / 64];
     const int tid = threadIdx.x;
     const LossPtrs& L = lk.views[r.v];
@@ -357,7 +411,23 @@ __device__ __forceinline__ void loss_epilogue(const TileArgs& a, const LossK& lk
         if (L.g_sil) L.g_sil[pix] = lk.w_sil * sgnf(rs) * inv_p;
         lpx = (double)lg;
     }
-    if constexpr (SEM == 1) {
+    if constexpr (SEM == 1 && NPASS > 1) {
+        // class passes: only the cross-entropy term, from the label's class
+        // sum captured in its pass; its gradient in the one-class form
+        if (r.inside && L.label) {
+            float gl = 0.f;
+            if (lab >= 0 && lab < a.C) {
+                lpx -= (double)(lk.w_sem * logf(fmaxf(q_label, lk.ce_floor)));
+                gl = q_label > lk.ce_floor ? -lk.w_sem * inv_p / q_label : 0.f;
+            } else {
+                atomicOr(&a.counters[kStatus], Plan::kBadIndex);
+            }
+            if (L.g_sem_at_label) L.g_sem_at_label[pix] = gl;
+        } else if (r.inside && L.g_sem_at_label) {
+            L.g_sem_at_label[pix] = 0.f;
+        }
+    }
+    if constexpr (SEM == 1 && NPASS == 1) {
         const int C = a.C;
         __syncthreads();  // class sums final
         if (a.maps[r.v].sem) {
@@ -458,7 +528,7 @@ __device__ __forceinline__ void write_sem_block(const v32f& acc, float* buf, flo
     }
 }
 
-template <int KT, int SEM, int NB, bool LOSS>
+template <int KT, int SEM, int NB, bool LOSS, int NPASS = 1>
 __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk) {
     extern __shared__ __align__(16) float smem[];
     const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
@@ -467,7 +537,27 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk
     TileResult r;
     v32f acc0, acc1, acc2, acc3;
     RegAcc<NB> racc{acc0, acc1, acc2, acc3};
-    composite_tile<KT, SEM, NB>(a, gt, smem, r, racc);
+    int lab = -1;        // fused cross-entropy under class passes: the pixel's label ...
+    float q_label = 0.f; // ... and its class sum, taken in the pass that holds it
+    if constexpr (NPASS == 1) {
+        composite_tile<KT, SEM, NB>(a, gt, smem, r, racc);
+    } else {
+        static_assert(SEM == 1, "class passes use the LDS class sums");
+        const int C = a.C, cpp = (C + NPASS - 1) / NPASS;
+        for (int pass = 0; pass < NPASS; pass++) {
+            const int lo = pass * cpp, cnt = min(cpp, C - lo);
+            composite_tile<KT, 1, NB, NPASS>(a, gt, smem, r, racc, lo, cnt, cpp);
+            __syncthreads();
+            float* out = a.maps[r.v].sem;
+            if (out) write_rows_range(smem, out, a.views[r.v], C, lo, cnt, r.tx, r.ty);
+            if constexpr (LOSS) {
+                if (pass == 0 && r.inside && lk.views[r.v].label)
+                    lab = lk.views[r.v].label[(int64_t)r.py * a.views[r.v].width + r.px];
+                if ((uint32_t)(lab - lo) < (uint32_t)cnt) q_label = smem[(lab - lo) * kAccStride + threadIdx.x];
+            }
+            __syncthreads();  // before the next pass clears the rows
+        }
+    }
     const ViewDev& vw = a.views[r.v];
     if (r.inside) {
         const int64_t pix = (int64_t)r.py * vw.width + r.px;
@@ -481,10 +571,10 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk
         a.pix_last[vw.pix_off + pix] = r.last;
     }
     if constexpr (LOSS) {
-        loss_epilogue<SEM>(a, lk, r, vw, gt, smem);
+        loss_epilogue<SEM, NPASS>(a, lk, r, vw, gt, smem, lab, q_label);
         return;
     }
-    if (SEM == 1) {
+    if (SEM == 1 && NPASS == 1) {
         float* out = a.maps[r.v].sem;
         if (!out) return;
         __syncthreads();
@@ -535,7 +625,7 @@ __device__ __forceinline__ void entropy_terms(const v32f& acc, int C, float lg_l
     }
 }
 
-template <int KT, int SEM, int NB>
+template <int KT, int SEM, int NB, int NPASS = 1>
 __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, ScoreOut so) {
     extern __shared__ __align__(16) float smem[];
     __shared__ double s_h[4];
@@ -556,9 +646,27 @@ __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, Sc
         TileResult r;
         v32f acc0, acc1, acc2, acc3;
         RegAcc<NB> racc{acc0, acc1, acc2, acc3};
+        double h = 0.0;
+        if constexpr (NPASS > 1) {
+            // class passes: Z and sum x log2 x grow pass by pass, in class order
+            const int cpp = (C + NPASS - 1) / NPASS;
+            float Z = 0.f, sxl = 0.f;
+            for (int pass = 0; pass < NPASS; pass++) {
+                const int lo = pass * cpp, cnt = min(cpp, C - lo);
+                composite_tile<KT, 1, NB, NPASS>(a, gt, smem, r, racc, lo, cnt, cpp);
+                if (r.inside)
+                    for (int c = 0; c < cnt; c++) {
+                        const float x = fminf(fmaxf(smem[c * kAccStride + tid], 0.001f), 1.f);
+                        const float lx = (x == 0.001f) ? lg_lo : __log2f(x);
+                        Z += x;
+                        sxl += x * lx;
+                    }
+                __syncthreads();
+            }
+            if (r.inside) h = (double)(ln2 * (__log2f(Z) - sxl / Z));
+        } else {
         composite_tile<KT, SEM, NB>(a, gt, smem, r, racc);
         __syncthreads();
-        double h = 0.0;
         if (r.inside) {
             float Z = 0.f, sxl = 0.f;
             if constexpr (SEM == 3) {
@@ -575,6 +683,7 @@ __global__ __launch_bounds__(kBlock) void score_persistent_kernel(TileArgs a, Sc
                 }
             }
             h = (double)(ln2 * (__log2f(Z) - sxl / Z));
+        }
         }
         const uint64_t em = __ballot(r.inside && r.ncon == 0);
 #pragma unroll
@@ -683,6 +792,20 @@ size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode) {
     return b;
 }
 
+// Classes per pass when the class sums are split into `passes` ranges.
+static int class_rows(int C, int passes) { return (C + passes - 1) / passes; }
+
+// Class passes of an LDS launch: the configured count, else the fewest
+// whose rows fit the LDS; 0 if none fits.
+static int lds_passes(const Plan& P) {
+    const size_t cap = device_max_lds();
+    if (P.cfg.sem_passes > 0)
+        return fwd_lds_bytes(class_rows(P.C, P.cfg.sem_passes), P.k, P.kpad, 1) <= cap ? P.cfg.sem_passes : 0;
+    for (int p = 1; p <= kMaxPasses; p++)
+        if (fwd_lds_bytes(class_rows(P.C, p), P.k, P.kpad, 1) <= cap) return p;
+    return 0;
+}
+
 // 0: no semantics; 1: LDS accumulators; 2: accumulate into the output map;
 // 3: register accumulators.  Automatic placement prefers LDS, which measures
 // faster on gfx950 at C = 102 (a register update costs four VALU operations
@@ -691,7 +814,7 @@ static int sem_mode_for(const Plan& P, bool want_sem) {
     if (!want_sem) return 0;
     const int acc = P.cfg.sem_accumulators;
     if (acc == SGR_ACC_REGISTERS) return 3;
-    if (fwd_lds_bytes(P.C, P.k, P.kpad, 1) <= device_max_lds()) return 1;
+    if (lds_passes(P) > 0) return 1;
     return (acc == SGR_ACC_AUTO && P.C <= kMaxRegC) ? 3 : 2;
 }
 
@@ -720,16 +843,26 @@ TileArgs make_tile_args(const Plan& P, char* ws) {
     return a;
 }
 
-template <int KT, int SEM, int NB, bool LOSS = false>
+template <int KT, int SEM, int NB, bool LOSS = false, int NPASS = 1>
 static void fwd_launch(const TileArgs& a, unsigned grid, size_t lds, hipStream_t st, const LossK& lk = LossK{}) {
-    set_lds(render_fwd_kernel<KT, SEM, NB, LOSS>, lds);
-    render_fwd_kernel<KT, SEM, NB, LOSS><<<grid, kBlock, lds, st>>>(a, lk);
+    set_lds(render_fwd_kernel<KT, SEM, NB, LOSS, NPASS>, lds);
+    render_fwd_kernel<KT, SEM, NB, LOSS, NPASS><<<grid, kBlock, lds, st>>>(a, lk);
+}
+
+template <int KT, bool LOSS>
+static void fwd_launch_lds(int passes, const TileArgs& a, unsigned grid, size_t lds, hipStream_t st,
+                           const LossK& lk = LossK{}) {
+    if (passes == 1) fwd_launch<KT, 1, 1, LOSS>(a, grid, lds, st, lk);
+    else if (passes == 2) fwd_launch<KT, 1, 1, LOSS, 2>(a, grid, lds, st, lk);
+    else if (passes == 3) fwd_launch<KT, 1, 1, LOSS, 3>(a, grid, lds, st, lk);
+    else fwd_launch<KT, 1, 1, LOSS, 4>(a, grid, lds, st, lk);
 }
 
 template <int KT>
-static void fwd_dispatch_sem(int sem, int nb, const TileArgs& a, unsigned grid, size_t lds, hipStream_t st) {
+static void fwd_dispatch_sem(int sem, int nb, int passes, const TileArgs& a, unsigned grid, size_t lds,
+                             hipStream_t st) {
     if (sem == 0) fwd_launch<KT, 0, 1>(a, grid, lds, st);
-    else if (sem == 1) fwd_launch<KT, 1, 1>(a, grid, lds, st);
+    else if (sem == 1) fwd_launch_lds<KT, false>(passes, a, grid, lds, st);
     else if (sem == 2) fwd_launch<KT, 2, 1>(a, grid, lds, st);
     else if (nb == 1) fwd_launch<KT, 3, 1>(a, grid, lds, st);
     else if (nb == 2) fwd_launch<KT, 3, 2>(a, grid, lds, st);
@@ -749,24 +882,25 @@ sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStrea
     a.maps = (const MapPtrs*)(ws + P.map_table);
     const int sem = sem_mode_for(P, want_sem);
     const int nb = (P.C + kRegBlock - 1) / kRegBlock;
-    const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, sem);
+    const int passes = sem == 1 ? lds_passes(P) : 1;
+    const size_t lds = fwd_lds_bytes(class_rows(P.C, passes), P.k, P.kpad, sem);
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
-    if (P.k == 16) fwd_dispatch_sem<16>(sem, nb, a, grid, lds, st);
-    else if (P.k == 3) fwd_dispatch_sem<3>(sem, nb, a, grid, lds, st);
-    else fwd_dispatch_sem<0>(sem, nb, a, grid, lds, st);
+    if (P.k == 16) fwd_dispatch_sem<16>(sem, nb, passes, a, grid, lds, st);
+    else if (P.k == 3) fwd_dispatch_sem<3>(sem, nb, passes, a, grid, lds, st);
+    else fwd_dispatch_sem<0>(sem, nb, passes, a, grid, lds, st);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }
 
 // A persistent grid of as many workgroups as fit on the device at once.
-template <int KT, int SEM, int NB>
+template <int KT, int SEM, int NB, int NPASS = 1>
 static sgr_status score_launch(const Plan& P, const TileArgs& a, const ScoreOut& so, size_t lds, hipStream_t st) {
-    set_lds(score_persistent_kernel<KT, SEM, NB>, lds);
+    set_lds(score_persistent_kernel<KT, SEM, NB, NPASS>, lds);
     static int per_cu = 0;  // per instantiation; the dynamic LDS size is fixed by C and k
     static size_t per_cu_lds = 0;
     if (per_cu == 0 || per_cu_lds != lds) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, score_persistent_kernel<KT, SEM, NB>, kBlock, lds) !=
-            hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, score_persistent_kernel<KT, SEM, NB, NPASS>, kBlock,
+                                                         lds) != hipSuccess)
             return SGR_EHIP;
         per_cu = std::max(1, n);
         per_cu_lds = lds;
@@ -774,7 +908,7 @@ static sgr_status score_launch(const Plan& P, const TileArgs& a, const ScoreOut&
     const int64_t resident = (int64_t)device_cu_count() * per_cu;
     const int64_t want = std::min<int64_t>(P.num_tiles, P.cfg.score_workgroups > 0 ? P.cfg.score_workgroups : resident);
     const unsigned grid = (unsigned)(div_up(want, 8) * 8);
-    score_persistent_kernel<KT, SEM, NB><<<grid, kBlock, lds, st>>>(a, so);
+    score_persistent_kernel<KT, SEM, NB, NPASS><<<grid, kBlock, lds, st>>>(a, so);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }
 
@@ -800,7 +934,7 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const ViewDev* views, 
 sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_loss_view* lv, const sgr_loss_config* lc,
                                double* loss, char* ws, hipStream_t st) {
     TileArgs a = make_tile_args(P, ws);
-    bool want_sem = false;
+    bool want_sem = false, dense_sem = false;
     std::vector<MapPtrs> mp(P.V);
     std::vector<LossPtrs> lp(P.V);
     for (int v = 0; v < P.V; v++) {
@@ -810,6 +944,7 @@ sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_los
                          lv[v].g_rgb, lv[v].g_depth, lv[v].g_sil, lv[v].g_sem, lv[v].g_sem_at_label};
         want_sem |= mp[v].sem != nullptr || lv[v].label != nullptr || lv[v].sem != nullptr || lv[v].g_sem != nullptr ||
                     lv[v].g_sem_at_label != nullptr;
+        dense_sem |= lv[v].sem != nullptr || lv[v].g_sem != nullptr;
     }
     upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
     upload_bytes(ws + P.loss_table, lp.data(), sizeof(LossPtrs) * P.V, st);
@@ -823,15 +958,19 @@ sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_los
     lk.sqrt_eps = lc->sqrt_eps;
     lk.tile_loss = (double*)(ws + P.tile_part);
     const int sem = want_sem ? 1 : 0;
-    const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, sem);
+    // the dense target terms and the dense gradient need every class of a
+    // pixel at once: one pass
+    const int passes = sem == 0 ? 1 : dense_sem ? 1 : lds_passes(P);
+    if (passes == 0) return SGR_EUNSUPPORTED;
+    const size_t lds = fwd_lds_bytes(class_rows(P.C, passes), P.k, P.kpad, sem);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
     if (P.k == 16) {
-        if (sem) fwd_launch<16, 1, 1, true>(a, grid, lds, st, lk); else fwd_launch<16, 0, 1, true>(a, grid, lds, st, lk);
+        if (sem) fwd_launch_lds<16, true>(passes, a, grid, lds, st, lk); else fwd_launch<16, 0, 1, true>(a, grid, lds, st, lk);
     } else if (P.k == 3) {
-        if (sem) fwd_launch<3, 1, 1, true>(a, grid, lds, st, lk); else fwd_launch<3, 0, 1, true>(a, grid, lds, st, lk);
+        if (sem) fwd_launch_lds<3, true>(passes, a, grid, lds, st, lk); else fwd_launch<3, 0, 1, true>(a, grid, lds, st, lk);
     } else {
-        if (sem) fwd_launch<0, 1, 1, true>(a, grid, lds, st, lk); else fwd_launch<0, 0, 1, true>(a, grid, lds, st, lk);
+        if (sem) fwd_launch_lds<0, true>(passes, a, grid, lds, st, lk); else fwd_launch<0, 0, 1, true>(a, grid, lds, st, lk);
     }
     loss_reduce_kernel<<<P.V, 256, 0, st>>>((const ViewDev*)(ws + P.views), lk.tile_loss,
                                             (const uint32_t*)(ws + P.counters), loss);
@@ -846,16 +985,24 @@ sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, c
     so.n_empty = n_empty;
     so.entropy_sum = entropy_sum;
     const int sem = sem_mode_for(P, true) == 3 ? 3 : 1;
-    const size_t lds = fwd_lds_bytes(P.C, P.k, P.kpad, sem == 3 ? 0 : 1);
+    const int passes = sem == 1 ? lds_passes(P) : 1;
+    if (passes == 0) return SGR_EUNSUPPORTED;
+    const size_t lds = fwd_lds_bytes(class_rows(P.C, passes), P.k, P.kpad, sem == 3 ? 0 : 1);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
     const int nb = (P.C + kRegBlock - 1) / kRegBlock;
     if (P.k == 16) {
+        if (sem == 1 && passes == 2) return score_launch<16, 1, 1, 2>(P, a, so, lds, st);
+        if (sem == 1 && passes == 3) return score_launch<16, 1, 1, 3>(P, a, so, lds, st);
+        if (sem == 1 && passes == 4) return score_launch<16, 1, 1, 4>(P, a, so, lds, st);
         if (sem == 1) return score_launch<16, 1, 1>(P, a, so, lds, st);
         if (nb == 1) return score_launch<16, 3, 1>(P, a, so, lds, st);
         if (nb == 2) return score_launch<16, 3, 2>(P, a, so, lds, st);
         if (nb == 3) return score_launch<16, 3, 3>(P, a, so, lds, st);
         return score_launch<16, 3, 4>(P, a, so, lds, st);
     }
+    if (sem == 1 && passes == 2) return score_launch<0, 1, 1, 2>(P, a, so, lds, st);
+    if (sem == 1 && passes == 3) return score_launch<0, 1, 1, 3>(P, a, so, lds, st);
+    if (sem == 1 && passes == 4) return score_launch<0, 1, 1, 4>(P, a, so, lds, st);
     if (sem == 1) return score_launch<0, 1, 1>(P, a, so, lds, st);
     if (nb == 1) return score_launch<0, 3, 1>(P, a, so, lds, st);
     if (nb == 2) return score_launch<0, 3, 2>(P, a, so, lds, st);

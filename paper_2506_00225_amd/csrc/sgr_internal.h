@@ -16,6 +16,7 @@ constexpr int kAccStride = 257;    // LDS class-major stride: conflict-free for 
 constexpr uint32_t kInvalid = 0xffffffffu;
 constexpr int kRegBlock = 32;      // classes per register accumulator vector
 constexpr int kMaxRegC = 128;      // classes that fit the register accumulators (4 vectors)
+constexpr int kMaxPasses = 4;      // class ranges the LDS class sums may be split into
 
 // Top-k entries are stored grouped by accumulator block (class / 32), in
 // their original order inside a block, so a compositing kernel can walk a

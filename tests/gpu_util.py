@@ -8,9 +8,10 @@ from paper_2506_00225_amd import Frame, Gaussians, make_config
 LN2 = 0.6931471805599453
 
 
-def frame_for(sc, cams=None, cap=None, semgeo=0, lowpass=None, acc=0):
+def frame_for(sc, cams=None, cap=None, semgeo=0, lowpass=None, acc=0, passes=0):
     kw = {} if lowpass is None else {"lowpass": lowpass}
-    cfg = make_config(sc.num_classes, sc.k, sem_grad_to_geometry=semgeo, sem_accumulators=acc, **kw)
+    cfg = make_config(sc.num_classes, sc.k, sem_grad_to_geometry=semgeo, sem_accumulators=acc, sem_passes=passes,
+                      **kw)
     cams = sc.cameras if cams is None else cams
     return Frame(sc.n, cams, cfg, key_capacity=cap, device="cuda")
 

@@ -107,6 +107,9 @@ def test_accumulator_placement_validated(L):
     for acc in (L.SGR_ACC_AUTO, L.SGR_ACC_LDS):
         cfg.sem_accumulators = acc
         assert L.sgr_workspace_size(10, _cams(_cam()), 1, cfg, 100) > 0
+    for passes, ok in ((-1, False), (0, True), (1, True), (4, True), (5, False)):
+        cfg.sem_passes = passes
+        assert (L.sgr_workspace_size(10, _cams(_cam()), 1, cfg, 100) > 0) == ok, passes
 
 
 def test_calls_validate_before_any_device_work(L):

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from oracle import oracle as O
-from paper_2506_00225_amd import Frame, Gaussians, autotune, make_config, render, scenes, score_maps
+from paper_2506_00225_amd import Frame, Gaussians, SgrError, autotune, make_config, render, scenes, score_maps
 
 import gpu_util as U
 
@@ -395,6 +395,58 @@ def test_accumulator_placements_give_identical_bits(case):
         assert torch.equal(res[0][2], other[2]) and torch.equal(res[0][3], other[3])
 
 
+@pytest.mark.parametrize("case", ["tiny_c16", "room_c102", "tiny_c256"])
+def test_class_passes_give_identical_bits(case):
+    """Class sums split into 2..4 ranges composited one after another give
+    the bits of a single pass: maps, scores and the fused cross-entropy loss
+    with its gradients.  At C = 256 a single pass does not fit the LDS: the
+    forward then accumulates in the output map (same bits), while scoring
+    and the fused loss report SGR_EUNSUPPORTED."""
+    _say("class passes", case)
+    if case == "tiny_c16":
+        sc = scenes.tiny_scene(seed=14)
+    elif case == "tiny_c256":
+        sc = scenes.tiny_scene(seed=15, num_classes=256, k=16)
+    else:
+        sc = _room_crop(n=60_000, w=400, h=300)
+    g = Gaussians.from_scene(sc)
+    cam = sc.cameras[0]
+    P, C = cam.width * cam.height, sc.num_classes
+    rng = np.random.default_rng(6)
+    tg = {"rgb": torch.from_numpy(rng.random((P, 3)).astype(np.float32)),
+          "depth": torch.from_numpy((rng.random(P) * 4.5 + 0.5).astype(np.float32)),
+          "label": torch.from_numpy(rng.integers(0, C, size=P).astype(np.int32))}
+    fwd, rest = [], []
+    for passes in (1, 2, 3, 4):
+        fr = U.frame_for(sc, passes=passes)
+        fr.prepare(g)
+        fwd.append({k: v.clone() for k, v in fr.forward(g).items()})
+        if case == "tiny_c256" and passes == 1:
+            with pytest.raises(SgrError):
+                fr.score(g)
+            with pytest.raises(SgrError):
+                fr.forward_loss(g, tg, sparse_sem=True)
+            continue
+        ne, hs = fr.score(g)
+        maps = fr.alloc_maps()
+        gr, loss = fr.forward_loss(g, tg, maps=maps, sparse_sem=True)
+        torch.cuda.synchronize()
+        rest.append((ne.clone(), hs.clone(), {k: v.clone() for k, v in gr.items()}, loss.clone(), maps))
+    torch.cuda.synchronize()
+    for other in fwd[1:]:
+        for k in fwd[0]:
+            assert torch.equal(fwd[0][k], other[k]), k
+    for ne, hs, gr, loss, maps in rest[1:]:
+        assert torch.equal(rest[0][0], ne) and torch.equal(rest[0][1], hs)
+        assert torch.equal(rest[0][3], loss)
+        for k in gr:
+            assert torch.equal(rest[0][2][k], gr[k]), k
+        for k in maps:
+            assert torch.equal(rest[0][4][k], maps[k]), k
+    for k in rest[0][4]:  # the fused launch writes the forward's maps
+        assert torch.equal(rest[0][4][k], fwd[-1][k]), k
+
+
 def test_out_of_range_class_index_reported():
     """An index >= C is an input error: reported as SGR_EINVAL by the status
     word, never used to address memory."""
@@ -513,11 +565,19 @@ def test_autotuner_choices_keep_outputs():
     fr = U.frame_for(sc)
     fr.prepare(g)
     rep = autotune.tune_mapping(fr, g, reps=1)
-    assert len(rep["candidates"]) == 4 and rep["chosen"] in rep["candidates"]
+    # placements: LDS in 1, 2 or 3 class ranges, registers; two tile orders
+    assert len(rep["candidates"]) == 8 and rep["chosen"] in rep["candidates"]
     rep2 = autotune.tune_score(fr, g, reps=1, workgroups=(0, 64))
-    assert len(rep2["candidates"]) == 8
+    assert len(rep2["candidates"]) == 16
     assert autotune.tune_score(fr, g)["cached"] == (fr.cfg.sem_accumulators, fr.cfg.tile_order,
-                                                    fr.cfg.score_workgroups)
+                                                    fr.cfg.score_workgroups, fr.cfg.sem_passes)
+    rng = np.random.default_rng(2)
+    tg = [{"rgb": torch.from_numpy(rng.random((c.width * c.height, 3)).astype(np.float32)),
+           "depth": torch.from_numpy(rng.random(c.width * c.height).astype(np.float32) + 1.0),
+           "label": torch.from_numpy(rng.integers(0, sc.num_classes, c.width * c.height).astype(np.int32))}
+          for c in sc.cameras]
+    rep3 = autotune.tune_mapping(fr, g, reps=1, targets=tg)
+    assert rep3["what"] == "mapping_loss" and len(rep3["candidates"]) == 8
     ref = U.frame_for(sc)
     ref.prepare(g)
     fr.prepare(g)
