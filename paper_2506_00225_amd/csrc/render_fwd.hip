@@ -93,9 +93,14 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     // The next batch is fetched into them while the current one is composited.
     constexpr int KM = KT > 0 ? KT : kMaxK;
     constexpr int KWM = (KM + 3) / 4;
+    // With the class sums in LDS in one pass and k fixed at compile time, a
+    // staged entry carries its classes as byte offsets of their accumulator
+    // rows (class * 257 * 4), so a blend does no index decoding.
+    constexpr bool OFFS = SEM == 1 && NPASS == 1 && KT > 0;
+    constexpr int KIDX = OFFS ? KM : KWM;  // index words per staged entry
     // One register array serves both roles (record: r0, r1, r2, colour as
-    // 16 words; semantics: KM values then KWM index words).
-    constexpr int KSTG = (KM + KWM) > 16 ? (KM + KWM) : 16;
+    // 16 words; semantics: KM values then KIDX index words).
+    constexpr int KSTG = (KM + KIDX) > 16 ? (KM + KIDX) : 16;
     uint32_t stg[KSTG];
 #pragma unroll
     for (int q = 0; q < KSTG; q++) stg[q] = 0u;
@@ -131,9 +136,19 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                     if (m < k) stg[m] = __float_as_uint(sv[m]);
             }
             const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
+            if constexpr (OFFS) {
 #pragma unroll
-            for (int m = 0; m < KWM; m++)
-                if (m < kw) stg[KM + m] = si[m];
+                for (int mw = 0; mw < KWM; mw++) {
+                    const uint32_t word = si[mw];
+#pragma unroll
+                    for (int b = 0; b < 4; b++)
+                        if (mw * 4 + b < KM) stg[KM + mw * 4 + b] = ((word >> (8 * b)) & 0xffu) * (kAccStride * 4);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < KWM; m++)
+                    if (m < kw) stg[KM + m] = si[m];
+            }
         }
     };
 
@@ -158,9 +173,14 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
 #pragma unroll
                 for (int m = 0; m < KM; m++)
                     if (m < k) s_sv[j * k + m] = __uint_as_float(stg[m]);
+                if constexpr (OFFS) {
 #pragma unroll
-                for (int m = 0; m < KWM; m++)
-                    if (m < kw) s_si[j * kw + m] = stg[KM + m];
+                    for (int m = 0; m < KM; m++) s_si[j * KM + m] = stg[KM + m];
+                } else {
+#pragma unroll
+                    for (int m = 0; m < KWM; m++)
+                        if (m < kw) s_si[j * kw + m] = stg[KM + m];
+                }
             }
         }
         __syncthreads();
@@ -194,164 +214,116 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
             }
             return -1;
         };
-        if constexpr (SEM == 3) {
-            // Uniform control flow: every lane takes every entry of the wave's
-            // mask, with w = 0 where it does not blend (a no-op update), so the
-            // register vectors are only ever updated in straight-line code.
-            if (__ballot(!done) == 0) continue;
-            int jn = next();
-            float4 n0 = {}, n1 = {}, n2 = {};
+        // Every lane takes every entry of the wave's mask, with w = 0 where
+        // it does not blend (outside the rectangle, alpha below the cutoff,
+        // terminated): adding 0 leaves a sum's bits unchanged, so lanes need
+        // no branches; an entry no lane blends is skipped as a whole.  The
+        // next entry's record is loaded before this one's updates.
+        if (__ballot(!done) == 0) continue;
+        int jn = next();
+        float4 n0 = {}, n1 = {}, n2 = {};
+        if (jn >= 0) {
+            n0 = s_r0[jn];
+            n1 = s_r1[jn];
+            n2 = s_r2[jn];
+        }
+        while (jn >= 0) {
+            const int j = jn;
+            const float4 q0 = n0, q1 = n1, q2 = n2;
+            jn = next();
             if (jn >= 0) {
                 n0 = s_r0[jn];
                 n1 = s_r1[jn];
                 n2 = s_r2[jn];
             }
-            while (jn >= 0) {
-                const int j = jn;
-                const float4 q0 = n0, q1 = n1, q2 = n2;
-                jn = next();
-                if (jn >= 0) {
-                    n0 = s_r0[jn];
-                    n1 = s_r1[jn];
-                    n2 = s_r2[jn];
-                }
-                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-                const bool inr = !done && px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) &&
-                                 py >= (int)(ry & 0xffffu) && py <= (int)(ry >> 16);
-                float G, dx, dy;
-                const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
-                const bool pass = inr && alpha >= amin;
-                const float Tn = T * (1.f - alpha);
-                const bool blend = pass && !(Tn < tmin);
-                done = done || (pass && Tn < tmin);
-                const float w = blend ? alpha * T : 0.f;
+            const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
+            const bool inr = !done && px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) &&
+                             py >= (int)(ry & 0xffffu) && py <= (int)(ry >> 16);
+            float G, dx, dy;
+            const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
+            const bool pass = inr && alpha >= amin;
+            const float Tn = T * (1.f - alpha);
+            const bool blend = pass && !(Tn < tmin);
+            done = done || (pass && Tn < tmin);
+            const float w = blend ? alpha * T : 0.f;
+            if (SEM == 3 || __ballot(blend) != 0) {
                 const float4 col = s_col[j];
                 cr = fmaf(col.x, w, cr);
                 cg = fmaf(col.y, w, cg);
                 cb = fmaf(col.z, w, cb);
                 dd = fmaf(col.w, w, dd);
                 ss += w;
-                const float* sv = s_sv + j * k;
-                const uint32_t* si = s_si + j * kw;
-                uint32_t wd[KWM];
-#pragma unroll
-                for (int q = 0; q < KWM; q++) wd[q] = q < kw ? __builtin_amdgcn_readfirstlane(si[q]) : 0u;
-                reg_accumulate<NB, KT, KM, KWM>(racc, sv, wd, k, w);
-                T = blend ? Tn : T;
-                ncon += blend ? 1 : 0;
-                last = blend ? b0 + j + 1 : last;
-                if (__ballot(!done) == 0) break;
-            }
-        } else if (!done) {
-            // The next entry's record is loaded before this one's
-            // accumulator updates are issued (records never alias the
-            // accumulators), hiding one LDS round trip per entry.
-            int jn = next();
-            float4 n0 = {}, n1 = {}, n2 = {};
-            if (jn >= 0) {
-                n0 = s_r0[jn];
-                n1 = s_r1[jn];
-                n2 = s_r2[jn];
-            }
-            while (jn >= 0) {
-                const int j = jn;
-                const float4 q0 = n0, q1 = n1, q2 = n2;
-                jn = next();
-                if (jn >= 0) {
-                    n0 = s_r0[jn];
-                    n1 = s_r1[jn];
-                    n2 = s_r2[jn];
-                }
-                const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-                if (px < (int)(rx & 0xffffu) || px > (int)(rx >> 16) || py < (int)(ry & 0xffffu) ||
-                    py > (int)(ry >> 16))
-                    continue;
-                float G, dx, dy;
-                const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
-                if (alpha < amin) continue;
-                const float Tn = T * (1.f - alpha);
-                if (Tn < tmin) {
-                    done = true;
-                    break;
-                }
-                const float w = alpha * T;
-                const float4 col = s_col[j];
-                cr = fmaf(col.x, w, cr);
-                cg = fmaf(col.y, w, cg);
-                cb = fmaf(col.z, w, cb);
-                dd = fmaf(col.w, w, dd);
-                ss += w;
-                if (SEM != 0) {
+                if constexpr (SEM == 3) {
                     const float* sv = s_sv + j * k;
                     const uint32_t* si = s_si + j * kw;
-                    const bool dup = (__float_as_uint(q2.w) >> 31) != 0u;
-                    if (false) {
-                    } else if (KT > 0 && SEM == 1 && !dup) {
-                        // distinct classes: all reads, then all updates
-                        constexpr int KK = KT > 0 ? KT : 1;
-                        float vals[KK];
-                        uint32_t cls[KK];
-                        if constexpr (KT > 0 && (KT & 3) == 0) {
+                    uint32_t wd[KWM];
 #pragma unroll
-                            for (int m = 0; m < KK; m += 4) {
-                                const float4 v4 = *(const float4*)(sv + m);
-                                vals[m] = v4.x; vals[m + 1] = v4.y; vals[m + 2] = v4.z; vals[m + 3] = v4.w;
-                            }
-                        } else {
+                    for (int q = 0; q < KWM; q++) wd[q] = q < kw ? __builtin_amdgcn_readfirstlane(si[q]) : 0u;
+                    reg_accumulate<NB, KT, KM, KWM>(racc, sv, wd, k, w);
+                } else if constexpr (OFFS) {
+                    // k values and k row offsets, then (distinct classes) all
+                    // reads before all updates; repeated classes in order
+                    const float* sv = s_sv + j * KT;
+                    const uint32_t* so = s_si + j * KT;
+                    float vals[KT];
+                    uint32_t off[KT];
+                    if constexpr ((KT & 3) == 0) {
 #pragma unroll
-                            for (int m = 0; m < KK; m++) vals[m] = sv[m];
-                        }
-                        if constexpr (NPASS == 1) {
-#pragma unroll
-                            for (int m = 0; m < KK; m++)
-                                cls[m] = ((si[m >> 2] >> (8 * (m & 3))) & 0xffu) * kAccStride + tid;
-                            float cur[KK];
-#pragma unroll
-                            for (int m = 0; m < KK; m++) cur[m] = acc[cls[m]];
-#pragma unroll
-                            for (int m = 0; m < KK; m++) acc[cls[m]] = fmaf(vals[m], w, cur[m]);
-                        } else {
-                            bool mine[KK];  // class in this pass's range (wave-uniform)
-#pragma unroll
-                            for (int m = 0; m < KK; m++) {
-                                const uint32_t rel = ((si[m >> 2] >> (8 * (m & 3))) & 0xffu) - (uint32_t)lo;
-                                mine[m] = rel < (uint32_t)cnt;
-                                cls[m] = rel * kAccStride + tid;
-                            }
-                            float cur[KK];
-#pragma unroll
-                            for (int m = 0; m < KK; m++)
-                                if (mine[m]) cur[m] = acc[cls[m]];
-#pragma unroll
-                            for (int m = 0; m < KK; m++)
-                                if (mine[m]) acc[cls[m]] = fmaf(vals[m], w, cur[m]);
+                        for (int m = 0; m < KT; m += 4) {
+                            const float4 v4 = *(const float4*)(sv + m);
+                            const uint4 o4 = *(const uint4*)(so + m);
+                            vals[m] = v4.x; vals[m + 1] = v4.y; vals[m + 2] = v4.z; vals[m + 3] = v4.w;
+                            off[m] = o4.x; off[m + 1] = o4.y; off[m + 2] = o4.z; off[m + 3] = o4.w;
                         }
                     } else {
 #pragma unroll
-                        for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
-                            if (KT == 0 && mw >= kw) break;
-                            const uint32_t word = si[mw];
+                        for (int m = 0; m < KT; m++) {
+                            vals[m] = sv[m];
+                            off[m] = so[m];
+                        }
+                    }
+                    char* col_base = (char*)(acc + tid);
+                    if ((__float_as_uint(q2.w) >> 31) == 0u) {
+                        float cur[KT];
 #pragma unroll
-                            for (int b = 0; b < 4; b++) {
-                                const int m = mw * 4 + b;
-                                if (m < k) {
-                                    const uint32_t cl = (word >> (8 * b)) & 0xffu;
-                                    if (SEM == 1) {
-                                        const uint32_t rel = cl - (uint32_t)lo;
-                                        if (NPASS == 1 || rel < (uint32_t)cnt)
-                                            acc[rel * kAccStride + tid] = fmaf(sv[m], w, acc[rel * kAccStride + tid]);
-                                    } else if (gacc) {
-                                        gacc[cl] = fmaf(sv[m], w, gacc[cl]);
-                                    }
+                        for (int m = 0; m < KT; m++) cur[m] = *(float*)(col_base + off[m]);
+#pragma unroll
+                        for (int m = 0; m < KT; m++) *(float*)(col_base + off[m]) = fmaf(vals[m], w, cur[m]);
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < KT; m++) {
+                            float* q = (float*)(col_base + off[m]);
+                            *q = fmaf(vals[m], w, *q);
+                        }
+                    }
+                } else if constexpr (SEM != 0) {
+                    const float* sv = s_sv + j * k;
+                    const uint32_t* si = s_si + j * kw;
+#pragma unroll
+                    for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
+                        if (KT == 0 && mw >= kw) break;
+                        const uint32_t word = si[mw];
+#pragma unroll
+                        for (int b = 0; b < 4; b++) {
+                            const int m = mw * 4 + b;
+                            if (m < k) {
+                                const uint32_t cl = (word >> (8 * b)) & 0xffu;
+                                if (SEM == 1) {
+                                    const uint32_t rel = cl - (uint32_t)lo;
+                                    if (NPASS == 1 || rel < (uint32_t)cnt)
+                                        acc[rel * kAccStride + tid] = fmaf(sv[m], w, acc[rel * kAccStride + tid]);
+                                } else if (gacc && blend) {
+                                    gacc[cl] = fmaf(sv[m], w, gacc[cl]);
                                 }
                             }
                         }
                     }
                 }
-                T = Tn;
-                ncon++;
-                last = b0 + j + 1;
             }
+            T = blend ? Tn : T;
+            ncon += blend ? 1 : 0;
+            last = blend ? b0 + j + 1 : last;
+            if (__ballot(!done) == 0) break;
         }
     }
     res.T = T;
@@ -786,7 +758,9 @@ static void set_lds(K kernel, size_t bytes) {
 // accumulators (mode 1) or, for mode 3, room for the four waves' 64 x 33
 // transpose buffers that reuse the staging area at the end.
 size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode) {
-    size_t b = (size_t)kFwdBatch * (4 * sizeof(float4) + k * sizeof(float) + kpad);
+    // per staged entry: records, k values, and the class indices as bytes
+    // or (LDS class sums) as one 4-byte row offset each
+    size_t b = (size_t)kFwdBatch * (4 * sizeof(float4) + k * sizeof(float) + std::max(kpad, 4 * k));
     if (sem_mode == 1) b += (size_t)acc_floats(C) * sizeof(float);
     if (sem_mode == 3) b = std::max(b, (size_t)4 * 64 * 33 * sizeof(float));
     return b;
