@@ -114,6 +114,7 @@ struct TileArgs {
     float alpha_min, alpha_max, t_min;
     int linear_tiles;  // 1: workgroup i takes tile i; 0: XCD-contiguous runs
     const MapPtrs* maps;
+    const LossPtrs* loss_views;  // label-only class sums: each view's label map
 };
 
 struct TileResult {
@@ -124,6 +125,8 @@ struct TileResult {
     uint32_t last;
     float c[3];
     float d, s;
+    int lab;    // label-only class sums: the pixel's label (-1 if none) ...
+    float ql;   // ... and its class sum
 };
 
 struct ScoreOut {

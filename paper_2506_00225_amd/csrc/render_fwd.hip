@@ -33,7 +33,9 @@ __device__ __forceinline__ void write_rows_range(const float* smem, float* out, 
 //      update 64 consecutive floats of one class row, conflict-free;
 //   2  the thread's own row of the output map (when LDS is too small);
 //   3  registers, NB vectors of 32 classes (C <= 128): no LDS, so more
-//      waves fit on a CU.
+//      waves fit on a CU;
+//   4  only the class sum at the pixel's label (a cross-entropy target
+//      needs no other class): one register per pixel, no LDS.
 // Every mode adds a blend's values in the same order with the same fused
 // multiply-add, so they give the same bits.
 //
@@ -74,6 +76,15 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     if (SEM == 1)
         for (int i = tid; i < cnt * kAccStride; i += kBlock) acc[i] = 0.f;
     if constexpr (SEM == 3) reg_zero(racc);
+    int lab = -1;
+    float ql = 0.f;
+    if (SEM == 4) {
+        const int32_t* lm = a.loss_views[v].label;
+        if (inside && lm) lab = lm[(int64_t)py * vw.width + px];
+        // taken here, so the compositing loop does not wait on the batch
+        // prefetch loads issued after it
+        asm volatile("" : "+v"(lab));
+    }
     float* gacc = nullptr;  // SEM == 2: the thread's own row of the output map
     if (SEM == 2 && inside && a.maps[v].sem) {
         gacc = a.maps[v].sem + ((int64_t)py * vw.width + px) * C;
@@ -296,6 +307,42 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                             *q = fmaf(vals[m], w, *q);
                         }
                     }
+                } else if constexpr (SEM == 4) {
+                    // the label's sum: entries of other classes add 0, in
+                    // list order (repeated classes add in turn)
+                    const float* sv = s_sv + j * k;
+                    const uint32_t* si = s_si + j * kw;
+                    if constexpr (KT > 0 && (KT & 15) == 0) {
+                        // whole rows first (16-byte loads), then selects
+#pragma unroll
+                        for (int m0 = 0; m0 < KT; m0 += 16) {
+                            const uint4 wd = *(const uint4*)(si + m0 / 4);
+                            float vv[16];
+#pragma unroll
+                            for (int q = 0; q < 16; q += 4) {
+                                const float4 v4 = *(const float4*)(sv + m0 + q);
+                                vv[q] = v4.x; vv[q + 1] = v4.y; vv[q + 2] = v4.z; vv[q + 3] = v4.w;
+                            }
+                            const uint32_t ww[4] = {wd.x, wd.y, wd.z, wd.w};
+#pragma unroll
+                            for (int q = 0; q < 16; q++)
+                                ql = fmaf((int)((ww[q >> 2] >> (8 * (q & 3))) & 0xffu) == lab ? vv[q] : 0.f, w, ql);
+                        }
+                    } else {
+#pragma unroll
+                        for (int mw = 0; mw < (KT > 0 ? (KT + 3) / 4 : kMaxK / 4); mw++) {
+                            if (KT == 0 && mw >= kw) break;
+                            const uint32_t word = si[mw];
+#pragma unroll
+                            for (int b = 0; b < 4; b++) {
+                                const int m = mw * 4 + b;
+                                if (m < k) {
+                                    const float v = sv[m];
+                                    ql = fmaf((int)((word >> (8 * b)) & 0xffu) == lab ? v : 0.f, w, ql);
+                                }
+                            }
+                        }
+                    }
                 } else if constexpr (SEM != 0) {
                     const float* sv = s_sv + j * k;
                     const uint32_t* si = s_si + j * kw;
@@ -338,6 +385,8 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     res.c[0] = cr; res.c[1] = cg; res.c[2] = cb;
     res.d = dd;
     res.s = ss;
+    res.lab = lab;
+    res.ql = ql;
 }
 
 __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
@@ -383,9 +432,9 @@ __device__ __forceinline__ void loss_epilogue(const TileArgs& a, const LossK& lk
         if (L.g_sil) L.g_sil[pix] = lk.w_sil * sgnf(rs) * inv_p;
         lpx = (double)lg;
     }
-    if constexpr (SEM == 1 && NPASS > 1) {
-        // class passes: only the cross-entropy term, from the label's class
-        // sum captured in its pass; its gradient in the one-class form
+    if constexpr ((SEM == 1 && NPASS > 1) || SEM == 4) {
+        // class passes or label-only sums: only the cross-entropy term, from
+        // the label's class sum; its gradient in the one-class form
         if (r.inside && L.label) {
             float gl = 0.f;
             if (lab >= 0 && lab < a.C) {
@@ -543,6 +592,10 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk
         a.pix_last[vw.pix_off + pix] = r.last;
     }
     if constexpr (LOSS) {
+        if constexpr (SEM == 4) {
+            lab = r.lab;
+            q_label = r.ql;
+        }
         loss_epilogue<SEM, NPASS>(a, lk, r, vw, gt, smem, lab, q_label);
         return;
     }
@@ -760,7 +813,7 @@ static void set_lds(K kernel, size_t bytes) {
 size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode) {
     // per staged entry: records, k values, and the class indices as bytes
     // or (LDS class sums) as one 4-byte row offset each
-    size_t b = (size_t)kFwdBatch * (4 * sizeof(float4) + k * sizeof(float) + std::max(kpad, 4 * k));
+    size_t b = (size_t)kFwdBatch * (4 * sizeof(float4) + k * sizeof(float) + (sem_mode == 1 ? std::max(kpad, 4 * k) : kpad));
     if (sem_mode == 1) b += (size_t)acc_floats(C) * sizeof(float);
     if (sem_mode == 3) b = std::max(b, (size_t)4 * 64 * 33 * sizeof(float));
     return b;
@@ -908,7 +961,7 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const ViewDev* views, 
 sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_loss_view* lv, const sgr_loss_config* lc,
                                double* loss, char* ws, hipStream_t st) {
     TileArgs a = make_tile_args(P, ws);
-    bool want_sem = false, dense_sem = false;
+    bool want_sem = false, dense_sem = false, sem_map = false;
     std::vector<MapPtrs> mp(P.V);
     std::vector<LossPtrs> lp(P.V);
     for (int v = 0; v < P.V; v++) {
@@ -919,6 +972,7 @@ sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_los
         want_sem |= mp[v].sem != nullptr || lv[v].label != nullptr || lv[v].sem != nullptr || lv[v].g_sem != nullptr ||
                     lv[v].g_sem_at_label != nullptr;
         dense_sem |= lv[v].sem != nullptr || lv[v].g_sem != nullptr;
+        sem_map |= mp[v].sem != nullptr;
     }
     upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
     upload_bytes(ws + P.loss_table, lp.data(), sizeof(LossPtrs) * P.V, st);
@@ -931,20 +985,30 @@ sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_los
     lk.tau = lc->entropy_tau > 0.f ? lc->entropy_tau : logf((float)P.k);
     lk.sqrt_eps = lc->sqrt_eps;
     lk.tile_loss = (double*)(ws + P.tile_part);
-    const int sem = want_sem ? 1 : 0;
+    a.loss_views = lk.views;
+    // Cross-entropy targets only, no dense semantic map or gradient asked
+    // for: each pixel needs only its label's class sum (mode 4).
+    const bool label_only = want_sem && !dense_sem && !sem_map;
+    const int sem = !want_sem ? 0 : label_only ? 4 : 1;
     // the dense target terms and the dense gradient need every class of a
     // pixel at once: one pass
-    const int passes = sem == 0 ? 1 : dense_sem ? 1 : lds_passes(P);
+    const int passes = sem != 1 ? 1 : dense_sem ? 1 : lds_passes(P);
     if (passes == 0) return SGR_EUNSUPPORTED;
     const size_t lds = fwd_lds_bytes(class_rows(P.C, passes), P.k, P.kpad, sem);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
     if (P.k == 16) {
-        if (sem) fwd_launch_lds<16, true>(passes, a, grid, lds, st, lk); else fwd_launch<16, 0, 1, true>(a, grid, lds, st, lk);
+        if (sem == 1) fwd_launch_lds<16, true>(passes, a, grid, lds, st, lk);
+        else if (sem == 4) fwd_launch<16, 4, 1, true>(a, grid, lds, st, lk);
+        else fwd_launch<16, 0, 1, true>(a, grid, lds, st, lk);
     } else if (P.k == 3) {
-        if (sem) fwd_launch_lds<3, true>(passes, a, grid, lds, st, lk); else fwd_launch<3, 0, 1, true>(a, grid, lds, st, lk);
+        if (sem == 1) fwd_launch_lds<3, true>(passes, a, grid, lds, st, lk);
+        else if (sem == 4) fwd_launch<3, 4, 1, true>(a, grid, lds, st, lk);
+        else fwd_launch<3, 0, 1, true>(a, grid, lds, st, lk);
     } else {
-        if (sem) fwd_launch_lds<0, true>(passes, a, grid, lds, st, lk); else fwd_launch<0, 0, 1, true>(a, grid, lds, st, lk);
+        if (sem == 1) fwd_launch_lds<0, true>(passes, a, grid, lds, st, lk);
+        else if (sem == 4) fwd_launch<0, 4, 1, true>(a, grid, lds, st, lk);
+        else fwd_launch<0, 0, 1, true>(a, grid, lds, st, lk);
     }
     loss_reduce_kernel<<<P.V, 256, 0, st>>>((const ViewDev*)(ws + P.views), lk.tile_loss,
                                             (const uint32_t*)(ws + P.counters), loss);

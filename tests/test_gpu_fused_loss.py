@@ -23,8 +23,8 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-def _scene(n=60_000, w=400, h=300):
-    sc = scenes.room_scene(seed=4, n=n, targets=False)
+def _scene(n=60_000, w=400, h=300, num_classes=102):
+    sc = scenes.room_scene(seed=4, n=n, num_classes=num_classes, targets=False)
     cam = sc.cameras[0]
     sc.cameras = [scenes.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx - (cam.width - w) / 2,
                                 cam.cy - (cam.height - h) / 2, w, h)]
@@ -170,3 +170,55 @@ def test_sparse_semantic_gradient_equals_dense():
     assert torch.equal(gdn["sem"].gather(1, lab[:, None])[:, 0], gsp["sem_at_label"])
     for k in ref:
         assert torch.equal(ref[k], got[k]), k
+
+
+@pytest.mark.parametrize("C", [102, 256])
+def test_label_only_class_sums_equal_full_path(C):
+    """With cross-entropy targets and no semantic map asked for, the fused
+    forward keeps only each pixel's class sum at its label.  Loss, maps and
+    gradients equal, bit for bit, those of the launch that accumulates all C
+    class sums (asked for the semantic map as well); two views of different
+    sizes, one with a label outside [0, C) reported as an input error; the
+    loss also matches the oracle on the rendered maps."""
+    _say("label-only class sums", C)
+    sc = _scene(n=40_000, w=256, h=192, num_classes=C)
+    cam = sc.cameras[0]
+    cams = [cam, scenes.Camera(cam.R, cam.t, cam.fx, cam.fy, cam.cx + 20, cam.cy - 10, 200, 150)]
+    rng = np.random.default_rng(11)
+    tgs = [{kk: torch.from_numpy(v) for kk, v in _targets(rng, c.width * c.height, C, "label", sc.k).items()}
+           for c in cams]
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc, cams=cams)
+    fr.prepare(g)
+    keys = ("rgb", "depth", "sil", "t_final", "n_contrib")
+    m1 = {kk: v for kk, v in fr.alloc_maps().items() if kk in keys}
+    g1, l1 = fr.forward_loss(g, tgs, maps=m1, sparse_sem=True)         # label-only sums
+    g1 = {kk: v.clone() for kk, v in g1.items()}
+    l1 = l1.clone()
+    m2 = fr.alloc_maps()
+    g2, l2 = fr.forward_loss(g, tgs, maps=m2, sparse_sem=True)         # all C sums (sem map asked for)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2)
+    for kk in g1:
+        assert torch.equal(g1[kk], g2[kk]), kk
+    for kk in m1:
+        assert torch.equal(m1[kk], m2[kk]), kk
+    st, _, _ = fr.status()
+    assert st == 0
+    # the oracle's loss on the maps of view 0
+    hw = (cam.height, cam.width)
+    P0 = cam.width * cam.height
+    m = {"rgb": U.to_np(m2["rgb"][:P0]).reshape(*hw, 3), "depth": U.to_np(m2["depth"][:P0]).reshape(hw),
+         "sil": U.to_np(m2["sil"][:P0]).reshape(hw), "sem": U.to_np(m2["sem"][:P0]).reshape(*hw, C)}
+    t = {"rgb": U.to_np(tgs[0]["rgb"]).reshape(*hw, 3), "depth": U.to_np(tgs[0]["depth"]).reshape(hw),
+         "label": U.to_np(tgs[0]["label"]).reshape(hw)}
+    want_loss, _, _ = OL.mapping_loss(m, t, C, sc.k)
+    assert float(l1[0]) == pytest.approx(want_loss, rel=1e-5)
+    # a label outside [0, C): status SGR_EINVAL, no loss term for that pixel
+    bad = [dict(tg) for tg in tgs]
+    bad[1]["label"] = bad[1]["label"].clone()
+    bad[1]["label"][7] = C
+    fr.forward_loss(g, bad, sparse_sem=True)
+    torch.cuda.synchronize()
+    st, _, _ = fr.status()
+    assert st == 1

@@ -401,7 +401,7 @@ def test_class_passes_give_identical_bits(case):
     the bits of a single pass: maps, scores and the fused cross-entropy loss
     with its gradients.  At C = 256 a single pass does not fit the LDS: the
     forward then accumulates in the output map (same bits), while scoring
-    and the fused loss report SGR_EUNSUPPORTED."""
+    and the fused loss asked for the semantic map report SGR_EUNSUPPORTED."""
     _say("class passes", case)
     if case == "tiny_c16":
         sc = scenes.tiny_scene(seed=14)
@@ -425,7 +425,7 @@ def test_class_passes_give_identical_bits(case):
             with pytest.raises(SgrError):
                 fr.score(g)
             with pytest.raises(SgrError):
-                fr.forward_loss(g, tg, sparse_sem=True)
+                fr.forward_loss(g, tg, maps=fr.alloc_maps(), sparse_sem=True)
             continue
         ne, hs = fr.score(g)
         maps = fr.alloc_maps()
