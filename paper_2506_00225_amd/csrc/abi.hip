@@ -102,6 +102,7 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     P->keys1 = take(4 * caps);
     P->vals1 = take(4 * caps);
     P->owner = take(4 * caps);
+    P->heads = take(4 * (caps / kKeyChunk + 2));
     P->sgp = take(4 * caps);
     P->ranges = take(8 * (size_t)tiles);
     const uint32_t big = (uint32_t)std::max<int64_t>(vn, cap);

@@ -290,49 +290,75 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
 
 // --------------------------------------------------------------- keys
 
-// Block b emits the keys of visible pairs [256 b, 256 b + 256): the block's
-// keys are spread evenly over its threads, each finding its owner by binary
-// search over the block's offsets in LDS.
-__global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
-    __shared__ uint32_t off[257];
-    __shared__ int32_t info[256][3];  // first global tile of the rect, rect width in tiles, view width in tiles
+// Keys are emitted in chunks of kKeyChunk consecutive keys, one chunk per
+// workgroup, so a pair near the camera that covers thousands of tiles is
+// spread over many workgroups.  chunk_heads records, for every chunk, the
+// visible pair that owns its first key (pair g owns keys
+// [toff[g], toff[g] + tcount[g])).
+__global__ __launch_bounds__(256) void chunk_heads(KeyArgs a) {
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
     const uint32_t nv = a.counters[kNumVisible];
-    const uint32_t g0 = blockIdx.x * 256u;
-    if (g0 >= nv) return;
-    const uint32_t cnt = min(256u, nv - g0);
-    const uint32_t g = g0 + threadIdx.x;
-    if (threadIdx.x < cnt) {
-        off[threadIdx.x] = a.toff[g];
-        const float4 r2 = a.srec[g].r2;
-        const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
-        const int v = __float_as_int(r2.w) & 0x7fffffff;
-        const int tx0 = (int)(rx & 0xffffu) / kTile, tx1 = (int)(rx >> 16) / kTile;
-        const int ty0 = (int)(ry & 0xffffu) / kTile;
-        const ViewDev& vw = a.views[v];
-        info[threadIdx.x][0] = vw.tile_off + ty0 * vw.tiles_x + tx0;
-        info[threadIdx.x][1] = tx1 - tx0 + 1;
-        info[threadIdx.x][2] = vw.tiles_x;
-        if (threadIdx.x == cnt - 1) off[cnt] = a.toff[g] + a.tcount[g];
-    }
-    __syncthreads();
-    const uint32_t base = off[0];
-    const uint32_t total = off[cnt] - base;
-    const uint32_t cap = (uint32_t)a.cap;
-    for (uint32_t p = threadIdx.x; p < total; p += 256) {
-        const uint32_t e = base + p;
-        // owner: last j with off[j] <= e
-        int lo = 0, hi = (int)cnt - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= e) lo = mid; else hi = mid - 1;
+    if (g >= nv) return;
+    const uint64_t s = a.toff[g], c = a.tcount[g];
+    const uint64_t lim = min((uint64_t)a.counters[kKeysLo], (uint64_t)a.cap);
+    if (c == 0 || s >= lim) return;
+    const uint64_t last = min(s + c, lim) - 1;
+    for (uint64_t q = (s + kKeyChunk - 1) / kKeyChunk; q * kKeyChunk <= last; q++) a.heads[q] = g;
+}
+
+// Workgroup q emits keys [q C, q C + C) (C = kKeyChunk): the pairs that own
+// them, heads[q] onwards, go to LDS (offsets and tile rectangle), and each
+// key finds its owner by binary search there.  A pair owns at least one key,
+// so at most C + 1 pairs meet a chunk; longer runs (pairs with none) are
+// taken in windows of that size.
+__global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
+    constexpr int W = kKeyChunk + 1;
+    __shared__ uint32_t off[W + 1];
+    __shared__ int32_t info[W][3];  // first global tile of the rect, rect width in tiles, view width in tiles
+    const uint32_t nv = a.counters[kNumVisible];
+    const uint64_t K = min((uint64_t)a.counters[kKeysLo], (uint64_t)a.cap);
+    const uint64_t e0 = (uint64_t)blockIdx.x * kKeyChunk;
+    if (e0 >= K || nv == 0) return;
+    const uint64_t e1 = min(e0 + kKeyChunk, K);
+    uint32_t w0 = a.heads[blockIdx.x];
+    while (true) {
+        // window of pairs [w0, w0 + nw)
+        const uint32_t nw = min((uint32_t)W, nv - w0);
+        for (uint32_t i = threadIdx.x; i < nw; i += 256) {
+            const uint32_t g = w0 + i;
+            off[i] = a.toff[g];
+            const float4 r2 = a.srec[g].r2;
+            const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
+            const int v = __float_as_int(r2.w) & 0x7fffffff;
+            const int tx0 = (int)(rx & 0xffffu) / kTile, tx1 = (int)(rx >> 16) / kTile;
+            const int ty0 = (int)(ry & 0xffffu) / kTile;
+            const ViewDev& vw = a.views[v];
+            info[i][0] = vw.tile_off + ty0 * vw.tiles_x + tx0;
+            info[i][1] = tx1 - tx0 + 1;
+            info[i][2] = vw.tiles_x;
+            if (i == nw - 1) off[nw] = a.toff[g] + a.tcount[g];
         }
-        const uint32_t local = e - off[lo];
-        const uint32_t wdt = (uint32_t)info[lo][1];
-        const uint32_t gt = (uint32_t)info[lo][0] + (local / wdt) * (uint32_t)info[lo][2] + local % wdt;
-        if (e < cap) {
+        __syncthreads();
+        // keys of this chunk owned by the window's pairs
+        const uint64_t k0 = max(e0, (uint64_t)off[0]), k1 = min(e1, (uint64_t)off[nw]);
+        for (uint64_t e = k0 + threadIdx.x; e < k1; e += 256) {
+            // owner: last j with off[j] <= e
+            int lo = 0, hi = (int)nw - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t local = (uint32_t)(e - off[lo]);
+            const uint32_t wdt = (uint32_t)info[lo][1];
+            const uint32_t gt = (uint32_t)info[lo][0] + (local / wdt) * (uint32_t)info[lo][2] + local % wdt;
             a.keys[e] = gt;
-            a.owner[e] = g0 + lo;
+            a.owner[e] = w0 + lo;
         }
+        // the same for every thread: taken as a scalar, so the loop exit is uniform
+        const int more = __builtin_amdgcn_readfirstlane((uint64_t)off[nw] < e1 && w0 + nw < nv ? 1 : 0);
+        __syncthreads();  // the window is read before it is replaced
+        if (!more) break;
+        w0 += nw;
     }
 }
 
@@ -425,7 +451,11 @@ sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t 
     ka.toff = toff; ka.tcount = tcount; ka.srec = (const Proj*)(ws + P.srec); ka.views = (const ViewDev*)(ws + P.views);
     ka.counters = counters; ka.cap = P.cap;
     ka.keys = (uint32_t*)(ws + P.keys0); ka.owner = (uint32_t*)(ws + P.owner);
-    if (P.vn > 0) emit_keys<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(ka);
+    ka.heads = (uint32_t*)(ws + P.heads);
+    if (P.vn > 0) {
+        chunk_heads<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(ka);
+        emit_keys<<<(unsigned)div_up(P.cap, kKeyChunk), 256, 0, st>>>(ka);
+    }
     const int passes = radix_sort((uint32_t*)(ws + P.keys0), (uint32_t*)(ws + P.vals0), (uint32_t*)(ws + P.keys1),
                                   (uint32_t*)(ws + P.vals1), true, device_count(counters + kKeysLo, (uint32_t)P.cap),
                                   (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st);

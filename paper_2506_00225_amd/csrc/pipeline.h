@@ -26,7 +26,7 @@ struct Plan {
     size_t count = 0, zbits = 0, gp_of_lin = 0;
     size_t vis_k0 = 0, vis_v0 = 0, vis_k1 = 0, vis_v1 = 0, order = 0;
     size_t srec = 0, scol = 0, ssv = 0, ssi = 0, tcount = 0, toff = 0;
-    size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, sgp = 0, ranges = 0;
+    size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, sgp = 0, ranges = 0, heads = 0;
     size_t sorted_keys = 0, sorted_vals = 0;
     size_t hist = 0, partial = 0;
     size_t pix_T = 0, pix_last = 0;
@@ -69,7 +69,10 @@ struct KeyArgs {
     const uint32_t* counters;
     int64_t cap;
     uint32_t *keys, *owner;
+    uint32_t* heads;  // [cap / kKeyChunk + 1]: owner of each chunk's first key
 };
+
+constexpr int kKeyChunk = 2048;  // keys emitted per workgroup
 
 sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st,
                           const float* d_poses = nullptr);

@@ -290,25 +290,33 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
 #pragma unroll
                 for (int q = 0; q < NREG; q++) val[q] = 0.f;
                 const float4 col = s_col[j];
-                // the pixel's dL/dsem at the key's top-k classes
-                float sg[KM];
-                float es = 0.f;
+                // the key's class words; the pixel's dL/dsem at its top-k
+                // classes (dense form) and their sum weighted by the key's
+                // values (only when the semantic loss reaches alpha)
+                uint32_t cw[KWM];
+                const float* sv = s_sv + j * k;
                 {
-                    const float* sv = s_sv + j * k;
                     const uint32_t* si = s_si + j * kw;
 #pragma unroll
-                    for (int mw = 0; mw < KWM; mw++) {
-                        if (KT == 0 && mw >= kw) break;
-                        const uint32_t word = si[mw];
+                    for (int mw = 0; mw < KWM; mw++) cw[mw] = (KT > 0 || mw < kw) ? si[mw] : 0u;
+                }
+                float sg[KM];
+                float es = 0.f;
+                if constexpr (!SPARSE) {
 #pragma unroll
-                        for (int bb = 0; bb < 4; bb++) {
-                            const int m = mw * 4 + bb;
-                            if (m < k) {
-                                const uint32_t cls = (word >> (8 * bb)) & 0xffu;
-                                if constexpr (SPARSE) sg[m] = (int)cls == lab ? gl : 0.f;
-                                else sg[m] = gp[cls * kAccStride + tid];
-                                es += sv[m] * sg[m];
-                            }
+                    for (int m = 0; m < KM; m++) {
+                        if (m < k) {
+                            const uint32_t cls = (cw[m >> 2] >> (8 * (m & 3))) & 0xffu;
+                            sg[m] = gp[cls * kAccStride + tid];
+                            es += sv[m] * sg[m];
+                        }
+                    }
+                } else if (b.semgeo) {
+#pragma unroll
+                    for (int m = 0; m < KM; m++) {
+                        if (m < k) {
+                            const uint32_t cls = (cw[m >> 2] >> (8 * (m & 3))) & 0xffu;
+                            es += sv[m] * ((int)cls == lab ? gl : 0.f);
                         }
                     }
                 }
@@ -339,9 +347,17 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
                 val[7] = act ? w * gC1 : 0.f;
                 val[8] = act ? w * gC2 : 0.f;
                 val[9] = act ? w * gD : 0.f;
+                if constexpr (SPARSE) {
+                    // one class per pixel: w gl where the key's class is the label
+                    const float wg = act ? w * gl : 0.f;
 #pragma unroll
-                for (int m = 0; m < KM; m++)
-                    if (m < k) val[10 + m] = act ? w * sg[m] : 0.f;
+                    for (int m = 0; m < KM; m++)
+                        if (m < k) val[10 + m] = (int)((cw[m >> 2] >> (8 * (m & 3))) & 0xffu) == lab ? wg : 0.f;
+                } else {
+#pragma unroll
+                    for (int m = 0; m < KM; m++)
+                        if (m < k) val[10 + m] = act ? w * sg[m] : 0.f;
+                }
                 float* dst = part + (wv * kBwdBatch + j) * NV;
                 if ((any & (any - 1)) == 0) {
                     // one active lane: its values are the wave's sums
