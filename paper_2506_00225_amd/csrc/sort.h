@@ -9,6 +9,9 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = 256 * kScanItems;
 constexpr int kRadixItems = 16;
 constexpr int kRadixTile = 256 * kRadixItems;
+// Up to this many radix blocks, each scatter workgroup forms its own digit
+// offsets from the raw per-block counts instead of a scan over them.
+constexpr uint32_t kRadixFewBlocks = 512;
 
 // Element count of a scan or sort: *d_n if d_n is set (device-resident,
 // known only on the GPU), else host_n; clamped to cap when cap != 0.

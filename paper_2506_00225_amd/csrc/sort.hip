@@ -90,13 +90,25 @@ __global__ __launch_bounds__(256) void scan_partials(uint32_t* __restrict__ part
     }
 }
 
-// Exclusive scan of `in` into `out` (may alias) using the scanned partials.
+// Exclusive scan of `in` into `out` (may alias) from the block sums: each
+// workgroup adds up the sums of the blocks before it (integers, so the
+// order does not matter), which saves a separate scan of the sums.  The last
+// block writes the total (and the saturating capacity check).
 __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec cs,
-                                                  const uint32_t* __restrict__ partial, uint32_t* out) {
+                                                  const uint32_t* __restrict__ partial, uint32_t* out,
+                                                  uint32_t* __restrict__ total_out, uint32_t cap,
+                                                  uint32_t* __restrict__ status) {
     __shared__ uint32_t wsum[4];
     const uint32_t n = count_of(cs);
     const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
-    if (blockIdx.x >= nblk) return;
+    if (blockIdx.x >= nblk) {
+        if (nblk == 0 && blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = 0;  // empty input
+        return;
+    }
+    uint32_t before = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += 256) before += partial[i];
+    uint32_t prefix;
+    block_exscan(before, wsum, &prefix);
     const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
     uint32_t v[kScanItems], s = 0;
 #pragma unroll
@@ -106,12 +118,17 @@ __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec 
         s += v[r];
     }
     uint32_t tot;
-    uint32_t pre = block_exscan(s, wsum, &tot) + partial[blockIdx.x];
+    uint32_t pre = block_exscan(s, wsum, &tot) + prefix;
 #pragma unroll
     for (int r = 0; r < kScanItems; r++) {
         const uint32_t i = base + r;
         if (i < n) out[i] = pre;
         pre += v[r];
+    }
+    if (blockIdx.x == nblk - 1 && threadIdx.x == 0) {
+        const uint32_t total = prefix + tot;
+        if (total_out) *total_out = total;
+        if (status && total > cap) atomicOr(status, (uint32_t)SGR_ECAPACITY);
     }
 }
 
@@ -124,12 +141,14 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t ma
     const uint32_t nblk_max = (uint32_t)div_up(max_n, kScanTile);
     if (nblk_max == 0) return;
     scan_block_sums<false><<<nblk_max, 256, 0, st>>>(in, cs, partial);
-    scan_partials<<<1, 256, 0, st>>>(partial, cs, total_out, cap, status);
-    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out);
+    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out, total_out, cap, status);
 }
 
 // ------------------------------------------------------------------ radix
 
+// Per-block digit counts: digit-major (hist[d * nblk + b], the order of the
+// scan over them) or, BLOCK_MAJOR, hist[b * 256 + d].
+template <bool BLOCK_MAJOR>
 __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ keys, CountSpec cs, int shift,
                                                   uint32_t* __restrict__ hist) {
     __shared__ uint32_t cnt[256];
@@ -145,12 +164,19 @@ __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ k
         if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    if (BLOCK_MAJOR) hist[blockIdx.x * 256 + threadIdx.x] = cnt[threadIdx.x];
+    else hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
 }
 
 // Stable scatter of one 8-bit digit.  Items are taken in index order, 256
 // per round; within a wave the rank among equal digits comes from eight
 // ballots, across the four waves from per-digit wave counts in LDS.
+// SCANNED: hist holds the exclusive scan over (digit, block).  Otherwise it
+// holds the raw counts, block-major, and each workgroup forms its own starting offsets:
+// the counts of its digit in earlier blocks plus, over all blocks, the counts
+// of smaller digits (used when there are few blocks; it saves three scan
+// launches per pass).
+template <bool SCANNED>
 __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict__ kin,
                                                      const uint32_t* __restrict__ vin,
                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -162,7 +188,19 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
     const uint32_t nblk = (uint32_t)div_up(n, kRadixTile);
     if (blockIdx.x >= nblk) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    run[tid] = hist[tid * nblk + blockIdx.x];
+    if constexpr (SCANNED) {
+        run[tid] = hist[tid * nblk + blockIdx.x];
+    } else {
+        uint32_t before = 0, all = 0;
+#pragma unroll 8
+        for (uint32_t b = 0; b < nblk; b++) {  // coalesced: the 256 digits of block b are adjacent
+            const uint32_t c = hist[b * 256 + tid];
+            all += c;
+            before += b < blockIdx.x ? c : 0u;
+        }
+        uint32_t tot;
+        run[tid] = block_exscan(all, wc[0], &tot) + before;  // wc[0] as scratch, cleared below
+    }
 #pragma unroll
     for (int j = 0; j < 4; j++) wc[j][tid] = 0;
     __syncthreads();
@@ -212,11 +250,17 @@ int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* v
     uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
     CountSpec hs = cs;
     hs.radix_blocks = 1;
+    const bool few = nblk_max <= kRadixFewBlocks;
     for (int p = 0; p < passes; p++) {
-        radix_hist<<<nblk_max, 256, 0, st>>>(ki, cs, 8 * p, hist);
-        scan_exclusive(hist, hist, hs, 256u * nblk_max, partial, nullptr, 0, nullptr, st);
-        radix_scatter<<<nblk_max, 256, 0, st>>>(ki, (p == 0 && vals_identity) ? nullptr : vi, ko, vo, cs, 8 * p,
-                                                hist);
+        if (few) radix_hist<true><<<nblk_max, 256, 0, st>>>(ki, cs, 8 * p, hist);
+        else radix_hist<false><<<nblk_max, 256, 0, st>>>(ki, cs, 8 * p, hist);
+        const uint32_t* vin = (p == 0 && vals_identity) ? nullptr : vi;
+        if (few) {
+            radix_scatter<false><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, 8 * p, hist);
+        } else {
+            scan_exclusive(hist, hist, hs, 256u * nblk_max, partial, nullptr, 0, nullptr, st);
+            radix_scatter<true><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, 8 * p, hist);
+        }
         uint32_t* t;
         t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
