@@ -269,8 +269,10 @@ __global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
         if (lane < nb) {
             const float4 q2 = s_r2[lane];
             const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-            hit = b0 + lane < wlast && (int)(rx & 0xffffu) <= wx0 + 7 && (int)(rx >> 16) >= wx0 &&
-                  (int)(ry & 0xffffu) <= wy0 + 7 && (int)(ry >> 16) >= wy0;
+            const int bx0 = max(wx0, (int)(rx & 0xffffu)), bx1 = min(wx0 + 7, (int)(rx >> 16));
+            const int by0 = max(wy0, (int)(ry & 0xffffu)), by1 = min(wy0 + 7, (int)(ry >> 16));
+            hit = b0 + lane < wlast && bx0 <= bx1 && by0 <= by1;
+            if (hit) hit = conic_meets_block(s_r0[lane], s_r1[lane], bx0, bx1, by0, by1, amin);
             if (!hit) flag[wv * kBwdBatch + lane] = 0u;
         }
         uint64_t todo = __ballot(hit);

@@ -172,6 +172,37 @@ __device__ __forceinline__ float eval_alpha(const float4& q0, const float4& q1, 
     return fminf(amax, q1.w * g);
 }
 
+// Whether an entry can reach alpha >= alpha_min at some pixel centre of the
+// block of pixels [bx0, bx1] x [by0, by1] (already clipped to the entry's
+// rectangle).  The exponent e = ca u^2 + cc dy^2 (u = dx + cb dy, the form
+// eval_alpha evaluates) is minimised over the continuous box spanned by the
+// block's pixel centres, a lower bound of its minimum over the pixels, and
+// compared with log2(o / alpha_min) plus slack for rounding.  It only answers
+// false where no pixel of the block passes the alpha cutoff, so skipping
+// such an entry changes no result.  (The rectangle is the box of the whole
+// ellipse; a block near one of its corners often misses the ellipse.)
+__device__ __forceinline__ bool conic_meets_block(const float4& q0, const float4& q1, int bx0, int bx1, int by0,
+                                                  int by1, float amin) {
+    const float x0 = (float)(bx0 - __float_as_int(q0.x)) + (0.5f - q0.z);
+    const float x1 = x0 + (float)(bx1 - bx0);
+    const float y0 = (float)(by0 - __float_as_int(q0.y)) + (0.5f - q0.w);
+    const float y1 = y0 + (float)(by1 - by0);
+    const float ca = q1.x, cb = q1.y, cc = q1.z;
+    // along a row y: u = dx + cb y is smallest at dx = -cb y
+    const float xa = fminf(fmaxf(-cb * y0, x0), x1), xb = fminf(fmaxf(-cb * y1, x0), x1);
+    const float ua = fmaf(cb, y0, xa), ub = fmaf(cb, y1, xb);
+    const float ea = fmaf(ca * ua, ua, cc * y0 * y0), eb = fmaf(ca * ub, ub, cc * y1 * y1);
+    // along a column x: e is smallest at dy = -ca cb x / (ca cb^2 + cc)
+    const float k = -ca * cb * __builtin_amdgcn_rcpf(fmaf(ca * cb, cb, cc));
+    const float yc = fminf(fmaxf(k * x0, y0), y1), yd = fminf(fmaxf(k * x1, y0), y1);
+    const float uc = fmaf(cb, yc, x0), ud = fmaf(cb, yd, x1);
+    const float ec = fmaf(ca * uc, uc, cc * yc * yc), ed = fmaf(ca * ud, ud, cc * yd * yd);
+    const bool inside = x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f;  // the mean's own pixel box
+    const float emin = inside ? 0.f : fminf(fminf(ea, eb), fminf(ec, ed));
+    const float E = __log2f(q1.w / amin);
+    return emin <= E + 1e-3f * (1.f + fabsf(E));
+}
+
 // Writes the tile's class-major LDS columns (one per pixel, stride 257) as
 // [H][W][C] rows: each tile row is one contiguous run of 16 C floats.
 __device__ __forceinline__ void write_rows_from_lds(const float* smem, float* out, const ViewDev& vw, int C, int tx,

@@ -197,8 +197,9 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
         __syncthreads();
         if (b0 + kFwdBatch < end) fetch(b0 + kFwdBatch, (int)min((uint32_t)kFwdBatch, end - b0 - kFwdBatch));
 
-        // Entries whose pixel rectangle meets this wave's block, as two
-        // 64-bit masks (entries lane and 64 + lane).
+        // Entries that can reach a pixel of this wave's block (pixel
+        // rectangle, then ellipse), as two 64-bit masks (entries lane and
+        // 64 + lane).
         bool h0 = false, h1 = false;
 #pragma unroll
         for (int half = 0; half < 2; half++) {
@@ -206,8 +207,10 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
             if (j < nb) {
                 const float4 q2 = s_r2[j];
                 const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-                const bool h = (int)(rx & 0xffffu) <= wx0 + 7 && (int)(rx >> 16) >= wx0 &&
-                               (int)(ry & 0xffffu) <= wy0 + 7 && (int)(ry >> 16) >= wy0;
+                const int bx0 = max(wx0, (int)(rx & 0xffffu)), bx1 = min(wx0 + 7, (int)(rx >> 16));
+                const int by0 = max(wy0, (int)(ry & 0xffffu)), by1 = min(wy0 + 7, (int)(ry >> 16));
+                bool h = bx0 <= bx1 && by0 <= by1;
+                if (h) h = conic_meets_block(s_r0[j], s_r1[j], bx0, bx1, by0, by1, amin);
                 if (half == 0) h0 = h; else h1 = h;
             }
         }
