@@ -115,6 +115,27 @@ def test_forward_ragged_view_and_brute_force():
     U.compare_maps(got, want, want["flags"])
 
 
+def test_forward_thin_rotated_gaussians():
+    """Needle-like Gaussians (one long axis, random rotations) whose pixel
+    rectangles mostly miss the ellipse: the per-block ellipse cull must
+    never drop a blend.  Maps and n_contrib against the oracle, and the
+    backward against the oracle's gradient."""
+    _say("forward thin rotated")
+    sc = scenes.tiny_scene(seed=21, n=1500, width=96, height=80, f=70.0)
+    rng = np.random.default_rng(22)
+    long_axis = rng.integers(0, 3, sc.n)
+    sc.scales[:] = np.float32(0.004)
+    sc.scales[np.arange(sc.n), long_axis] = rng.uniform(0.05, 0.4, sc.n).astype(np.float32)
+    q = rng.standard_normal((sc.n, 4))
+    sc.quats[:] = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
+    sc.opacity[:] = rng.uniform(0.3, 0.99, sc.n).astype(np.float32)
+    fr, got, pr, want = _forward_case(sc)
+    rep = U.compare_maps(got, want, want["flags"])
+    assert rep["flagged"] <= 20, rep
+    assert int(want["n_contrib"].sum()) > 20 * sc.cameras[0].width  # the needles do overlap pixels
+    _backward_case(sc, 0)
+
+
 def test_forward_room_full_frame():
     """200k Gaussians in the room at 1200x680 (the forward+backward workload)."""
     _say("forward room 200k 1200x680")
