@@ -1,6 +1,8 @@
 // Scan and radix-sort launchers (device code in sort.hip).
 #pragma once
 
+#include <algorithm>
+
 #include "sgr_internal.h"
 
 namespace sgr {
@@ -9,8 +11,11 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = 256 * kScanItems;
 constexpr int kRadixItems = 16;
 constexpr int kRadixTile = 256 * kRadixItems;
-// Up to this many radix blocks, each scatter workgroup forms its own digit
-// offsets from the raw per-block counts instead of a scan over them.
+// Small sorts (up to kRadixFewBlocks tiles of kRadixTileSmall items) use
+// smaller tiles, for more workgroups, and each scatter workgroup forms its
+// own digit offsets from the raw per-block counts instead of a scan.
+constexpr int kRadixItemsSmall = 8;
+constexpr int kRadixTileSmall = 256 * kRadixItemsSmall;
 constexpr uint32_t kRadixFewBlocks = 512;
 
 // Element count of a scan or sort: *d_n if d_n is set (device-resident,
@@ -44,7 +49,9 @@ void scan_flag_partials(const uint32_t* in, uint32_t n, uint32_t* partial, uint3
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
                CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st);
 
-inline size_t radix_hist_words(uint32_t max_n) { return 256u * (size_t)div_up(max_n, kRadixTile); }
+inline size_t radix_hist_words(uint32_t max_n) {
+    return 256u * (size_t)std::max(div_up(max_n, kRadixTile), div_up(max_n, kRadixTileSmall));
+}
 inline size_t scan_partial_words(size_t max_n) { return (size_t)div_up((int64_t)max_n, kScanTile) + 1; }
 
 }  // namespace sgr

@@ -148,18 +148,19 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t ma
 
 // Per-block digit counts: digit-major (hist[d * nblk + b], the order of the
 // scan over them) or, BLOCK_MAJOR, hist[b * 256 + d].
-template <bool BLOCK_MAJOR>
+template <bool BLOCK_MAJOR, int ITEMS>
 __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ keys, CountSpec cs, int shift,
                                                   uint32_t* __restrict__ hist) {
+    constexpr uint32_t TILE = 256u * ITEMS;
     __shared__ uint32_t cnt[256];
     const uint32_t n = count_of(cs);
-    const uint32_t nblk = (uint32_t)div_up(n, kRadixTile);
+    const uint32_t nblk = (uint32_t)div_up(n, TILE);
     if (blockIdx.x >= nblk) return;
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t base = blockIdx.x * kRadixTile;
+    const uint32_t base = blockIdx.x * TILE;
 #pragma unroll 4
-    for (int r = 0; r < kRadixItems; r++) {
+    for (int r = 0; r < ITEMS; r++) {
         const uint32_t i = base + r * 256 + threadIdx.x;
         if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
     }
@@ -176,16 +177,17 @@ __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ k
 // the counts of its digit in earlier blocks plus, over all blocks, the counts
 // of smaller digits (used when there are few blocks; it saves three scan
 // launches per pass).
-template <bool SCANNED>
+template <bool SCANNED, int ITEMS>
 __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict__ kin,
                                                      const uint32_t* __restrict__ vin,
                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                      CountSpec cs, int shift,
                                                      const uint32_t* __restrict__ hist) {
+    constexpr uint32_t TILE = 256u * ITEMS;
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[4][256];
     const uint32_t n = count_of(cs);
-    const uint32_t nblk = (uint32_t)div_up(n, kRadixTile);
+    const uint32_t nblk = (uint32_t)div_up(n, TILE);
     if (blockIdx.x >= nblk) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if constexpr (SCANNED) {
@@ -205,8 +207,8 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
     for (int j = 0; j < 4; j++) wc[j][tid] = 0;
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t base = blockIdx.x * kRadixTile;
-    for (int r = 0; r < kRadixItems; r++) {
+    const uint32_t base = blockIdx.x * TILE;
+    for (int r = 0; r < ITEMS; r++) {
         const uint32_t i = base + r * 256 + tid;
         const bool valid = i < n;
         const uint32_t key = valid ? kin[i] : 0u;
@@ -246,20 +248,22 @@ int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* v
                CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st) {
     const uint32_t nblk_max = (uint32_t)div_up(max_n, kRadixTile);
     if (nblk_max == 0) return 0;
+    // few: small tiles (more workgroups for a small sort) and offsets formed in the scatter
+    const uint32_t nblk_small = (uint32_t)div_up(max_n, kRadixTileSmall);
     int passes = (bits + 7) / 8;
     uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
     CountSpec hs = cs;
     hs.radix_blocks = 1;
-    const bool few = nblk_max <= kRadixFewBlocks;
+    const bool few = nblk_small <= kRadixFewBlocks;
     for (int p = 0; p < passes; p++) {
-        if (few) radix_hist<true><<<nblk_max, 256, 0, st>>>(ki, cs, 8 * p, hist);
-        else radix_hist<false><<<nblk_max, 256, 0, st>>>(ki, cs, 8 * p, hist);
+        if (few) radix_hist<true, kRadixItemsSmall><<<nblk_small, 256, 0, st>>>(ki, cs, 8 * p, hist);
+        else radix_hist<false, kRadixItems><<<nblk_max, 256, 0, st>>>(ki, cs, 8 * p, hist);
         const uint32_t* vin = (p == 0 && vals_identity) ? nullptr : vi;
         if (few) {
-            radix_scatter<false><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, 8 * p, hist);
+            radix_scatter<false, kRadixItemsSmall><<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, 8 * p, hist);
         } else {
             scan_exclusive(hist, hist, hs, 256u * nblk_max, partial, nullptr, 0, nullptr, st);
-            radix_scatter<true><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, 8 * p, hist);
+            radix_scatter<true, kRadixItems><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, 8 * p, hist);
         }
         uint32_t* t;
         t = ki; ki = ko; ko = t;
