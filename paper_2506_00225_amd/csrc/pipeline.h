@@ -10,7 +10,7 @@
 namespace sgr {
 
 constexpr int kViewChunk = 16;
-constexpr int kMaxAdamSegs = SGR_MAX_ADAM_SEGMENTS;  // cameras per upload launch (kernel-argument payload)
+constexpr int kMaxAdamSegs = SGR_MAX_ADAM_SEGMENTS;  // segments of one Adam launch
 
 // Workspace layout of one frame: a pure function of the call arguments.
 struct Plan {
