@@ -211,7 +211,7 @@ def roofline(out):
     stage = out["stage_ms"]
     dom = max(alg, key=lambda s: stage[s])
     achieved = alg[dom] / (stage[dom] * 1e-3) / 1e9
-    kern = {"fwd": "render_fwd_kernel", "bwd_tiles": "render_bwd_kernel"}.get(dom, dom)
+    kern = {"fwd": "render_fwd_label_kernel", "bwd_tiles": "render_bwd_kernel"}.get(dom, dom)
     return dom, {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counted_traffic(dom), "kernel": kern,
                  "alg_bytes": int(alg[dom]), "ms": round(stage[dom], 4)}

@@ -553,7 +553,7 @@ __device__ __forceinline__ void write_sem_block(const v32f& acc, float* buf, flo
 }
 
 template <int KT, int SEM, int NB, bool LOSS, int NPASS = 1>
-__global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk) {
+__device__ __forceinline__ void render_fwd_body(const TileArgs& a, const LossK& lk) {
     extern __shared__ __align__(16) float smem[];
     const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
     if (gt >= a.num_tiles) return;
@@ -625,6 +625,19 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk
         if constexpr (NB > 2) write_sem_block<2>(racc.a2, buf, out, vw, C, pairs, wx0, wy0, lane);
         if constexpr (NB > 3) write_sem_block<3>(racc.a3, buf, out, vw, C, pairs, wx0, wy0, lane);
     }
+}
+
+template <int KT, int SEM, int NB, bool LOSS, int NPASS = 1>
+__global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk) {
+    render_fwd_body<KT, SEM, NB, LOSS, NPASS>(a, lk);
+}
+
+// Label-only class sums keep no class sums in LDS, so registers bound the
+// workgroups per CU: the kernel is held to 80 VGPRs, six waves per SIMD
+// (the one value this costs is kept in scratch outside the loops).
+template <int KT>
+__global__ __launch_bounds__(kBlock, 6) void render_fwd_label_kernel(TileArgs a, LossK lk) {
+    render_fwd_body<KT, 4, 1, true, 1>(a, lk);
 }
 
 // ------------------------------------------------------------------ scoring
@@ -1002,15 +1015,15 @@ sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_los
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
     if (P.k == 16) {
         if (sem == 1) fwd_launch_lds<16, true>(passes, a, grid, lds, st, lk);
-        else if (sem == 4) fwd_launch<16, 4, 1, true>(a, grid, lds, st, lk);
+        else if (sem == 4) render_fwd_label_kernel<16><<<grid, kBlock, lds, st>>>(a, lk);
         else fwd_launch<16, 0, 1, true>(a, grid, lds, st, lk);
     } else if (P.k == 3) {
         if (sem == 1) fwd_launch_lds<3, true>(passes, a, grid, lds, st, lk);
-        else if (sem == 4) fwd_launch<3, 4, 1, true>(a, grid, lds, st, lk);
+        else if (sem == 4) render_fwd_label_kernel<3><<<grid, kBlock, lds, st>>>(a, lk);
         else fwd_launch<3, 0, 1, true>(a, grid, lds, st, lk);
     } else {
         if (sem == 1) fwd_launch_lds<0, true>(passes, a, grid, lds, st, lk);
-        else if (sem == 4) fwd_launch<0, 4, 1, true>(a, grid, lds, st, lk);
+        else if (sem == 4) render_fwd_label_kernel<0><<<grid, kBlock, lds, st>>>(a, lk);
         else fwd_launch<0, 0, 1, true>(a, grid, lds, st, lk);
     }
     loss_reduce_kernel<<<P.V, 256, 0, st>>>((const ViewDev*)(ws + P.views), lk.tile_loss,
