@@ -6,8 +6,11 @@
 
 namespace sgr {
 
-constexpr int kBwdBatch = 64;  // keys per batch: one per lane of the culling ballot
-static_assert(kBwdBatch == 64, "the backward culls a batch with one 64-lane ballot");
+// Keys per batch, each culled by one lane of a 64-lane ballot.  48 keeps the
+// LDS of the one-class semantic gradient at 28 KB, so five workgroups share
+// a CU (64 would take 37 KB and allow four).
+constexpr int kBwdBatch = 48;
+static_assert(kBwdBatch <= 64, "the backward culls a batch with one 64-lane ballot");
 
 // Sum over the 64 lanes of a wave; the total lands in lane 63.  Row-wise
 // inclusive scan with row_shr (zero fill), then row_bcast:15 / row_bcast:31
@@ -105,8 +108,11 @@ __device__ __forceinline__ int transposed_value_index(int lane) {
 // SPARSE: no view has a dense dL/dsem; each pixel's semantic gradient is one
 // (class, value) pair (or none), held in registers instead of a 257-float
 // LDS column per class, which leaves room for more workgroups per CU.
+// With k fixed at compile time the kernel is held to 96 VGPRs for five waves
+// per SIMD, matching the five workgroups the LDS allows (the staging
+// registers of the next batch go to scratch once per batch, not per key).
 template <int KT, bool SPARSE>
-__global__ __launch_bounds__(kBwdThreads) void render_bwd_kernel(BwdArgs b) {
+__global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void render_bwd_kernel(BwdArgs b) {
     extern __shared__ __align__(16) float smem[];
     const TileArgs& a = b.t;
     const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
