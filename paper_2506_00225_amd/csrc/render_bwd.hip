@@ -109,8 +109,7 @@ __device__ __forceinline__ int transposed_value_index(int lane) {
 // (class, value) pair (or none), held in registers instead of a 257-float
 // LDS column per class, which leaves room for more workgroups per CU.
 // With k fixed at compile time the kernel is held to 96 VGPRs for five waves
-// per SIMD, matching the five workgroups the LDS allows (the staging
-// registers of the next batch go to scratch once per batch, not per key).
+// per SIMD, matching the five workgroups the LDS allows.
 template <int KT, bool SPARSE>
 __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void render_bwd_kernel(BwdArgs b) {
     extern __shared__ __align__(16) float smem[];
@@ -207,40 +206,46 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
     const int wx0 = tx * kTile + (wv & 1) * 8, wy0 = ty * kTile + (wv >> 1) * 8;  // this wave's 8x8 block
     float R = 0.f;
 
-    // Staging registers: thread j < kBwdBatch carries key j's record, colour
-    // and emission index, thread 128 + j its top-k values and class indices.
-    // The next batch is fetched into them while the current one is composited.
-    float4 p0 = {}, p1 = {}, p2 = {}, pc = {};
-    uint32_t pe = 0;
-    float psv[KM];
-    uint32_t psi[KWM];
+    // Staging registers: the four waves each carry a quarter of the next
+    // batch while the current one is composited.  For key j: lane j of wave
+    // 0 holds r0 and r1, of wave 1 r2, the colour and the emission index, of
+    // waves 2 and 3 each half of the top-k values and class words.
+    constexpr int VH = (KM + 1) / 2, WH = (KWM + 1) / 2;  // values / words of the first half
+    constexpr int NSTG = (VH + WH) > 9 ? (VH + WH) : 9;
+    uint32_t stg[NSTG];
+#pragma unroll
+    for (int q = 0; q < NSTG; q++) stg[q] = 0u;
+    const int role = tid >> 6, rl = tid & 63;
+    auto put4 = [&](int at, const float4& v) {
+        stg[at] = __float_as_uint(v.x); stg[at + 1] = __float_as_uint(v.y);
+        stg[at + 2] = __float_as_uint(v.z); stg[at + 3] = __float_as_uint(v.w);
+    };
+    auto get4 = [&](int at) {
+        return make_float4(__uint_as_float(stg[at]), __uint_as_float(stg[at + 1]), __uint_as_float(stg[at + 2]),
+                           __uint_as_float(stg[at + 3]));
+    };
     auto fetch = [&](uint32_t f0, int fn) {
-        if (tid < fn) {
-            const uint32_t g = a.sgp[f0 + tid];
-            const Proj p = a.srec[g];
-            p0 = p.r0;
-            p1 = p.r1;
-            p2 = p.r2;
-            pc = a.scol[g];
-            pe = b.svals[f0 + tid];
-        } else if (tid >= 128 && tid - 128 < fn) {
-            const uint32_t g = a.sgp[f0 + tid - 128];
+        if (rl >= fn) return;
+        const uint32_t g = a.sgp[f0 + rl];
+        if (role == 0) {
+            const float4* rp = (const float4*)(a.srec + g);
+            put4(0, rp[0]);
+            put4(4, rp[1]);
+        } else if (role == 1) {
+            const float4* rp = (const float4*)(a.srec + g);
+            put4(0, rp[2]);
+            put4(4, a.scol[g]);
+            stg[8] = b.svals[f0 + rl];
+        } else {
+            const int v0 = role == 2 ? 0 : VH, w0 = role == 2 ? 0 : WH;
             const float* sv = a.ssv + (size_t)g * k;
-            if constexpr (KT > 0 && (KT & 3) == 0) {
-#pragma unroll
-                for (int m = 0; m < KM; m += 4) {
-                    const float4 v4 = *(const float4*)(sv + m);
-                    psv[m] = v4.x; psv[m + 1] = v4.y; psv[m + 2] = v4.z; psv[m + 3] = v4.w;
-                }
-            } else {
-#pragma unroll
-                for (int m = 0; m < KM; m++)
-                    if (m < k) psv[m] = sv[m];
-            }
             const uint32_t* si = (const uint32_t*)(a.ssi) + (size_t)g * kw;
 #pragma unroll
-            for (int m = 0; m < KWM; m++)
-                if (m < kw) psi[m] = si[m];
+            for (int m = 0; m < VH; m++)
+                if (v0 + m < k && v0 + m < KM) stg[m] = __float_as_uint(sv[v0 + m]);
+#pragma unroll
+            for (int m = 0; m < WH; m++)
+                if (w0 + m < kw && w0 + m < KWM) stg[VH + m] = si[w0 + m];
         }
     };
 
@@ -249,20 +254,23 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
     if (bend > (int64_t)start) fetch(b0, (int)(bend - b0));
     while (bend > (int64_t)start) {
         const int nb = (int)(bend - b0);
-        if (tid < nb) {
-            s_r0[tid] = p0;
-            s_r1[tid] = p1;
-            s_r2[tid] = p2;
-            s_col[tid] = pc;
-            s_e[tid] = pe;
-        } else if (tid >= 128 && tid - 128 < nb) {
-            const int j = tid - 128;
+        if (rl < nb) {
+            if (role == 0) {
+                s_r0[rl] = get4(0);
+                s_r1[rl] = get4(4);
+            } else if (role == 1) {
+                s_r2[rl] = get4(0);
+                s_col[rl] = get4(4);
+                s_e[rl] = stg[8];
+            } else {
+                const int v0 = role == 2 ? 0 : VH, w0 = role == 2 ? 0 : WH;
 #pragma unroll
-            for (int m = 0; m < KM; m++)
-                if (m < k) s_sv[j * k + m] = psv[m];
+                for (int m = 0; m < VH; m++)
+                    if (v0 + m < k && v0 + m < KM) s_sv[rl * k + v0 + m] = __uint_as_float(stg[m]);
 #pragma unroll
-            for (int m = 0; m < KWM; m++)
-                if (m < kw) s_si[j * kw + m] = psi[m];
+                for (int m = 0; m < WH; m++)
+                    if (w0 + m < kw && w0 + m < KWM) s_si[rl * kw + w0 + m] = stg[VH + m];
+            }
         }
         __syncthreads();
         const int64_t nend = b0;
