@@ -20,7 +20,8 @@ constexpr uint32_t kRadixFewBlocks = 512;
 
 // Element count of a scan or sort: *d_n if d_n is set (device-resident,
 // known only on the GPU), else host_n; clamped to cap when cap != 0.
-// radix_blocks: the count is 256 digit bins times the radix block count of n.
+// radix_blocks: if set, the count is radix_blocks digit bins times the radix
+// block count of n.
 struct CountSpec {
     const uint32_t* d_n;
     uint32_t host_n;
@@ -43,7 +44,8 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t ma
 void scan_flag_partials(const uint32_t* in, uint32_t n, uint32_t* partial, uint32_t* total_out, hipStream_t st);
 
 // Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
-// 8 bits per pass, ping-ponging between the a and b buffers.  Returns the
+// at most 8 bits per pass (spread evenly), ping-ponging between the a and b
+// buffers.  Returns the
 // pass count: the result is in the a buffers when it is even, else in b.
 // vals_identity: the a values are not read; value i is taken to be i.
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,

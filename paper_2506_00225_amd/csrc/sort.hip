@@ -8,7 +8,7 @@ namespace sgr {
 __device__ __forceinline__ uint32_t count_of(const CountSpec& c) {
     uint32_t n = c.d_n ? *c.d_n : c.host_n;
     if (c.cap && n > c.cap) n = c.cap;
-    if (c.radix_blocks) n = 256u * (uint32_t)div_up(n, kRadixTile);
+    if (c.radix_blocks) n = c.radix_blocks * (uint32_t)div_up(n, kRadixTile);
     return n;
 }
 
@@ -146,11 +146,14 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t ma
 
 // ------------------------------------------------------------------ radix
 
-// Per-block digit counts: digit-major (hist[d * nblk + b], the order of the
-// scan over them) or, BLOCK_MAJOR, hist[b * 256 + d].
-template <bool BLOCK_MAJOR, int ITEMS>
+// Per-block counts of the digit (key >> shift) & (2^dbits - 1): digit-major
+// (hist[d * nblk + b], the order of the scan over them) or, BLOCK_MAJOR,
+// hist[b * 2^dbits + d].
+// DBITS: the digit width if fixed at compile time (8), else 0 and dbits.
+template <bool BLOCK_MAJOR, int ITEMS, int DBITS>
 __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ keys, CountSpec cs, int shift,
-                                                  uint32_t* __restrict__ hist) {
+                                                  int dbits_rt, uint32_t* __restrict__ hist) {
+    const int dbits = DBITS > 0 ? DBITS : dbits_rt;
     constexpr uint32_t TILE = 256u * ITEMS;
     __shared__ uint32_t cnt[256];
     const uint32_t n = count_of(cs);
@@ -162,11 +165,14 @@ __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ k
 #pragma unroll 4
     for (int r = 0; r < ITEMS; r++) {
         const uint32_t i = base + r * 256 + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & ((1u << dbits) - 1u)], 1u);
     }
     __syncthreads();
-    if (BLOCK_MAJOR) hist[blockIdx.x * 256 + threadIdx.x] = cnt[threadIdx.x];
-    else hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    const uint32_t bins = 1u << dbits;
+    if (DBITS == 8 || threadIdx.x < bins) {  // (every thread when the digit has 8 bits)
+        if (BLOCK_MAJOR) hist[blockIdx.x * bins + threadIdx.x] = cnt[threadIdx.x];
+        else hist[threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    }
 }
 
 // Stable scatter of one 8-bit digit.  Items are taken in index order, 256
@@ -177,12 +183,13 @@ __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ k
 // the counts of its digit in earlier blocks plus, over all blocks, the counts
 // of smaller digits (used when there are few blocks; it saves three scan
 // launches per pass).
-template <bool SCANNED, int ITEMS>
+template <bool SCANNED, int ITEMS, int DBITS>
 __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict__ kin,
                                                      const uint32_t* __restrict__ vin,
                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                     CountSpec cs, int shift,
+                                                     CountSpec cs, int shift, int dbits_rt,
                                                      const uint32_t* __restrict__ hist) {
+    const int dbits = DBITS > 0 ? DBITS : dbits_rt;
     constexpr uint32_t TILE = 256u * ITEMS;
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[4][256];
@@ -190,13 +197,15 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
     const uint32_t nblk = (uint32_t)div_up(n, TILE);
     if (blockIdx.x >= nblk) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t bins = 1u << dbits, mask = bins - 1u;
+    const bool has_bin = DBITS == 8 || (uint32_t)tid < bins;  // thread tid owns digit tid
     if constexpr (SCANNED) {
-        run[tid] = hist[tid * nblk + blockIdx.x];
+        run[tid] = has_bin ? hist[tid * nblk + blockIdx.x] : 0u;
     } else {
         uint32_t before = 0, all = 0;
 #pragma unroll 8
-        for (uint32_t b = 0; b < nblk; b++) {  // coalesced: the 256 digits of block b are adjacent
-            const uint32_t c = hist[b * 256 + tid];
+        for (uint32_t b = 0; b < nblk; b++) {  // coalesced: the digits of block b are adjacent
+            const uint32_t c = has_bin ? hist[b * bins + tid] : 0u;
             all += c;
             before += b < blockIdx.x ? c : 0u;
         }
@@ -213,13 +222,15 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
         const bool valid = i < n;
         const uint32_t key = valid ? kin[i] : 0u;
         const uint32_t val = valid ? (vin ? vin[i] : i) : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t d = (key >> shift) & mask;
         uint64_t match = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            match &= bit ? bb : ~bb;
+            if (b < dbits) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                match &= bit ? bb : ~bb;
+            }
         }
         const uint32_t rank = __popcll(match & lt);
         if (valid && rank == 0) wc[w][d] = __popcll(match);
@@ -250,20 +261,33 @@ int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* v
     if (nblk_max == 0) return 0;
     // few: small tiles (more workgroups for a small sort) and offsets formed in the scatter
     const uint32_t nblk_small = (uint32_t)div_up(max_n, kRadixTileSmall);
-    int passes = (bits + 7) / 8;
+    // passes of at most 8 bits, the bits spread evenly (12 bits: two 6-bit
+    // digits, whose 64 buckets keep the scatter's writes in longer runs)
+    const int passes = (bits + 7) / 8;
+    const int dbits = passes > 0 ? (bits + passes - 1) / passes : 8;
+    const uint32_t bins = 1u << dbits;
     uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
     CountSpec hs = cs;
-    hs.radix_blocks = 1;
+    hs.radix_blocks = bins;
     const bool few = nblk_small <= kRadixFewBlocks;
     for (int p = 0; p < passes; p++) {
-        if (few) radix_hist<true, kRadixItemsSmall><<<nblk_small, 256, 0, st>>>(ki, cs, 8 * p, hist);
-        else radix_hist<false, kRadixItems><<<nblk_max, 256, 0, st>>>(ki, cs, 8 * p, hist);
         const uint32_t* vin = (p == 0 && vals_identity) ? nullptr : vi;
+        const int sh = dbits * p;
         if (few) {
-            radix_scatter<false, kRadixItemsSmall><<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, 8 * p, hist);
+            if (dbits == 8) {
+                radix_hist<true, kRadixItemsSmall, 8><<<nblk_small, 256, 0, st>>>(ki, cs, sh, 8, hist);
+                radix_scatter<false, kRadixItemsSmall, 8><<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist);
+            } else {
+                radix_hist<true, kRadixItemsSmall, 0><<<nblk_small, 256, 0, st>>>(ki, cs, sh, dbits, hist);
+                radix_scatter<false, kRadixItemsSmall, 0><<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits,
+                                                                                   hist);
+            }
         } else {
-            scan_exclusive(hist, hist, hs, 256u * nblk_max, partial, nullptr, 0, nullptr, st);
-            radix_scatter<true, kRadixItems><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, 8 * p, hist);
+            if (dbits == 8) radix_hist<false, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, cs, sh, 8, hist);
+            else radix_hist<false, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, cs, sh, dbits, hist);
+            scan_exclusive(hist, hist, hs, bins * nblk_max, partial, nullptr, 0, nullptr, st);
+            if (dbits == 8) radix_scatter<true, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist);
+            else radix_scatter<true, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist);
         }
         uint32_t* t;
         t = ki; ki = ko; ko = t;
