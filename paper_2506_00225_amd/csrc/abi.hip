@@ -133,6 +133,14 @@ __global__ void copy_payload(BytePayload p, uint32_t* dst) {
     for (uint32_t i = threadIdx.x; i < p.nwords; i += blockDim.x) dst[i] = p.words[i];
 }
 
+// Words [0, n1) of the payload to dst1, the rest to dst2.
+__global__ void copy_payload2(BytePayload p, uint32_t n1, uint32_t* dst1, uint32_t* dst2) {
+    for (uint32_t i = threadIdx.x; i < p.nwords; i += blockDim.x) {
+        if (i < n1) dst1[i] = p.words[i];
+        else dst2[i - n1] = p.words[i];
+    }
+}
+
 // Host -> device copy carried in kernel arguments (no host staging buffer,
 // safe to capture in a graph).  bytes must be a multiple of 4.
 void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t st) {
@@ -145,6 +153,22 @@ void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t st) {
         memcpy(p.words, s + off, 4 * p.nwords);
         copy_payload<<<1, 256, 0, st>>>(p, d + off);
     }
+}
+
+// Two host -> device copies in one launch when they fit one payload.
+void upload_pair(void* dst1, const void* src1, size_t bytes1, void* dst2, const void* src2, size_t bytes2,
+                 hipStream_t st) {
+    const size_t w1 = bytes1 / 4, w2 = bytes2 / 4;
+    if (w1 + w2 > 480) {
+        upload_bytes(dst1, src1, bytes1, st);
+        upload_bytes(dst2, src2, bytes2, st);
+        return;
+    }
+    BytePayload p;
+    p.nwords = (uint32_t)(w1 + w2);
+    memcpy(p.words, src1, 4 * w1);
+    memcpy(p.words + w1, src2, 4 * w2);
+    copy_payload2<<<1, 256, 0, st>>>(p, (uint32_t)w1, (uint32_t*)dst1, (uint32_t*)dst2);
 }
 
 __global__ void zero_u32(uint32_t* p) { *p = 0u; }

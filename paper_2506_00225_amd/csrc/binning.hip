@@ -18,10 +18,13 @@ __global__ void upload_views(ViewChunk chunk, ViewDev* views) {
     if (j < chunk.count) views[chunk.first + j] = chunk.v[j];
 }
 
-__global__ void init_frame(uint32_t* counters, uint2* ranges, int64_t num_tiles) {
+// Clears the counters and tile ranges; block 0 also stores one chunk of the
+// view table (count 0: none).
+__global__ void init_frame(uint32_t* counters, uint2* ranges, int64_t num_tiles, ViewChunk chunk, ViewDev* views) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < kNumCounters) counters[i] = 0;
     if (i < num_tiles) ranges[i] = make_uint2(0u, 0u);
+    if (blockIdx.x == 0 && threadIdx.x < chunk.count) views[chunk.first + threadIdx.x] = chunk.v[threadIdx.x];
 }
 
 __global__ void publish_num_keys(const uint32_t* counters, int64_t* d_num_keys) {
@@ -141,11 +144,25 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
 // --------------------------------------------------------------- compaction
 
 // Writes (depth key, view*n + id) of every visible pair in index order.
+// partial[b] holds block b's count of visible pairs; each workgroup adds up
+// those before it, and the last one writes the total to *total.
 __global__ __launch_bounds__(256) void compact_visible(const uint32_t* __restrict__ count,
                                                        const uint32_t* __restrict__ zbits, int64_t vn,
                                                        const uint32_t* __restrict__ partial,
-                                                       uint32_t* __restrict__ out_key, uint32_t* __restrict__ out_val) {
+                                                       uint32_t* __restrict__ out_key, uint32_t* __restrict__ out_val,
+                                                       uint32_t* __restrict__ total) {
     __shared__ uint32_t wsum[4];
+    __shared__ uint32_t s_before;
+    {
+        uint32_t before = 0;
+        for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) before += partial[b];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = before;
+        __syncthreads();
+        if (threadIdx.x == 0) s_before = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
     const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanItems;
     uint32_t f[kScanItems], s = 0;
 #pragma unroll
@@ -164,8 +181,9 @@ __global__ __launch_bounds__(256) void compact_visible(const uint32_t* __restric
     }
     if (lane == 63) wsum[w] = x;
     __syncthreads();
-    uint32_t pre = partial[blockIdx.x] + x - s;
+    uint32_t pre = s_before + x - s;
     for (int j = 0; j < w; j++) pre += wsum[j];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) *total = pre + s;  // every visible pair
 #pragma unroll
     for (int r = 0; r < kScanItems; r++) {
         if (f[r]) {
@@ -392,20 +410,23 @@ __global__ __launch_bounds__(256) void set_view_poses(ViewDev* views, const floa
 sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipStream_t st, const float* d_poses) {
     ViewDev* views = (ViewDev*)(ws + P.views);
     uint32_t* counters = (uint32_t*)(ws + P.counters);
-    // camera table, as kernel arguments
-    for (int first = 0; first < P.V; first += kViewChunk) {
+    // camera table, as kernel arguments: the first chunk with the counter
+    // clear, any further chunks on their own
+    auto chunk = [&](int first) {
         ViewChunk ch;
         memset(&ch, 0, sizeof(ch));
         ch.first = first;
         ch.count = std::min(kViewChunk, P.V - first);
         for (int j = 0; j < ch.count; j++) ch.v[j] = P.view_table[first + j];
-        upload_views<<<1, kViewChunk, 0, st>>>(ch, views);
-    }
-    if (d_poses) set_view_poses<<<(unsigned)div_up(P.V, 256), 256, 0, st>>>(views, d_poses, P.V);
+        return ch;
+    };
     {
         const int64_t nthreads = std::max<int64_t>(P.num_tiles, kNumCounters);
-        init_frame<<<(unsigned)div_up(nthreads, 256), 256, 0, st>>>(counters, (uint2*)(ws + P.ranges), P.num_tiles);
+        init_frame<<<(unsigned)div_up(nthreads, 256), 256, 0, st>>>(counters, (uint2*)(ws + P.ranges), P.num_tiles,
+                                                                    chunk(0), views);
     }
+    for (int first = kViewChunk; first < P.V; first += kViewChunk) upload_views<<<1, kViewChunk, 0, st>>>(chunk(first), views);
+    if (d_poses) set_view_poses<<<(unsigned)div_up(P.V, 256), 256, 0, st>>>(views, d_poses, P.V);
     ProjectArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opacity = g->opacity;
     pa.views = views; pa.n = P.n; pa.vn = P.vn;
@@ -418,9 +439,9 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
     uint32_t* partial = (uint32_t*)(ws + P.partial);
     {
         const uint32_t nblk = (uint32_t)div_up(P.vn, kScanTile);
-        scan_flag_partials(pa.count, (uint32_t)P.vn, partial, counters + kNumVisible, st);
+        scan_flag_sums(pa.count, (uint32_t)P.vn, partial, st);
         compact_visible<<<nblk, 256, 0, st>>>(pa.count, pa.zbits, P.vn, partial, (uint32_t*)(ws + P.vis_k0),
-                                              (uint32_t*)(ws + P.vis_v0));
+                                              (uint32_t*)(ws + P.vis_v0), counters + kNumVisible);
     }
     const int passes = radix_sort((uint32_t*)(ws + P.vis_k0), (uint32_t*)(ws + P.vis_v0), (uint32_t*)(ws + P.vis_k1),
                                   (uint32_t*)(ws + P.vis_v1), false, device_count(counters + kNumVisible, 0),

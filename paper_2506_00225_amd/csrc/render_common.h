@@ -228,6 +228,8 @@ size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode);
 int device_cu_count();
 size_t device_max_lds();
 void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t st);
+void upload_pair(void* dst1, const void* src1, size_t bytes1, void* dst2, const void* src2, size_t bytes2,
+                 hipStream_t st);
 
 __global__ void zero_u32(uint32_t* p);
 

@@ -990,8 +990,8 @@ sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_los
         dense_sem |= lv[v].sem != nullptr || lv[v].g_sem != nullptr;
         sem_map |= mp[v].sem != nullptr;
     }
-    upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
-    upload_bytes(ws + P.loss_table, lp.data(), sizeof(LossPtrs) * P.V, st);
+    upload_pair(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, ws + P.loss_table, lp.data(),
+                sizeof(LossPtrs) * P.V, st);
     a.maps = (const MapPtrs*)(ws + P.map_table);
     LossK lk;
     lk.views = (const LossPtrs*)(ws + P.loss_table);

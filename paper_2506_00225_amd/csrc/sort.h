@@ -38,10 +38,9 @@ inline CountSpec device_count(const uint32_t* d, uint32_t cap) { return CountSpe
 void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
                     uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st);
 
-// Block sums of (in[i] != 0) over in[0..n), scanned: partial[b] is the
-// number of non-zero items before block b (blocks of kScanTile); the total
-// goes to *total_out.
-void scan_flag_partials(const uint32_t* in, uint32_t n, uint32_t* partial, uint32_t* total_out, hipStream_t st);
+// Block sums of (in[i] != 0) over in[0..n): partial[b] is the number of
+// non-zero items in block b (blocks of kScanTile).
+void scan_flag_sums(const uint32_t* in, uint32_t n, uint32_t* partial, hipStream_t st);
 
 // Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
 // at most 8 bits per pass (spread evenly), ping-ponging between the a and b

@@ -57,39 +57,6 @@ __global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restric
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// One workgroup: exclusive scan of partial[0..nblk) in place; writes the
-// grand total to *total_out (and, if given, the saturating capacity check).
-__global__ __launch_bounds__(256) void scan_partials(uint32_t* __restrict__ partial, CountSpec cs,
-                                                     uint32_t* __restrict__ total_out, uint32_t cap,
-                                                     uint32_t* __restrict__ status) {
-    __shared__ uint32_t wsum[4];
-    const uint32_t n = count_of(cs);
-    const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
-    uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < nblk; b0 += 256 * 8) {
-        uint32_t v[8], s = 0;
-#pragma unroll
-        for (int r = 0; r < 8; r++) {
-            const uint32_t i = b0 + threadIdx.x * 8 + r;
-            v[r] = i < nblk ? partial[i] : 0u;
-            s += v[r];
-        }
-        uint32_t tot;
-        uint32_t pre = block_exscan(s, wsum, &tot) + carry;
-#pragma unroll
-        for (int r = 0; r < 8; r++) {
-            const uint32_t i = b0 + threadIdx.x * 8 + r;
-            if (i < nblk) partial[i] = pre;
-            pre += v[r];
-        }
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        if (total_out) *total_out = carry;
-        if (status && carry > cap) atomicOr(status, (uint32_t)SGR_ECAPACITY);
-    }
-}
-
 // Exclusive scan of `in` into `out` (may alias) from the block sums: each
 // workgroup adds up the sums of the blocks before it (integers, so the
 // order does not matter), which saves a separate scan of the sums.  The last
@@ -248,11 +215,10 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
     }
 }
 
-void scan_flag_partials(const uint32_t* in, uint32_t n, uint32_t* partial, uint32_t* total_out, hipStream_t st) {
+void scan_flag_sums(const uint32_t* in, uint32_t n, uint32_t* partial, hipStream_t st) {
     const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
     if (nblk == 0) return;
     scan_block_sums<true><<<nblk, 256, 0, st>>>(in, host_count(n), partial);
-    scan_partials<<<1, 256, 0, st>>>(partial, host_count(n), total_out, 0, nullptr);
 }
 
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
