@@ -375,13 +375,20 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
                         if (m < k) val[10 + m] = act ? w * sg[m] : 0.f;
                 }
                 float* dst = part + (wv * kBwdBatch + j) * NV;
-                if ((any & (any - 1)) == 0) {
+                const bool one = (any & (any - 1)) == 0;
+                if (one) {
                     // one active lane: its values are the wave's sums
                     if (act) {
 #pragma unroll
                         for (int q = 0; q < NREG; q++)
                             if (q < NV) dst[q] = val[q];
                     }
+                }
+                // Two separate regions, the single-lane one first: the
+                // reduction's in-place lane swaps then need no copies of the
+                // values for a single-lane store after them.
+                __builtin_amdgcn_sched_barrier(0);
+                if (one) {
                 } else if constexpr (NP > 0) {
                     const float sum = wave_transpose_sum<NP>(val, lane);
                     const int q = transposed_value_index<NP>(lane);
