@@ -117,7 +117,8 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
     const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
     if (gt >= a.num_tiles) return;
     if (a.counters[kStatus] & SGR_ECAPACITY) return;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, held in a scalar register
     const int k = KT > 0 ? KT : a.k;
     const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
     const int C = a.C;
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
                 const float om = 1.f - alpha;
                 const float rom = __builtin_amdgcn_rcpf(om);
                 const float Tf = T * rom;  // transmittance in front of this Gaussian
-                const float w = alpha * Tf;
+                const float w = act ? alpha * Tf : 0.f;  // blend weight; 0 where this pixel does not blend
                 float e = col.x * gC0 + col.y * gC1 + col.z * gC2 + col.w * gD + gS;
                 if (b.semgeo) e += es;
                 const float dalpha = Tf * e - R * rom;
@@ -359,20 +360,25 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
                 val[4] = dQ * dy * dy;
                 val[0] = -2.f * dQ * (ca * dx + cb * dy);
                 val[1] = -2.f * dQ * (cb * dx + cc * dy);
-                val[6] = act ? w * gC0 : 0.f;
-                val[7] = act ? w * gC1 : 0.f;
-                val[8] = act ? w * gC2 : 0.f;
-                val[9] = act ? w * gD : 0.f;
+                val[6] = w * gC0;
+                val[7] = w * gC1;
+                val[8] = w * gC2;
+                val[9] = w * gD;
                 if constexpr (SPARSE) {
-                    // one class per pixel: w gl where the key's class is the label
-                    const float wg = act ? w * gl : 0.f;
+                    // one class per pixel: w gl where the key's class is the
+                    // label (no class where the pixel does not blend); the
+                    // label is kept in one register, so each class costs a
+                    // compare and a select
+                    const float wg = w * gl;
+                    int labm = act ? lab : -1;
+                    asm volatile("" : "+v"(labm));
 #pragma unroll
                     for (int m = 0; m < KM; m++)
-                        if (m < k) val[10 + m] = (int)((cw[m >> 2] >> (8 * (m & 3))) & 0xffu) == lab ? wg : 0.f;
+                        if (m < k) val[10 + m] = (int)((cw[m >> 2] >> (8 * (m & 3))) & 0xffu) == labm ? wg : 0.f;
                 } else {
 #pragma unroll
                     for (int m = 0; m < KM; m++)
-                        if (m < k) val[10 + m] = act ? w * sg[m] : 0.f;
+                        if (m < k) val[10 + m] = w * sg[m];
                 }
                 float* dst = part + (wv * kBwdBatch + j) * NV;
                 const bool one = (any & (any - 1)) == 0;
