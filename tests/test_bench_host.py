@@ -1,0 +1,33 @@
+"""Host-side checks of the benchmark's roofline bookkeeping (no GPU)."""
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def _out(**stage):
+    base = {"proj": 0.2, "bin": 0.15, "fwd": 0.27, "bwd_tiles": 0.48, "bwd_gather": 0.15, "adam": 0.14}
+    base.update(stage)
+    return {"pixels": 1200 * 680, "C": 102, "k": 16, "keys": 2_500_000, "nvis": 280_000, "n": 1_000_000,
+            "blends": 5.0e7, "stage_ms": base}
+
+
+def test_compositing_stage_is_reported_against_the_alu_peak():
+    dom, r = bench.roofline(_out())
+    assert dom == "bwd_tiles" and r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+    assert r["ops_per_blend"] == 13 + 40 + 3 * 16
+    assert abs(r["achieved"] - 5.0e7 * r["ops_per_blend"] / 0.48e-3 / 1e12) < 1e-3
+    assert abs(r["frac"] - r["achieved"] / bench.FP32_PEAK_TFLOPS) < 1e-4
+    assert 0 < r["hbm_frac"] < 1
+
+
+def test_forward_dominant_uses_forward_count():
+    dom, r = bench.roofline(_out(fwd=0.9))
+    assert dom == "fwd" and r["ops_per_blend"] == 13 + 6 + 16 and r["kernel"] == "render_fwd_label_kernel"
+
+
+def test_memory_stage_is_reported_against_hbm():
+    dom, r = bench.roofline(_out(bwd_gather=2.0))
+    assert dom == "bwd_gather" and r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["frac"] - r["achieved"] / bench.HBM_PEAK_GBS) < 1e-4
