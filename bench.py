@@ -101,12 +101,12 @@ def mapping_bench(args, torch, out):
                      (g.quats, gout["quats"], -inf, inf), (g.opacity, gout["opacity"], 1e-4, 0.9999),
                      (g.rgb, gout["rgb"], -inf, inf), (g.sem_val, gout["sem_val"], 0.0, inf)],
                     lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
-    blends = torch.zeros(args.steps + args.warmup, dtype=torch.int64, device=dev)
+    blends = torch.zeros(2 * args.steps + args.warmup, dtype=torch.int64, device=dev)
 
     targets = {"rgb": t_rgb, "depth": t_depth, "label": label}
     lcfg = loss_config()  # Sec. 3.1 masked depth + 0.5 colour L1, |S - 1|, cross-entropy
     ncon = {"n_contrib": torch.empty(P, dtype=torch.int32, device=dev)}
-    losses = torch.zeros(args.steps + args.warmup, dtype=torch.float64, device=dev)
+    losses = torch.zeros(2 * args.steps + args.warmup, dtype=torch.float64, device=dev)
 
     if not args.no_tune:  # times the fused forward + loss and the backward, as the step runs them
         rep = autotune.tune_mapping(fr, g, reps=3, targets=targets, loss_cfg=lcfg)
@@ -116,8 +116,8 @@ def mapping_bench(args, torch, out):
     names = ["s0", "proj", "bin", "fwd", "bwd_tiles", "bwd_gather", "adam"]
     tm = Timer(torch, names)
 
-    def step(i, timed):
-        mk = tm.mark if timed else (lambda _n: None)
+    def step(i, marked):
+        mk = tm.mark if marked else (lambda _n: None)
         mk("s0")
         fr.project(g)
         mk("proj")
@@ -131,19 +131,33 @@ def mapping_bench(args, torch, out):
         mk("bwd_gather")
         opt.step()
         mk("adam")
-        blends[i].copy_(ncon["n_contrib"].sum(dtype=torch.int64))
-        losses[i].copy_(loss[0])
+        if marked:  # bookkeeping, after the step's last event
+            blends[i].copy_(ncon["n_contrib"].sum(dtype=torch.int64))
+            losses[i].copy_(loss[0])
 
     log("warmup", args.warmup)
     for i in range(args.warmup):
         step(i, False)
     torch.cuda.synchronize()
+    # The timed steps carry no events between stages (each event costs a few
+    # microseconds of idle GPU); the per-stage breakdown, the blend count B
+    # and the losses come from as many further steps with an event at every
+    # stage boundary.
     log("timed", args.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    e0.record()
     for i in range(args.steps):
-        step(args.warmup + i, True)
+        step(args.warmup + i, False)
+    e1.record()
+    enqueue = time.perf_counter() - t0  # host time to issue the steps (well below the GPU time: GPU-bound)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    step_ms = e0.elapsed_time(e1) / args.steps
+    log("breakdown", args.steps)
+    for i in range(args.steps):
+        step(args.warmup + args.steps + i, True)
+    torch.cuda.synchronize()
     st, nvis, nkeys = fr.status()
     if st != 0:
         raise RuntimeError(f"device status {st} after the timed steps (key capacity {fr.key_capacity}, K {nkeys})")
@@ -151,12 +165,13 @@ def mapping_bench(args, torch, out):
     for a, b in zip(names[:-1], names[1:]):
         stage[b] = float(np.mean(tm.pairs_ms(a, b)))
     stage["bwd"] = stage["bwd_tiles"] + stage["bwd_gather"]
-    step_ms = float(np.mean(tm.pairs_ms("s0", "adam")))
-    B = blends[args.warmup:].double().mean().item()
+    marked_ms = float(np.mean(tm.pairs_ms("s0", "adam")))
+    B = blends[args.warmup + args.steps:].double().mean().item()
     fwd_bwd_ms = stage["proj"] + stage["bin"] + stage["fwd"] + stage["bwd"]
-    out.update(dict(step_ms=step_ms, wall_ms=wall * 1e3 / args.steps, stage_ms=stage, blends=B, nvis=nvis, keys=nkeys,
-                    fwd_bwd_ms=fwd_bwd_ms, pixels=P, C=C, k=k, n=sc.n,
-                    loss_first_last=[float(losses[args.warmup]), float(losses[-1])]))
+    out.update(dict(step_ms=step_ms, step_ms_with_stage_events=marked_ms, wall_ms=wall * 1e3 / args.steps,
+                    enqueue_ms=enqueue * 1e3 / args.steps,
+                    stage_ms=stage, blends=B, nvis=nvis, keys=nkeys, fwd_bwd_ms=fwd_bwd_ms, pixels=P, C=C, k=k,
+                    n=sc.n, loss_first_last=[float(losses[args.warmup + args.steps]), float(losses[-1])]))
     log("stages ms", json.dumps({k_: round(v, 4) for k_, v in stage.items()}), "K", nkeys, "Nv", nvis, "B", B)
     return sc
 
@@ -454,7 +469,10 @@ def main():
     value = out["blends"] / (out["step_ms"] * 1e-3)
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "blends/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(out["step_ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": round(out["step_ms"], 4),
+        "ms_per_step_with_stage_events": round(out["step_ms_with_stage_events"], 4),
+        "host_wall_ms_per_step": round(out["wall_ms"], 4), "host_enqueue_ms_per_step": round(out["enqueue_ms"], 4),
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "mapping iteration: 1M Gaussians, 10x8x3 m room, 1200x680 keyframe, C=102, k=16, "
                                "fwd + loss + bwd + Adam", "gaussians": out["n"], "width": 1200, "height": 680,
