@@ -31,7 +31,7 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
 
 struct BwdArgs {
     TileArgs t;
-    const GradPtrs* grads;     // [V]
+    ViewTable<GradPtrs> grads;
     float* slots;              // [cap][nvals]
     uint8_t* touched;          // [cap]
     const uint32_t* svals;     // sorted emission index of each key
@@ -56,12 +56,18 @@ __device__ __forceinline__ float dpp_perm(float x) {
 // every lane holds the full 64-lane sum of value
 //   NP = 32: 16 b1 + 8 b2 + 4 b3 + 2 b4 + b5,   NP = 16: 8 b2 + 4 b3 + 2 b4 + b5
 // (b_i = bit i of the lane id); see transposed_value_index.
-template <int NP>
+// Values from index NREAL on are zero in every lane: swaps of two such
+// values are skipped.
+template <int NP, int NREAL = NP>
 __device__ __forceinline__ float wave_transpose_sum(float (&v)[NP], int lane) {
     static_assert(NP == 16 || NP == 32, "16 or 32 values");
     float r1[NP / 2];
 #pragma unroll
     for (int i = 0; i < NP / 2; i++) {
+        if (2 * i >= NREAL) {
+            r1[i] = 0.f;
+            continue;
+        }
         const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]), __float_as_uint(v[2 * i + 1]),
                                                        false, false);
         r1[i] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
@@ -69,6 +75,10 @@ __device__ __forceinline__ float wave_transpose_sum(float (&v)[NP], int lane) {
     float r2[NP / 4];
 #pragma unroll
     for (int i = 0; i < NP / 4; i++) {
+        if (4 * i >= NREAL) {
+            r2[i] = 0.f;
+            continue;
+        }
         const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(r1[2 * i]), __float_as_uint(r1[2 * i + 1]),
                                                        false, false);
         r2[i] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
@@ -396,7 +406,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
                 __builtin_amdgcn_sched_barrier(0);
                 if (one) {
                 } else if constexpr (NP > 0) {
-                    const float sum = wave_transpose_sum<NP>(val, lane);
+                    const float sum = wave_transpose_sum<NP, (KT > 0 ? 10 + KT : NP)>(val, lane);
                     const int q = transposed_value_index<NP>(lane);
                     if ((lane & (NP == 32 ? 1 : 3)) == 0 && q < NV) dst[q] = sum;
                 } else {
@@ -684,8 +694,7 @@ sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* w
         gpt[v] = GradPtrs{dL[v].rgb, dL[v].depth, dL[v].sil, dL[v].sem, dL[v].sem_label, dL[v].sem_at_label};
         sparse &= dL[v].sem == nullptr;
     }
-    upload_bytes(ws + P.grad_table, gpt.data(), sizeof(GradPtrs) * P.V, st);
-    b.grads = (const GradPtrs*)(ws + P.grad_table);
+    set_view_table(b.grads, gpt, ws + P.grad_table, st);
     b.slots = (float*)(ws + P.slots);
     b.touched = (uint8_t*)(ws + P.touched);
     b.svals = (const uint32_t*)(ws + P.sorted_vals);

@@ -73,6 +73,16 @@ __device__ __forceinline__ void reg_zero(RegAcc<NB>& A) {
     if constexpr (NB > 3) A.a3 = 0.f;
 }
 
+// Per-view pointer tables.  With one view the entry travels inline in the
+// kernel arguments, so no upload launch precedes the kernel; with more it is
+// a table in the workspace.
+template <class T>
+struct ViewTable {
+    const T* table;  // [V] in the workspace, or nullptr: use `one`
+    T one;
+    __device__ __forceinline__ T operator[](int v) const { return table ? table[v] : one; }
+};
+
 struct MapPtrs {
     float *rgb, *depth, *sil, *sem, *t_final;
     int32_t* n_contrib;
@@ -86,7 +96,7 @@ struct LossPtrs {  // one view's loss targets and gradient outputs
 };
 
 struct LossK {  // fused-loss kernel arguments
-    const LossPtrs* views;
+    ViewTable<LossPtrs> views;
     float w_depth, w_rgb, w_sil, w_sem, sil_thresh, ce_floor, lambda_hd, lambda_cos, tau, sqrt_eps;
     double* tile_loss;  // [num_tiles]
 };
@@ -113,8 +123,8 @@ struct TileArgs {
     uint32_t* pix_last;
     float alpha_min, alpha_max, t_min;
     int linear_tiles;  // 1: workgroup i takes tile i; 0: XCD-contiguous runs
-    const MapPtrs* maps;
-    const LossPtrs* loss_views;  // label-only class sums: each view's label map
+    ViewTable<MapPtrs> maps;
+    ViewTable<LossPtrs> loss_views;  // label-only class sums: each view's label map
 };
 
 struct TileResult {
@@ -228,6 +238,20 @@ size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode);
 int device_cu_count();
 size_t device_max_lds();
 void upload_bytes(void* dst, const void* src, size_t bytes, hipStream_t st);
+
+// Fills `t` from the host entries: inline for one view, else uploaded to
+// `dst` in the workspace.
+template <class T>
+void set_view_table(ViewTable<T>& t, const std::vector<T>& entries, char* dst, hipStream_t st) {
+    if (entries.size() == 1) {
+        t.table = nullptr;
+        t.one = entries[0];
+    } else {
+        upload_bytes(dst, entries.data(), sizeof(T) * entries.size(), st);
+        t.table = (const T*)dst;
+        t.one = T{};
+    }
+}
 void upload_pair(void* dst1, const void* src1, size_t bytes1, void* dst2, const void* src2, size_t bytes2,
                  hipStream_t st);
 

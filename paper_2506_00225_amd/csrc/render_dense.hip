@@ -146,8 +146,7 @@ sgr_status launch_forward_dense(const Plan& P, const float* dense, const sgr_map
     std::vector<MapPtrs> mp(P.V);
     for (int v = 0; v < P.V; v++)
         mp[v] = MapPtrs{out[v].rgb, out[v].depth, out[v].sil, out[v].sem, out[v].t_final, out[v].n_contrib};
-    upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
-    d.t.maps = (const MapPtrs*)(ws + P.map_table);
+    set_view_table(d.t.maps, mp, ws + P.map_table, st);
     d.order = (const uint32_t*)(ws + P.order);
     d.n = P.n;
     d.dense = dense;

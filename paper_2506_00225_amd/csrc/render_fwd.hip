@@ -921,8 +921,7 @@ sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStrea
         mp[v] = MapPtrs{out[v].rgb, out[v].depth, out[v].sil, out[v].sem, out[v].t_final, out[v].n_contrib};
         want_sem |= out[v].sem != nullptr;
     }
-    upload_bytes(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, st);
-    a.maps = (const MapPtrs*)(ws + P.map_table);
+    set_view_table(a.maps, mp, ws + P.map_table, st);
     const int sem = sem_mode_for(P, want_sem);
     const int nb = (P.C + kRegBlock - 1) / kRegBlock;
     const int passes = sem == 1 ? lds_passes(P) : 1;
@@ -990,11 +989,18 @@ sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_los
         dense_sem |= lv[v].sem != nullptr || lv[v].g_sem != nullptr;
         sem_map |= mp[v].sem != nullptr;
     }
-    upload_pair(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, ws + P.loss_table, lp.data(),
-                sizeof(LossPtrs) * P.V, st);
-    a.maps = (const MapPtrs*)(ws + P.map_table);
     LossK lk;
-    lk.views = (const LossPtrs*)(ws + P.loss_table);
+    if (P.V == 1) {
+        set_view_table(a.maps, mp, nullptr, st);
+        set_view_table(lk.views, lp, nullptr, st);
+    } else {
+        upload_pair(ws + P.map_table, mp.data(), sizeof(MapPtrs) * P.V, ws + P.loss_table, lp.data(),
+                    sizeof(LossPtrs) * P.V, st);
+        a.maps.table = (const MapPtrs*)(ws + P.map_table);
+        a.maps.one = MapPtrs{};
+        lk.views.table = (const LossPtrs*)(ws + P.loss_table);
+        lk.views.one = LossPtrs{};
+    }
     lk.w_depth = lc->w_depth; lk.w_rgb = lc->w_rgb; lk.w_sil = lc->w_sil; lk.w_sem = lc->w_sem;
     lk.sil_thresh = lc->sil_thresh; lk.ce_floor = lc->ce_floor;
     lk.lambda_hd = lc->lambda_hd; lk.lambda_cos = lc->lambda_cos;
