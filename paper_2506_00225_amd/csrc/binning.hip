@@ -120,7 +120,9 @@ __device__ __forceinline__ uint32_t project_pair(const ProjectArgs& a, const Vie
         const double ixd = floor(mx), iyd = floor(my);
         const double a_ = syy / det;  // conic entries
         const double kInv2Ln2 = 0.72134752044448170368;  // 1 / (2 ln 2)
-        rec->r0 = make_float4(__int_as_float((int)ixd), __int_as_float((int)iyd), (float)(mx - ixd), (float)(my - iyd));
+        // the pixel-centre offset 0.5 - fraction, rounded once here rather than at every use
+        rec->r0 = make_float4(__int_as_float((int)ixd), __int_as_float((int)iyd), 0.5f - (float)(mx - ixd),
+                              0.5f - (float)(my - iyd));
         rec->r1 = make_float4((float)(a_ * kInv2Ln2), (float)(-sxy / syy), (float)(kInv2Ln2 / syy), (float)o);
         rec->r2 = make_float4(__uint_as_float((uint32_t)c0 | ((uint32_t)c1 << 16)),
                               __uint_as_float((uint32_t)r0 | ((uint32_t)r1 << 16)), zf, __int_as_float(v));

@@ -166,13 +166,13 @@ __device__ inline int view_of_tile(const ViewDev* views, int V, int gt) {
 }
 
 // alpha = min(alpha_max, o G) at the centre of pixel (px, py).  The offset
-// from the mean is formed from the record's integer and fractional parts
-// (exact up to one rounding), and log2 G = -(ca u^2 + cc dy^2) with
+// from the mean is formed from the record's integer part and its stored
+// 0.5 - fraction (exact up to one rounding), and log2 G = -(ca u^2 + cc dy^2) with
 // u = dx + cb dy has no cancellation.  dx, dy are pixel centre minus mean.
 __device__ __forceinline__ float eval_alpha(const float4& q0, const float4& q1, int px, int py, float amax,
                                             float* G, float* dx, float* dy) {
-    const float ddx = (float)(px - __float_as_int(q0.x)) + (0.5f - q0.z);
-    const float ddy = (float)(py - __float_as_int(q0.y)) + (0.5f - q0.w);
+    const float ddx = (float)(px - __float_as_int(q0.x)) + q0.z;
+    const float ddy = (float)(py - __float_as_int(q0.y)) + q0.w;
     const float u = fmaf(q1.y, ddy, ddx);
     const float e = fmaf(q1.x * u, u, q1.z * ddy * ddy);
     const float g = __builtin_amdgcn_exp2f(-e);  // v_exp_f32; e >= 0 here
@@ -193,9 +193,9 @@ __device__ __forceinline__ float eval_alpha(const float4& q0, const float4& q1, 
 // ellipse; a block near one of its corners often misses the ellipse.)
 __device__ __forceinline__ bool conic_meets_block(const float4& q0, const float4& q1, int bx0, int bx1, int by0,
                                                   int by1, float amin) {
-    const float x0 = (float)(bx0 - __float_as_int(q0.x)) + (0.5f - q0.z);
+    const float x0 = (float)(bx0 - __float_as_int(q0.x)) + q0.z;
     const float x1 = x0 + (float)(bx1 - bx0);
-    const float y0 = (float)(by0 - __float_as_int(q0.y)) + (0.5f - q0.w);
+    const float y0 = (float)(by0 - __float_as_int(q0.y)) + q0.w;
     const float y1 = y0 + (float)(by1 - by0);
     const float ca = q1.x, cb = q1.y, cc = q1.z;
     // along a row y: u = dx + cb y is smallest at dx = -cb y

@@ -54,8 +54,10 @@ struct alignas(16) ViewDev {
 };
 
 // Projected record of one (view, Gaussian) pair, 48 bytes.
-//   r0 = (ix, iy as int bits, fx, fy): pixel-space mean = (ix + fx, iy + fy),
-//        integer part exact, fraction in [0,1) to fp32 precision
+//   r0 = (ix, iy as int bits, hx, hy): pixel-space mean = (ix + fx, iy + fy),
+//        integer part exact, fraction f in [0,1) to fp32 precision, stored
+//        as h = 0.5 - f (fp32), so a pixel centre's offset from the mean is
+//        (px - ix) + hx
 //   r1 = (ca, cb, cc, o): exponent of the splat in base 2,
 //        log2 G = -(ca*u^2 + cc*dy^2), u = dx + cb*dy, with
 //        ca = a/(2 ln 2), cb = b/a, cc = (c - b^2/a)/(2 ln 2) for the conic

@@ -67,7 +67,8 @@ def gpu_proj(fr):
     rec[order[mask]] = srec[mask]
     ri = rec.view(np.int32)
     ru = rec.view(np.uint32)
-    mean2d = np.stack([ri[:, 0] + rec[:, 2].astype(np.float64), ri[:, 1] + rec[:, 3].astype(np.float64)], 1)
+    # the record holds 0.5 - fraction of the mean (fp32)
+    mean2d = np.stack([ri[:, 0] + (0.5 - rec[:, 2].astype(np.float64)), ri[:, 1] + (0.5 - rec[:, 3].astype(np.float64))], 1)
     ca = rec[:, 4].astype(np.float64) * 2 * LN2
     cb = rec[:, 5].astype(np.float64) * ca
     cc = rec[:, 6].astype(np.float64) * 2 * LN2 + rec[:, 5].astype(np.float64) * cb
