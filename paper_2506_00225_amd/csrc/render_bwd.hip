@@ -113,8 +113,10 @@ __device__ __forceinline__ int transposed_value_index(int lane) {
     return NP == 32 ? 16 * b1 + 8 * b2 + 4 * b3 + 2 * b4 + b5 : 8 * b2 + 4 * b3 + 2 * b4 + b5;
 }
 
-// Per-key value layout: 0,1 mean2d; 2,3,4 conic (a, b, c); 5 opacity;
-// 6,7,8 rgb; 9 depth; 10.. semantic values.
+// Per-key value layout (slots): 0,1 mean2d; 2,3,4 conic (a, b, c);
+// 5 opacity; 6,7,8 rgb; 9 depth; 10.. semantic values.  Per pixel the first
+// five are dQ dx, dQ dy, dQ dx^2, dQ dx dy, dQ dy^2 (dQ the gradient of the
+// exponent); the key's mean and conic gradients are formed from their sums.
 // SPARSE: no view has a dense dL/dsem; each pixel's semantic gradient is one
 // (class, value) pair (or none), held in registers instead of a 257-float
 // LDS column per class, which leaves room for more workgroups per CU.
@@ -362,14 +364,14 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
                 const bool free = act && q1.w * G < amax;
                 const float dQ = free ? dalpha * (-0.5f * alpha) : 0.f;
                 val[5] = free ? dalpha * G : 0.f;
-                const float ca = q1.x * k2ln2;
-                const float cb = q1.y * ca;
-                const float cc = q1.z * k2ln2 + q1.y * cb;
-                val[2] = dQ * dx * dx;
-                val[3] = dQ * 2.f * dx * dy;
-                val[4] = dQ * dy * dy;
-                val[0] = -2.f * dQ * (ca * dx + cb * dy);
-                val[1] = -2.f * dQ * (cb * dx + cc * dy);
+                // per pixel: dQ dx, dQ dy, dQ dx^2, dQ dx dy, dQ dy^2; the
+                // key's conic and mean gradients are formed from their sums
+                // (the conic is the same for all of the key's pixels)
+                val[0] = dQ * dx;
+                val[1] = dQ * dy;
+                val[2] = val[0] * dx;
+                val[3] = val[0] * dy;
+                val[4] = val[1] * dy;
                 val[6] = w * gC0;
                 val[7] = w * gC1;
                 val[8] = w * gC2;
@@ -437,6 +439,22 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
 #pragma unroll
                 for (int w = 0; w < kBwdWaves; w++)
                     if (fl[w]) sum += part[(w * kBwdBatch + j) * NV + q];
+                if (q < 2) {
+                    // mean: dL/dmu = -2 [[a, b], [b, c]] (sum dQ dx, sum dQ dy),
+                    // with the conic (a, b, c) of this key
+                    float other = 0.f;
+#pragma unroll
+                    for (int w = 0; w < kBwdWaves; w++)
+                        if (fl[w]) other += part[(w * kBwdBatch + j) * NV + (q ^ 1)];
+                    const float4 c1 = s_r1[j];
+                    const float ca = c1.x * k2ln2;
+                    const float cb = c1.y * ca;
+                    const float cc = c1.z * k2ln2 + c1.y * cb;
+                    const float sx = q == 0 ? sum : other, sy = q == 0 ? other : sum;
+                    sum = -2.f * (q == 0 ? fmaf(ca, sx, cb * sy) : fmaf(cb, sx, cc * sy));
+                } else if (q == 3) {
+                    sum *= 2.f;  // the conic's off-diagonal term carries 2 dx dy
+                }
                 b.slots[(size_t)e * NV + q] = sum;
             }
             if (q == 0) b.touched[e] = t ? 1 : 0;
