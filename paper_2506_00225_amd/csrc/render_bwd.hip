@@ -361,7 +361,8 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void re
                     R += e * w;
                 }
                 // alpha = min(alpha_max, o G): no gradient through the clamp
-                const bool free = act && q1.w * G < amax;
+                // (o G < alpha_max exactly when alpha < alpha_max)
+                const bool free = act && alpha < amax;
                 const float dQ = free ? dalpha * (-0.5f * alpha) : 0.f;
                 val[5] = free ? dalpha * G : 0.f;
                 // per pixel: dQ dx, dQ dy, dQ dx^2, dQ dx dy, dQ dy^2; the
