@@ -63,6 +63,14 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     float4* s_col = s_r2 + kFwdBatch;
     float* s_sv = (float*)(s_col + kFwdBatch);
     uint32_t* s_si = (uint32_t*)(s_sv + kFwdBatch * k);
+    // Label-only sums with k = 16 and C <= 128: each staged entry also
+    // carries its classes as a 128-bit mask, four (mask word, classes in
+    // lower words) pairs and a zero pair, and (distinct classes) its values
+    // in class order, so a pixel finds its label's value with one mask
+    // lookup and one read instead of 16 compares.
+    constexpr bool RANKED = SEM == 4 && KT == 16;
+    uint2* s_lm = (uint2*)(s_si + kFwdBatch * kw);  // [kFwdBatch][5]
+    const bool ranked = RANKED && C <= 128;
 
     const int v = view_of_tile(a.views, a.V, gt);
     const ViewDev& vw = a.views[v];
@@ -85,6 +93,10 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
         // prefetch loads issued after it
         asm volatile("" : "+v"(lab));
     }
+    // the label's mask word (4: the zero pair, for no label or one >= 128),
+    // its bit and the bits below it
+    const int lword = (lab >= 0 && lab < 128) ? (lab >> 5) : 4;
+    const uint32_t lbit = (uint32_t)lab & 31u, lbelow = (1u << lbit) - 1u;
     float* gacc = nullptr;  // SEM == 2: the thread's own row of the output map
     if (SEM == 2 && inside && a.maps[v].sem) {
         gacc = a.maps[v].sem + ((int64_t)py * vw.width + px) * C;
@@ -180,7 +192,42 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
             }
         } else if (SEM != 0) {
             const int j = tid - kFwdBatch;
-            if (j < nb) {
+            if (RANKED && ranked && j < nb) {
+                // class mask, classes in lower words, and the values in class
+                // order when the classes are distinct (list order otherwise)
+                uint32_t mk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int m = 0; m < 16; m++) {
+                    const uint32_t c = (stg[KM + (m >> 2)] >> (8 * (m & 3))) & 0xffu;
+                    const uint32_t bit = 1u << (c & 31u), wsel = c >> 5;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) mk[q] |= wsel == (uint32_t)q ? bit : 0u;
+                }
+                uint32_t below[4], nset = 0;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    below[q] = nset;
+                    nset += __builtin_popcount(mk[q]);
+                    s_lm[j * 5 + q] = make_uint2(mk[q], below[q]);
+                }
+                s_lm[j * 5 + 4] = make_uint2(0u, 0u);
+                const bool distinct = nset == 16u;
+#pragma unroll
+                for (int m = 0; m < 16; m++) {
+                    const uint32_t c = (stg[KM + (m >> 2)] >> (8 * (m & 3))) & 0xffu;
+                    const uint32_t wsel = c >> 5, lowbits = (1u << (c & 31u)) - 1u;
+                    uint32_t word = mk[0], pre = below[0];
+#pragma unroll
+                    for (int q = 1; q < 4; q++) {
+                        word = wsel == (uint32_t)q ? mk[q] : word;
+                        pre = wsel == (uint32_t)q ? below[q] : pre;
+                    }
+                    const uint32_t pos = distinct ? pre + __builtin_popcount(word & lowbits) : (uint32_t)m;
+                    s_sv[j * 16 + pos] = __uint_as_float(stg[m]);
+                }
+#pragma unroll
+                for (int m = 0; m < KWM; m++) s_si[j * kw + m] = stg[KM + m];
+            } else if (j < nb) {
 #pragma unroll
                 for (int m = 0; m < KM; m++)
                     if (m < k) s_sv[j * k + m] = __uint_as_float(stg[m]);
@@ -315,7 +362,15 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                     // list order (repeated classes add in turn)
                     const float* sv = s_sv + j * k;
                     const uint32_t* si = s_si + j * kw;
-                    if constexpr (KT > 0 && (KT & 15) == 0) {
+                    if (RANKED && ranked && (__float_as_uint(q2.w) >> 31) == 0u) {
+                        // distinct classes: the one update the list would make
+                        // (the others add exact zeros), with the label's value
+                        // found through the class mask
+                        const uint2 mw = s_lm[j * 5 + lword];
+                        const uint32_t pos = mw.y + __builtin_popcount(mw.x & lbelow);
+                        const float vl = s_sv[j * 16 + (pos & 15u)];
+                        ql = fmaf((mw.x >> lbit) & 1u ? vl : 0.f, w, ql);
+                    } else if constexpr (KT > 0 && (KT & 15) == 0) {
                         // whole rows first (16-byte loads), then selects
 #pragma unroll
                         for (int m0 = 0; m0 < KT; m0 += 16) {
@@ -832,6 +887,7 @@ size_t fwd_lds_bytes(int C, int k, int kpad, int sem_mode) {
     size_t b = (size_t)kFwdBatch * (4 * sizeof(float4) + k * sizeof(float) + (sem_mode == 1 ? std::max(kpad, 4 * k) : kpad));
     if (sem_mode == 1) b += (size_t)acc_floats(C) * sizeof(float);
     if (sem_mode == 3) b = std::max(b, (size_t)4 * 64 * 33 * sizeof(float));
+    if (sem_mode == 4 && k == 16) b += (size_t)kFwdBatch * 5 * sizeof(uint2);  // class masks
     return b;
 }
 
