@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
         run[tid] = has_bin ? hist[tid * nblk + blockIdx.x] : 0u;
     } else {
         uint32_t before = 0, all = 0;
-#pragma unroll 8
+#pragma unroll 32
         for (uint32_t b = 0; b < nblk; b++) {  // coalesced: the digits of block b are adjacent
             const uint32_t c = has_bin ? hist[b * bins + tid] : 0u;
             all += c;
