@@ -172,6 +172,38 @@ def test_sparse_semantic_gradient_equals_dense():
         assert torch.equal(ref[k], got[k]), k
 
 
+def test_label_only_lookup_with_repeated_classes():
+    """The label-only forward finds the label's value through a class mask
+    when an entry's classes are distinct and walks the list otherwise:
+    with 30 % of the top-k lists carrying a repeated class, loss, maps and
+    gradients still equal, bit for bit, those of the launch with all C class
+    sums."""
+    _say("label-only lookup, repeated classes")
+    sc = _scene(n=40_000, w=256, h=192, num_classes=102)
+    rng = np.random.default_rng(12)
+    dup = rng.random(sc.n) < 0.3
+    sc.sem_idx[dup, 3] = sc.sem_idx[dup, 0]
+    cam = sc.cameras[0]
+    tgs = [{kk: torch.from_numpy(v) for kk, v in _targets(rng, cam.width * cam.height, 102, "label", sc.k).items()}]
+    g = Gaussians.from_scene(sc)
+    fr = U.frame_for(sc)
+    fr.prepare(g)
+    keys = ("rgb", "depth", "sil", "t_final", "n_contrib")
+    m1 = {kk: v for kk, v in fr.alloc_maps().items() if kk in keys}
+    g1, l1 = fr.forward_loss(g, tgs, maps=m1, sparse_sem=True)
+    g1 = {kk: v.clone() for kk, v in g1.items()}
+    l1 = l1.clone()
+    m2 = fr.alloc_maps()
+    g2, l2 = fr.forward_loss(g, tgs, maps=m2, sparse_sem=True)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2)
+    for kk in g1:
+        assert torch.equal(g1[kk], g2[kk]), kk
+    for kk in m1:
+        assert torch.equal(m1[kk], m2[kk]), kk
+    assert fr.status()[0] == 0
+
+
 @pytest.mark.parametrize("C", [102, 256])
 def test_label_only_class_sums_equal_full_path(C):
     """With cross-entropy targets and no semantic map asked for, the fused
