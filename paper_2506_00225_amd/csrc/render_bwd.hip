@@ -6,10 +6,10 @@
 
 namespace sgr {
 
-// Keys per batch, each culled by one lane of a 64-lane ballot.  48 keeps the
-// LDS of the one-class semantic gradient at 28 KB, so five workgroups share
-// a CU (64 would take 37 KB and allow four).
-constexpr int kBwdBatch = 48;
+// Keys per batch, each culled by one lane of a 64-lane ballot.  44 keeps the
+// LDS of the one-class semantic gradient at 25.5 KB, so six workgroups share
+// a CU, as many as 80 VGPRs allow (48 would take 28 KB and allow five).
+constexpr int kBwdBatch = 44;
 static_assert(kBwdBatch <= 64, "the backward culls a batch with one 64-lane ballot");
 
 // Sum over the 64 lanes of a wave; the total lands in lane 63.  Row-wise
@@ -120,10 +120,10 @@ __device__ __forceinline__ int transposed_value_index(int lane) {
 // SPARSE: no view has a dense dL/dsem; each pixel's semantic gradient is one
 // (class, value) pair (or none), held in registers instead of a 257-float
 // LDS column per class, which leaves room for more workgroups per CU.
-// With k fixed at compile time the kernel is held to 96 VGPRs for five waves
-// per SIMD, matching the five workgroups the LDS allows.
+// With k fixed at compile time the one-class kernel is held to 80 VGPRs for
+// six waves per SIMD, matching the six workgroups its LDS allows.
 template <int KT, bool SPARSE>
-__global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? 5 : 1) void render_bwd_kernel(BwdArgs b) {
+__global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 5) : 1) void render_bwd_kernel(BwdArgs b) {
     extern __shared__ __align__(16) float smem[];
     const TileArgs& a = b.t;
     const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
