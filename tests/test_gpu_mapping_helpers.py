@@ -49,10 +49,17 @@ def test_mapping_loss_grad_matches_torch(P, C):
 def test_fused_adam_matches_torch_adam_with_clamps():
     print("[case] fused adam", flush=True)
     g = torch.Generator().manual_seed(0)
-    ps = [torch.randn(1000, 3, generator=g), torch.rand(777, generator=g), torch.rand(500, 16, generator=g)]
-    bounds = [(-float("inf"), float("inf")), (1e-4, 0.9999), (0.0, float("inf"))]
+    ps = [torch.randn(1000, 3, generator=g), torch.rand(777, generator=g), torch.rand(500, 16, generator=g),
+          torch.randn(1001, generator=g)]
+    bounds = [(-float("inf"), float("inf")), (1e-4, 0.9999), (0.0, float("inf")), (-1.0, 1.0)]
     ref = [p.clone() for p in ps]
-    dev = [p.cuda() for p in ps]
+    dev = [p.cuda() for p in ps[:3]]
+    # the last parameter starts 4 bytes into its allocation: the kernel's
+    # element-wise path (16-byte vectors need aligned arrays)
+    holder = torch.empty(1002, device="cuda")
+    holder[1:].copy_(ps[3])
+    dev.append(holder[1:])
+    assert dev[3].data_ptr() % 16 != 0
     grads = [torch.zeros_like(p) for p in dev]
     opt = FusedAdam([(p, gr, lo, hi) for p, gr, (lo, hi) in zip(dev, grads, bounds)], lr=1e-2)
     topt = torch.optim.Adam(ref, lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
