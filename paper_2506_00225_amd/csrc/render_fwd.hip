@@ -689,7 +689,8 @@ __global__ __launch_bounds__(kBlock) void render_fwd_kernel(TileArgs a, LossK lk
 
 // Label-only class sums keep no class sums in LDS, so registers bound the
 // workgroups per CU: the kernel is held to 80 VGPRs, six waves per SIMD
-// (the one value this costs is kept in scratch outside the loops).
+// (the few values this costs are kept in scratch, reloaded once per staged
+// batch, outside the compositing loop).
 template <int KT>
 __global__ __launch_bounds__(kBlock, 6) void render_fwd_label_kernel(TileArgs a, LossK lk) {
     render_fwd_body<KT, 4, 1, true, 1>(a, lk);
