@@ -341,9 +341,12 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
     if (e0 >= K || nv == 0) return;
     const uint64_t e1 = min(e0 + kKeyChunk, K);
     uint32_t w0 = a.heads[blockIdx.x];
+    // the pairs that own this chunk's keys end with the owner of the next
+    // chunk's first key (recorded when that chunk exists)
+    const uint32_t wend = e1 < K ? min(nv, a.heads[blockIdx.x + 1] + 1) : nv;
     while (true) {
         // window of pairs [w0, w0 + nw)
-        const uint32_t nw = min((uint32_t)W, nv - w0);
+        const uint32_t nw = min((uint32_t)W, wend - w0);
         for (uint32_t i = threadIdx.x; i < nw; i += 256) {
             const uint32_t g = w0 + i;
             off[i] = a.toff[g];
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
             a.owner[e] = w0 + lo;
         }
         // the same for every thread: taken as a scalar, so the loop exit is uniform
-        const int more = __builtin_amdgcn_readfirstlane((uint64_t)off[nw] < e1 && w0 + nw < nv ? 1 : 0);
+        const int more = __builtin_amdgcn_readfirstlane((uint64_t)off[nw] < e1 && w0 + nw < wend ? 1 : 0);
         __syncthreads();  // the window is read before it is replaced
         if (!more) break;
         w0 += nw;
