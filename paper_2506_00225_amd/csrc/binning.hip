@@ -312,19 +312,9 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
 
 // Keys are emitted in chunks of kKeyChunk consecutive keys, one chunk per
 // workgroup, so a pair near the camera that covers thousands of tiles is
-// spread over many workgroups.  chunk_heads records, for every chunk, the
-// visible pair that owns its first key (pair g owns keys
-// [toff[g], toff[g] + tcount[g])).
-__global__ __launch_bounds__(256) void chunk_heads(KeyArgs a) {
-    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t nv = a.counters[kNumVisible];
-    if (g >= nv) return;
-    const uint64_t s = a.toff[g], c = a.tcount[g];
-    const uint64_t lim = min((uint64_t)a.counters[kKeysLo], (uint64_t)a.cap);
-    if (c == 0 || s >= lim) return;
-    const uint64_t last = min(s + c, lim) - 1;
-    for (uint64_t q = (s + kKeyChunk - 1) / kKeyChunk; q * kKeyChunk <= last; q++) a.heads[q] = g;
-}
+// spread over many workgroups.  The scan of the pairs' key counts records,
+// for every chunk, the visible pair that owns its first key (pair g owns keys
+// [toff[g], toff[g] + tcount[g])) in heads.
 
 // Workgroup q emits keys [q C, q C + C) (C = kKeyChunk): the pairs that own
 // them, heads[q] onwards, go to LDS (offsets and tile rectangle), and each
@@ -470,18 +460,18 @@ sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t 
     uint32_t* partial = (uint32_t*)(ws + P.partial);
     uint32_t* tcount = (uint32_t*)(ws + P.tcount);
     uint32_t* toff = (uint32_t*)(ws + P.toff);
-    // per-pair key offsets; the total is the key count K
+    // per-pair key offsets; the total is the key count K.  The scan also
+    // records, for every chunk of kKeyChunk keys, the pair that owns its
+    // first key.
     scan_exclusive(tcount, toff, device_count(counters + kNumVisible, 0), (uint32_t)P.vn, partial,
-                   counters + kKeysLo, (uint32_t)P.cap, counters + kStatus, st);
+                   counters + kKeysLo, (uint32_t)P.cap, counters + kStatus, st, (uint32_t*)(ws + P.heads),
+                   (uint32_t)kKeyChunk);
     KeyArgs ka;
     ka.toff = toff; ka.tcount = tcount; ka.srec = (const Proj*)(ws + P.srec); ka.views = (const ViewDev*)(ws + P.views);
     ka.counters = counters; ka.cap = P.cap;
     ka.keys = (uint32_t*)(ws + P.keys0); ka.owner = (uint32_t*)(ws + P.owner);
     ka.heads = (uint32_t*)(ws + P.heads);
-    if (P.vn > 0) {
-        chunk_heads<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(ka);
-        emit_keys<<<(unsigned)div_up(P.cap, kKeyChunk), 256, 0, st>>>(ka);
-    }
+    if (P.vn > 0) emit_keys<<<(unsigned)div_up(P.cap, kKeyChunk), 256, 0, st>>>(ka);
     const int passes = radix_sort((uint32_t*)(ws + P.keys0), (uint32_t*)(ws + P.vals0), (uint32_t*)(ws + P.keys1),
                                   (uint32_t*)(ws + P.vals1), true, device_count(counters + kKeysLo, (uint32_t)P.cap),
                                   (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st);

@@ -35,8 +35,11 @@ inline CountSpec device_count(const uint32_t* d, uint32_t cap) { return CountSpe
 // Exclusive scan of in[0..n) into out (may alias in).  max_n bounds n and
 // sizes the grid; partial needs div_up(max_n, kScanTile) words.  The total
 // goes to *total_out (if set); total > cap sets SGR_ECAPACITY in *status.
+// With heads set, heads[q] receives the item whose run [out[i], out[i] +
+// in[i]) holds position q * chunk, for every such position below cap.
 void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
-                    uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st);
+                    uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st,
+                    uint32_t* heads = nullptr, uint32_t chunk = 0);
 
 // Block sums of (in[i] != 0) over in[0..n): partial[b] is the number of
 // non-zero items in block b (blocks of kScanTile).

@@ -60,11 +60,15 @@ __global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restric
 // Exclusive scan of `in` into `out` (may alias) from the block sums: each
 // workgroup adds up the sums of the blocks before it (integers, so the
 // order does not matter), which saves a separate scan of the sums.  The last
-// block writes the total (and the saturating capacity check).
+// block writes the total (and the saturating capacity check).  With `heads`
+// set, the scan is of per-item run lengths, and for every chunk of `chunk`
+// positions below `cap` the item whose run holds the chunk's first position
+// is recorded in heads[chunk index].
 __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec cs,
                                                   const uint32_t* __restrict__ partial, uint32_t* out,
                                                   uint32_t* __restrict__ total_out, uint32_t cap,
-                                                  uint32_t* __restrict__ status) {
+                                                  uint32_t* __restrict__ status, uint32_t* __restrict__ heads,
+                                                  uint32_t chunk) {
     __shared__ uint32_t wsum[4];
     const uint32_t n = count_of(cs);
     const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
@@ -89,7 +93,13 @@ __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec 
 #pragma unroll
     for (int r = 0; r < kScanItems; r++) {
         const uint32_t i = base + r;
-        if (i < n) out[i] = pre;
+        if (i < n) {
+            out[i] = pre;
+            if (heads && v[r] > 0u && pre < cap) {
+                const uint64_t last = min((uint64_t)pre + v[r], (uint64_t)cap) - 1;
+                for (uint64_t q = ((uint64_t)pre + chunk - 1) / chunk; q * chunk <= last; q++) heads[q] = i;
+            }
+        }
         pre += v[r];
     }
     if (blockIdx.x == nblk - 1 && threadIdx.x == 0) {
@@ -104,11 +114,12 @@ __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec 
 // items per block, which is all the block sums need.
 
 void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
-                    uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st) {
+                    uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st, uint32_t* heads,
+                    uint32_t chunk) {
     const uint32_t nblk_max = (uint32_t)div_up(max_n, kScanTile);
     if (nblk_max == 0) return;
     scan_block_sums<false><<<nblk_max, 256, 0, st>>>(in, cs, partial);
-    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out, total_out, cap, status);
+    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out, total_out, cap, status, heads, chunk);
 }
 
 // ------------------------------------------------------------------ radix
