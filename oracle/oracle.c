@@ -27,9 +27,17 @@
  * Gaussian's alpha is below the cutoff by construction), and "brute" mode
  * drops even that.
  *
+ * Where single and double precision may legitimately decide a threshold
+ * test differently (alpha near alpha_min, T (1 - alpha) near t_min), the
+ * pixel walk can take the other outcome of each such "flagged" decision
+ * (a per-pixel branch word), so a comparison can follow the outcome the
+ * single-precision path took and still check every value exactly.
+ *
  * Parity status: every function here is pinned by the CPU tests (closed
  * forms, textbook over-compositing, invariants, brute force, central finite
- * differences).  None is "parity unpinned".
+ * differences, the tight rectangle by numerical search, flipped decisions
+ * against closed forms and against the threshold moved across them).  None
+ * is "parity unpinned".
  */
 #include <math.h>
 #include <stdint.h>
@@ -67,8 +75,8 @@ static void quat_to_rot(const double *q, double *R, double *qn_out, double *norm
  * Projection of every Gaussian into one camera (Sec. 3.1: transform to
  * camera space, project to the image plane).  EWA: Sigma2 = J W Sigma3 W^T
  * J^T + lowpass*I with Sigma3 = Rq diag(s^2) Rq^T.  Culling: z <= z_near,
- * det(Sigma2) <= 0, opacity below the alpha cutoff, or an empty pixel
- * rectangle.  The rectangle is the exact axis-aligned box of the set where
+ * det(Sigma2) <= 0, opacity below the alpha cutoff, an empty pixel
+ * rectangle, or a projected mean beyond 2^30 px.  The rectangle is the exact axis-aligned box of the set where
  * o*exp(-Q/2) >= alpha_min, i.e. Q <= 2 ln(o/alpha_min), with pixel centres
  * at (col+0.5, row+0.5).
  */
@@ -144,6 +152,11 @@ int oracle_project(int64_t n, const double *means, const double *scales, const d
         if (rlo < 0) rlo = 0;
         if (rhi > height - 1) rhi = height - 1;
         if (!(clo <= chi) || !(rlo <= rhi)) continue;
+        /* Reading: a projected mean farther than 2^30 px from the image
+         * origin (on either axis) is culled.  Such a point lies outside what
+         * a pixel-space record can hold; it reaches the image only through
+         * a footprint of the same astronomical size. */
+        if (!(fabs(mx) < 1073741824.0) || !(fabs(my) < 1073741824.0)) continue;
         rect[4 * i + 0] = (int32_t)clo; rect[4 * i + 1] = (int32_t)chi;
         rect[4 * i + 2] = (int32_t)rlo; rect[4 * i + 3] = (int32_t)rhi;
         visible[i] = 1;
@@ -198,25 +211,44 @@ static void build_rowlists(int64_t nv, const int64_t *ord, const int32_t *rect, 
     free(fill);
 }
 
-static void row_range(const rowlists *rl, int64_t nv, int y, int brute, int64_t *b, int64_t *e) {
-    if (brute) { *b = 0; *e = nv; }
-    else { *b = rl->start[y]; *e = rl->start[y + 1]; }
+/* The projected scene of one view as the compositing reads it. */
+typedef struct {
+    const double *mean2d, *conic, *depth, *opacity;
+    const int32_t *rect;
+    int32_t width, height, brute;
+    double amin, amax, tmin, ma, mt;
+    int64_t nv;
+    int64_t *ord;
+    rowlists rl;
+} view_scene;
+
+static void scene_open(view_scene *s, int64_t n, const double *mean2d, const double *conic, const double *depth,
+                       const double *opacity, const int32_t *rect, const uint32_t *zbits, const int32_t *visible,
+                       int32_t width, int32_t height, const double *cfg, int32_t brute) {
+    s->mean2d = mean2d; s->conic = conic; s->depth = depth; s->opacity = opacity; s->rect = rect;
+    s->width = width; s->height = height; s->brute = brute;
+    s->amin = cfg[CF_AMIN]; s->amax = cfg[CF_AMAX]; s->tmin = cfg[CF_TMIN];
+    s->ma = cfg[CF_MA]; s->mt = cfg[CF_MT];
+    s->nv = depth_order(n, zbits, visible, &s->ord);
+    build_rowlists(s->nv, s->ord, rect, height, brute, &s->rl);
+}
+
+static void scene_close(view_scene *s) {
+    free(s->ord);
+    free(s->rl.ids);
+    free(s->rl.start);
 }
 
 /* One blend step's record, kept for the reverse walk. */
 typedef struct { int64_t id; double alpha, G, T; int clamped; double dx, dy; } blendrec;
+typedef struct { blendrec *r; int64_t cap; } blendbuf;
 
-/* Evaluates f_i at pixel centre (px,py): returns alpha (clamped), G, dx, dy. */
-static double eval_alpha(const double *mean2d, const double *conic, const double *opacity, double amax,
-                         int64_t i, double px, double py, double *G, double *dx, double *dy, int *clamped) {
-    const double ddx = px - mean2d[2 * i], ddy = py - mean2d[2 * i + 1];
-    const double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
-    const double Q = a * ddx * ddx + 2.0 * b * ddx * ddy + c * ddy * ddy;
-    const double g = exp(-0.5 * Q);
-    const double og = opacity[i] * g;
-    *G = g; *dx = ddx; *dy = ddy;
-    *clamped = og >= amax;
-    return og < amax ? og : amax;
+static void buf_push(blendbuf *b, int64_t nb, const blendrec *x) {
+    if (nb == b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 64;
+        b->r = (blendrec *)realloc(b->r, sizeof(blendrec) * b->cap);
+    }
+    b->r[nb] = *x;
 }
 
 static uint64_t mix64(uint64_t h, uint64_t v) {
@@ -224,80 +256,178 @@ static uint64_t mix64(uint64_t h, uint64_t v) {
     return h;
 }
 
+/* What a pixel's walk reports besides its blends. */
+typedef struct {
+    double T;        /* final transmittance */
+    int flags;       /* bit 0: an alpha near alpha_min; bit 1: a T(1 - alpha) near t_min */
+    int nflagged;    /* decisions met within the margins, in walk order */
+    uint64_t sig;    /* hash of every candidate's decision (finite differences) */
+} walk_info;
+
 /*
- * Eq. 1 and Eq. 3, one pixel at a time.  For each candidate in front-to-back
- * order: alpha = min(alpha_max, o G); skip when alpha < alpha_min; stop
- * (without blending) when T (1 - alpha) < t_min; otherwise add z*alpha*T to
- * every channel and multiply T by (1 - alpha).  Also reports, per pixel, a
- * flag word (bit 0: an alpha within margin_alpha (relative) of alpha_min;
- * bit 1: a T(1-alpha) within margin_t (relative) of t_min) and a signature
- * hashing every candidate's decision (for finite differences).
+ * The front-to-back walk of Eq. 1 at the centre of pixel (x, y): for each
+ * candidate in (depth, id) order, alpha = min(alpha_max, o G) with
+ * G = exp(-Q/2), Q = d^T A d; skip it when alpha < alpha_min; stop, without
+ * blending it, when T (1 - alpha) < t_min; otherwise record the blend (its
+ * alpha, G and the transmittance T in front of it) and multiply T by
+ * (1 - alpha).
+ *
+ * A decision is "flagged" when alpha lies within the relative margin
+ * margin_alpha of alpha_min, or T (1 - alpha) within margin_t of t_min:
+ * there single and double precision may legitimately decide differently.
+ * Bit j of `branch` takes the other outcome of the j-th flagged decision met
+ * on the walk (j < 32); branch = 0 is the plain definition.
+ */
+static int64_t walk_pixel(const view_scene *s, int x, int y, uint32_t branch, blendbuf *buf, walk_info *info) {
+    const double px = x + 0.5, py = y + 0.5;
+    int64_t lb, le;
+    if (s->brute) { lb = 0; le = s->nv; }
+    else { lb = s->rl.start[y]; le = s->rl.start[y + 1]; }
+    double T = 1.0;
+    int64_t nb = 0;
+    int flags = 0, nfl = 0;
+    uint64_t sig = 0;
+    for (int64_t a = lb; a < le; a++) {
+        const int64_t i = s->rl.ids[a];
+        if (!s->brute) {
+            const int32_t *r = s->rect + 4 * i;
+            if (x < r[0] || x > r[1]) continue;
+        }
+        const double dx = px - s->mean2d[2 * i], dy = py - s->mean2d[2 * i + 1];
+        const double A = s->conic[3 * i], B = s->conic[3 * i + 1], Cc = s->conic[3 * i + 2];
+        const double Q = A * dx * dx + 2.0 * B * dx * dy + Cc * dy * dy;
+        const double G = exp(-0.5 * Q);
+        const double og = s->opacity[i] * G;
+        const int clamped = og >= s->amax;
+        const double alpha = clamped ? s->amax : og;
+        int skip = alpha < s->amin;
+        if (fabs(alpha / s->amin - 1.0) < s->ma) {
+            flags |= 1;
+            if (nfl < 32 && (branch >> nfl) & 1u) skip = !skip;
+            nfl++;
+        }
+        if (skip) {
+            sig = mix64(sig, (uint64_t)i * 4 + 0);
+            continue;
+        }
+        const double Tn = T * (1.0 - alpha);
+        int stop = Tn < s->tmin;
+        if (fabs(Tn / s->tmin - 1.0) < s->mt) {
+            flags |= 2;
+            if (nfl < 32 && (branch >> nfl) & 1u) stop = !stop;
+            nfl++;
+        }
+        if (stop) {
+            sig = mix64(sig, (uint64_t)i * 4 + 3);
+            break;
+        }
+        blendrec rec = {i, alpha, G, T, clamped, dx, dy};
+        buf_push(buf, nb, &rec);
+        nb++;
+        T = Tn;
+        sig = mix64(sig, (uint64_t)i * 4 + (clamped ? 2 : 1));
+    }
+    info->T = T;
+    info->flags = flags;
+    info->nflagged = nfl;
+    info->sig = sig;
+    return nb;
+}
+
+/* Eq. 1 and Eq. 3 over one pixel's blends: C = sum c_i w_i, D = sum z_i w_i,
+ * S = sum w_i and P[idx_ij] += v_ij w_i, with w_i = alpha_i T_i. */
+static void accumulate_pixel(const blendbuf *buf, int64_t nb, const double *depth, const double *rgb,
+                             const double *sem_val, const int32_t *sem_idx, int32_t k, int32_t C,
+                             double *out_c, double *out_d, double *out_s, double *out_p) {
+    double Cc[3] = {0, 0, 0}, Dd = 0, Ss = 0;
+    for (int m = 0; m < C; m++) out_p[m] = 0;
+    for (int64_t b = 0; b < nb; b++) {
+        const int64_t i = buf->r[b].id;
+        const double w = buf->r[b].alpha * buf->r[b].T;
+        for (int c = 0; c < 3; c++) Cc[c] += rgb[3 * i + c] * w;
+        Dd += depth[i] * w;
+        Ss += w;
+        for (int j = 0; j < k; j++) out_p[sem_idx[(int64_t)i * k + j]] += sem_val[(int64_t)i * k + j] * w;
+    }
+    for (int c = 0; c < 3; c++) out_c[c] = Cc[c];
+    *out_d = Dd;
+    *out_s = Ss;
+}
+
+/*
+ * Eq. 1 and Eq. 3, one pixel at a time (walk_pixel, then accumulate_pixel).
+ * `branch` (may be NULL: all zero) picks, per pixel, the outcomes of its
+ * flagged decisions.  Also reports, per pixel, the flag word and the
+ * decision signature of walk_pixel.
  */
 int oracle_render(int64_t n, const double *mean2d, const double *conic, const double *depth,
                   const double *opacity, const double *rgb, const double *sem_val, const int32_t *sem_idx,
                   int32_t k, int32_t C, const int32_t *rect, const uint32_t *zbits, const int32_t *visible,
-                  int32_t width, int32_t height, const double *cfg, int32_t brute,
+                  int32_t width, int32_t height, const double *cfg, int32_t brute, const uint32_t *branch,
                   double *out_rgb, double *out_depth, double *out_sil, double *out_sem, double *out_tfinal,
                   int32_t *out_ncontrib, int32_t *out_flags, uint64_t *out_sig) {
-    const double amin = cfg[CF_AMIN], amax = cfg[CF_AMAX], tmin = cfg[CF_TMIN];
-    const double ma = cfg[CF_MA], mt = cfg[CF_MT];
-    int64_t *ord;
-    const int64_t nv = depth_order(n, zbits, visible, &ord);
-    rowlists rl;
-    build_rowlists(nv, ord, rect, height, brute, &rl);
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int y = 0; y < height; y++) {
-        int64_t lb, le;
-        row_range(&rl, nv, y, brute, &lb, &le);
-        for (int x = 0; x < width; x++) {
-            const int64_t pix = (int64_t)y * width + x;
-            const double px = x + 0.5, py = y + 0.5;
-            double T = 1.0, Cc[3] = {0, 0, 0}, Dd = 0, Ss = 0;
-            double *P = out_sem + pix * C;
-            for (int m = 0; m < C; m++) P[m] = 0;
-            int32_t ncon = 0, flags = 0;
-            uint64_t sig = 0;
-            for (int64_t a = lb; a < le; a++) {
-                const int64_t i = rl.ids[a];
-                if (!brute) {
-                    const int32_t *r = rect + 4 * i;
-                    if (x < r[0] || x > r[1]) continue;
-                }
-                double G, dx, dy;
-                int cl;
-                const double alpha = eval_alpha(mean2d, conic, opacity, amax, i, px, py, &G, &dx, &dy, &cl);
-                if (fabs(alpha / amin - 1.0) < ma) flags |= 1;
-                if (alpha < amin) {
-                    sig = mix64(sig, (uint64_t)i * 4 + 0);
-                    continue;
-                }
-                const double Tn = T * (1.0 - alpha);
-                if (fabs(Tn / tmin - 1.0) < mt) flags |= 2;
-                if (Tn < tmin) {
-                    sig = mix64(sig, (uint64_t)i * 4 + 3);
-                    break;
-                }
-                const double w = alpha * T;
-                for (int c = 0; c < 3; c++) Cc[c] += rgb[3 * i + c] * w;
-                Dd += depth[i] * w;
-                Ss += w;
-                for (int j = 0; j < k; j++) P[sem_idx[(int64_t)i * k + j]] += sem_val[(int64_t)i * k + j] * w;
-                T = Tn;
-                ncon++;
-                sig = mix64(sig, (uint64_t)i * 4 + (cl ? 2 : 1));
+    view_scene s;
+    scene_open(&s, n, mean2d, conic, depth, opacity, rect, zbits, visible, width, height, cfg, brute);
+#pragma omp parallel
+    {
+        blendbuf buf = {NULL, 0};
+#pragma omp for schedule(dynamic, 1)
+        for (int y = 0; y < height; y++) {
+            for (int x = 0; x < width; x++) {
+                const int64_t pix = (int64_t)y * width + x;
+                walk_info info;
+                const int64_t nb = walk_pixel(&s, x, y, branch ? branch[pix] : 0u, &buf, &info);
+                accumulate_pixel(&buf, nb, depth, rgb, sem_val, sem_idx, k, C, out_rgb + 3 * pix, out_depth + pix,
+                                 out_sil + pix, out_sem + pix * C);
+                out_tfinal[pix] = info.T;
+                out_ncontrib[pix] = (int32_t)nb;
+                if (out_flags) out_flags[pix] = info.flags;
+                if (out_sig) out_sig[pix] = info.sig;
             }
-            for (int c = 0; c < 3; c++) out_rgb[3 * pix + c] = Cc[c];
-            out_depth[pix] = Dd;
-            out_sil[pix] = Ss;
-            out_tfinal[pix] = T;
-            out_ncontrib[pix] = ncon;
-            if (out_flags) out_flags[pix] = flags;
-            if (out_sig) out_sig[pix] = sig;
         }
+        free(buf.r);
     }
-    free(ord);
-    free(rl.ids);
-    free(rl.start);
+    scene_close(&s);
+    return 0;
+}
+
+/*
+ * Every outcome of the flagged decisions of the listed pixels (pix[2 q] = x,
+ * pix[2 q + 1] = y): for branch word b in [0, 2^nbits), the maps of pixel q
+ * under walk_pixel(.., b, ..), stored at row q * 2^nbits + b of the outputs.
+ * out_nflag gives, per row, the flagged decisions that walk met: a walk
+ * that met more than nbits of them has outcomes this enumeration leaves out.
+ */
+int oracle_render_branches(int64_t n, const double *mean2d, const double *conic, const double *depth,
+                           const double *opacity, const double *rgb, const double *sem_val, const int32_t *sem_idx,
+                           int32_t k, int32_t C, const int32_t *rect, const uint32_t *zbits, const int32_t *visible,
+                           int32_t width, int32_t height, const double *cfg, int64_t npix, const int32_t *pix,
+                           int32_t nbits, double *out_rgb, double *out_depth, double *out_sil, double *out_sem,
+                           double *out_tfinal, int32_t *out_ncontrib, int32_t *out_nflag) {
+    if (nbits < 0 || nbits > 16) return 1;
+    const int64_t nb_rows = (int64_t)1 << nbits;
+    view_scene s;
+    scene_open(&s, n, mean2d, conic, depth, opacity, rect, zbits, visible, width, height, cfg, 0);
+#pragma omp parallel
+    {
+        blendbuf buf = {NULL, 0};
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < npix; q++) {
+            const int x = pix[2 * q], y = pix[2 * q + 1];
+            for (int64_t b = 0; b < nb_rows; b++) {
+                const int64_t row = q * nb_rows + b;
+                walk_info info;
+                const int64_t nb = walk_pixel(&s, x, y, (uint32_t)b, &buf, &info);
+                accumulate_pixel(&buf, nb, depth, rgb, sem_val, sem_idx, k, C, out_rgb + 3 * row, out_depth + row,
+                                 out_sil + row, out_sem + row * C);
+                out_tfinal[row] = info.T;
+                out_ncontrib[row] = (int32_t)nb;
+                out_nflag[row] = info.nflagged;
+            }
+        }
+        free(buf.r);
+    }
+    scene_close(&s);
     return 0;
 }
 
@@ -305,7 +435,8 @@ int oracle_render(int64_t n, const double *mean2d, const double *conic, const do
  * Analytic gradient of  L = sum_p <g(p), maps(p)>  with respect to each
  * Gaussian's 2D parameters: mean2d (2), conic (a, b, c with Q = a dx^2 +
  * 2 b dx dy + c dy^2), opacity, rgb (3), depth value z, and the k semantic
- * values.  Reverse walk per pixel:
+ * values.  Reverse walk over each pixel's blends (walk_pixel, with the
+ * pixel's `branch` word, may be NULL):
  *   w_i = alpha_i T_i;  dL/dz_i^ch = w_i g_ch;
  *   dL/dalpha_i = T_i e_i - R_i / (1 - alpha_i),  e_i = sum_ch z_i^ch g_ch,
  *   R_i = sum_{l>i} e_l w_l;
@@ -317,16 +448,13 @@ int oracle_render_backward(int64_t n, const double *mean2d, const double *conic,
                            const double *opacity, const double *rgb, const double *sem_val,
                            const int32_t *sem_idx, int32_t k, int32_t C, const int32_t *rect,
                            const uint32_t *zbits, const int32_t *visible, int32_t width, int32_t height,
-                           const double *cfg, const double *g_rgb, const double *g_depth,
+                           const double *cfg, const uint32_t *branch, const double *g_rgb, const double *g_depth,
                            const double *g_sil, const double *g_sem,
                            double *d_mean2d, double *d_conic, double *d_opacity, double *d_rgb,
                            double *d_depth, double *d_sem) {
-    const double amin = cfg[CF_AMIN], amax = cfg[CF_AMAX], tmin = cfg[CF_TMIN];
     const int semgeo = cfg[CF_SEMGEO] != 0;
-    int64_t *ord;
-    const int64_t nv = depth_order(n, zbits, visible, &ord);
-    rowlists rl;
-    build_rowlists(nv, ord, rect, height, 0, &rl);
+    view_scene s;
+    scene_open(&s, n, mean2d, conic, depth, opacity, rect, zbits, visible, width, height, cfg, 0);
     int nthreads = 1;
 #ifdef _OPENMP
     nthreads = omp_get_max_threads();
@@ -340,39 +468,21 @@ int oracle_render_backward(int64_t n, const double *mean2d, const double *conic,
         tid = omp_get_thread_num();
 #endif
         double *my = acc + (int64_t)tid * n * stride;
-        int64_t cap = 64;
-        blendrec *rec = (blendrec *)malloc(sizeof(blendrec) * cap);
+        blendbuf buf = {NULL, 0};
 #pragma omp for schedule(static)
         for (int y = 0; y < height; y++) {
-            const int64_t lb = rl.start[y], le = rl.start[y + 1];
             for (int x = 0; x < width; x++) {
                 const int64_t pix = (int64_t)y * width + x;
-                const double px = x + 0.5, py = y + 0.5;
-                double T = 1.0;
-                int64_t nb = 0;
-                for (int64_t a = lb; a < le; a++) {
-                    const int64_t i = rl.ids[a];
-                    const int32_t *r = rect + 4 * i;
-                    if (x < r[0] || x > r[1]) continue;
-                    double G, dx, dy;
-                    int cl;
-                    const double alpha = eval_alpha(mean2d, conic, opacity, amax, i, px, py, &G, &dx, &dy, &cl);
-                    if (alpha < amin) continue;
-                    const double Tn = T * (1.0 - alpha);
-                    if (Tn < tmin) break;
-                    if (nb == cap) { cap *= 2; rec = (blendrec *)realloc(rec, sizeof(blendrec) * cap); }
-                    rec[nb].id = i; rec[nb].alpha = alpha; rec[nb].G = G; rec[nb].T = T;
-                    rec[nb].clamped = cl; rec[nb].dx = dx; rec[nb].dy = dy;
-                    nb++;
-                    T = Tn;
-                }
+                walk_info info;
+                const int64_t nb = walk_pixel(&s, x, y, branch ? branch[pix] : 0u, &buf, &info);
                 const double *gC = g_rgb + 3 * pix;
                 const double gD = g_depth[pix], gS = g_sil[pix];
                 const double *gP = g_sem + pix * C;
                 double R = 0.0;
                 for (int64_t b = nb - 1; b >= 0; b--) {
-                    const int64_t i = rec[b].id;
-                    const double alpha = rec[b].alpha, Ti = rec[b].T, w = alpha * Ti;
+                    const blendrec *rb = buf.r + b;
+                    const int64_t i = rb->id;
+                    const double alpha = rb->alpha, Ti = rb->T, w = alpha * Ti;
                     double *gi = my + i * stride;
                     double e = gD * depth[i] + gS;
                     for (int c = 0; c < 3; c++) {
@@ -389,10 +499,10 @@ int oracle_render_backward(int64_t n, const double *mean2d, const double *conic,
                     if (semgeo) e += es;
                     const double dalpha = Ti * e - R / (1.0 - alpha);
                     R += e * w;
-                    if (rec[b].clamped) continue;
-                    gi[5] += dalpha * rec[b].G;
+                    if (rb->clamped) continue;
+                    gi[5] += dalpha * rb->G;
                     const double dQ = dalpha * (-0.5 * alpha);
-                    const double dx = rec[b].dx, dy = rec[b].dy;
+                    const double dx = rb->dx, dy = rb->dy;
                     const double ca = conic[3 * i], cb = conic[3 * i + 1], cc = conic[3 * i + 2];
                     gi[2] += dQ * dx * dx;
                     gi[3] += dQ * 2.0 * dx * dy;
@@ -402,26 +512,24 @@ int oracle_render_backward(int64_t n, const double *mean2d, const double *conic,
                 }
             }
         }
-        free(rec);
+        free(buf.r);
     }
     for (int64_t i = 0; i < n; i++) {
-        double s[64];
-        for (int64_t v = 0; v < stride; v++) s[v] = 0;
+        double sm[64];
+        for (int64_t v = 0; v < stride; v++) sm[v] = 0;
         for (int th = 0; th < nthreads; th++) {
             const double *src = acc + ((int64_t)th * n + i) * stride;
-            for (int64_t v = 0; v < stride; v++) s[v] += src[v];
+            for (int64_t v = 0; v < stride; v++) sm[v] += src[v];
         }
-        d_mean2d[2 * i] = s[0]; d_mean2d[2 * i + 1] = s[1];
-        d_conic[3 * i] = s[2]; d_conic[3 * i + 1] = s[3]; d_conic[3 * i + 2] = s[4];
-        d_opacity[i] = s[5];
-        d_rgb[3 * i] = s[6]; d_rgb[3 * i + 1] = s[7]; d_rgb[3 * i + 2] = s[8];
-        d_depth[i] = s[9];
-        for (int j = 0; j < k; j++) d_sem[i * k + j] = s[10 + j];
+        d_mean2d[2 * i] = sm[0]; d_mean2d[2 * i + 1] = sm[1];
+        d_conic[3 * i] = sm[2]; d_conic[3 * i + 1] = sm[3]; d_conic[3 * i + 2] = sm[4];
+        d_opacity[i] = sm[5];
+        d_rgb[3 * i] = sm[6]; d_rgb[3 * i + 1] = sm[7]; d_rgb[3 * i + 2] = sm[8];
+        d_depth[i] = sm[9];
+        for (int j = 0; j < k; j++) d_sem[i * k + j] = sm[10 + j];
     }
     free(acc);
-    free(ord);
-    free(rl.ids);
-    free(rl.start);
+    scene_close(&s);
     return 0;
 }
 

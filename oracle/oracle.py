@@ -49,8 +49,10 @@ def lib():
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int32
         L.oracle_project.argtypes = [i64] + [P] * 6 + [P] * 7
-        L.oracle_render.argtypes = [i64] + [P] * 7 + [i32, i32] + [P] * 3 + [i32, i32, P, i32] + [P] * 8
-        L.oracle_render_backward.argtypes = ([i64] + [P] * 7 + [i32, i32] + [P] * 3 + [i32, i32, P]
+        L.oracle_render.argtypes = [i64] + [P] * 7 + [i32, i32] + [P] * 3 + [i32, i32, P, i32, P] + [P] * 8
+        L.oracle_render_branches.argtypes = ([i64] + [P] * 7 + [i32, i32] + [P] * 3 + [i32, i32, P, i64, P, i32]
+                                             + [P] * 7)
+        L.oracle_render_backward.argtypes = ([i64] + [P] * 7 + [i32, i32] + [P] * 3 + [i32, i32, P, P]
                                              + [P] * 4 + [P] * 6)
         L.oracle_project_backward.argtypes = [i64] + [P] * 5 + [P] * 4 + [P] * 3
         L.oracle_score.argtypes = [i32, i32, i32, P, P, P, P, P]
@@ -137,8 +139,17 @@ def reference_keys(projs, cams, tile_w=16, tile_h=16):
     return keys, ranges, np.asarray(tile_off, np.int64)
 
 
-def render(proj, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, brute=False) -> dict:
-    """Per-pixel compositing of Eq. 1 / Eq. 3 (oracle.c oracle_render)."""
+def _branch_arg(branch, H, W):
+    if branch is None:
+        return None
+    b = np.ascontiguousarray(branch, dtype=np.uint32).reshape(H, W)
+    return b
+
+
+def render(proj, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, brute=False, branch=None) -> dict:
+    """Per-pixel compositing of Eq. 1 / Eq. 3 (oracle.c oracle_render).
+    branch: optional [H, W] words choosing the outcomes of each pixel's
+    flagged decisions (walk_pixel in oracle.c); None is the plain definition."""
     n = proj["mean2d"].shape[0]
     k = int(sem_val.shape[1])
     W, H, C = cam.width, cam.height, int(num_classes)
@@ -149,16 +160,46 @@ def render(proj, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, brute=Fa
         "sem": np.zeros((H, W, C)), "t_final": np.zeros((H, W)), "n_contrib": np.zeros((H, W), np.int32),
         "flags": np.zeros((H, W), np.int32), "sig": np.zeros((H, W), np.uint64),
     }
+    br = _branch_arg(branch, H, W)
     lib().oracle_render(n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["depth"]), _p(opacity), _p(rgb),
                         _p(sem_val), _p(sem_idx), k, C, _p(proj["rect"]), _p(proj["zbits"]), _p(proj["visible"]),
-                        W, H, _p(cfg), int(bool(brute)), _p(out["rgb"]), _p(out["depth"]), _p(out["sil"]),
+                        W, H, _p(cfg), int(bool(brute)), _p(br), _p(out["rgb"]), _p(out["depth"]), _p(out["sil"]),
                         _p(out["sem"]), _p(out["t_final"]), _p(out["n_contrib"]), _p(out["flags"]), _p(out["sig"]))
     return out
 
 
-def render_backward(proj, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, grads) -> dict:
+def render_branches(proj, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, pixels, nbits=4) -> dict:
+    """Every outcome of the flagged decisions of the listed pixels
+    (oracle.c oracle_render_branches).  pixels: [q, 2] (x, y).  Returns maps
+    of shape [q, 2^nbits, ...] indexed by branch word, and "nflag" [q, 2^nbits],
+    the flagged decisions each walk met (a walk that met more than nbits of
+    them has outcomes left out)."""
+    n = proj["mean2d"].shape[0]
+    k = int(sem_val.shape[1])
+    W, H, C = cam.width, cam.height, int(num_classes)
+    opacity, rgb, sem_val = _f64(opacity), _f64(rgb), _f64(sem_val)
+    sem_idx = np.ascontiguousarray(sem_idx, dtype=np.int32)
+    pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int32).reshape(-1, 2))
+    q, nb = pix.shape[0], 1 << int(nbits)
+    out = {"rgb": np.zeros((q, nb, 3)), "depth": np.zeros((q, nb)), "sil": np.zeros((q, nb)),
+           "sem": np.zeros((q, nb, C)), "t_final": np.zeros((q, nb)), "n_contrib": np.zeros((q, nb), np.int32),
+           "nflag": np.zeros((q, nb), np.int32)}
+    if q == 0:
+        return out
+    rc = lib().oracle_render_branches(n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["depth"]), _p(opacity),
+                                      _p(rgb), _p(sem_val), _p(sem_idx), k, C, _p(proj["rect"]), _p(proj["zbits"]),
+                                      _p(proj["visible"]), W, H, _p(cfg), q, _p(pix), int(nbits), _p(out["rgb"]),
+                                      _p(out["depth"]), _p(out["sil"]), _p(out["sem"]), _p(out["t_final"]),
+                                      _p(out["n_contrib"]), _p(out["nflag"]))
+    if rc != 0:
+        raise ValueError("nbits must lie in [0, 16]")
+    return out
+
+
+def render_backward(proj, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, grads, branch=None) -> dict:
     """Analytic gradient with respect to the 2D parameters
-    (oracle.c oracle_render_backward); `grads` holds dL/d{rgb,depth,sil,sem}."""
+    (oracle.c oracle_render_backward); `grads` holds dL/d{rgb,depth,sil,sem};
+    `branch` as in render()."""
     n = proj["mean2d"].shape[0]
     k = int(sem_val.shape[1])
     W, H, C = cam.width, cam.height, int(num_classes)
@@ -169,7 +210,8 @@ def render_backward(proj, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg,
            "rgb": np.zeros((n, 3)), "depth": np.zeros(n), "sem_val": np.zeros((n, k))}
     lib().oracle_render_backward(n, _p(proj["mean2d"]), _p(proj["conic"]), _p(proj["depth"]), _p(opacity),
                                  _p(rgb), _p(sem_val), _p(sem_idx), k, C, _p(proj["rect"]), _p(proj["zbits"]),
-                                 _p(proj["visible"]), W, H, _p(cfg), _p(g["rgb"]), _p(g["depth"]), _p(g["sil"]),
+                                 _p(proj["visible"]), W, H, _p(cfg), _p(_branch_arg(branch, H, W)), _p(g["rgb"]),
+                                 _p(g["depth"]), _p(g["sil"]),
                                  _p(g["sem"]), _p(out["mean2d"]), _p(out["conic"]), _p(out["opacity"]),
                                  _p(out["rgb"]), _p(out["depth"]), _p(out["sem_val"]))
     return out
@@ -201,21 +243,22 @@ def score(maps, num_classes) -> dict:
 
 # ---------------------------------------------------------------- helpers
 
-def forward(scene_arrays, cam, cfg, num_classes, brute=False):
+def forward(scene_arrays, cam, cfg, num_classes, brute=False, branch=None):
     """Project + render one view.  scene_arrays: (means, scales, quats,
     opacity, rgb, sem_val, sem_idx)."""
     means, scales, quats, opacity, rgb, sem_val, sem_idx = scene_arrays
     pr = project(means, scales, quats, opacity, cam, cfg)
-    mp = render(pr, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, brute=brute)
+    mp = render(pr, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, brute=brute, branch=branch)
     return pr, mp
 
 
-def backward(scene_arrays, cam, cfg, num_classes, grads, proj=None):
+def backward(scene_arrays, cam, cfg, num_classes, grads, proj=None, branch=None):
     """Full analytic gradient of sum_p <grads, maps> for one view, with
-    respect to means, scales, quats, opacity, rgb, sem_val."""
+    respect to means, scales, quats, opacity, rgb, sem_val (`branch` as in
+    render())."""
     means, scales, quats, opacity, rgb, sem_val, sem_idx = scene_arrays
     pr = proj if proj is not None else project(means, scales, quats, opacity, cam, cfg)
-    g2 = render_backward(pr, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, grads)
+    g2 = render_backward(pr, opacity, rgb, sem_val, sem_idx, num_classes, cam, cfg, grads, branch=branch)
     g3 = project_backward(means, scales, quats, cam, pr, g2)
     return {"means": g3["means"], "scales": g3["scales"], "quats": g3["quats"], "opacity": g2["opacity"],
             "rgb": g2["rgb"], "sem_val": g2["sem_val"]}, g2

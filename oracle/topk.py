@@ -13,6 +13,13 @@ never does.  Plain numpy.
 * Fixed-index update: with the indices held fixed, each kept value moves
   toward a new observation, v <- (1 - rate) v + rate * dist[pixel][index]
   (float32, in this order of operations).
+
+Parity status: selection is pinned (a hand example with ties and NaN, brute
+force over all k-subsets).  The update rule is PARITY UNPINNED: the paper
+says the kept values are updated with their indices fixed but gives no
+rule (in mapping they are refined through the semantic loss's gradient), so
+the convex step above is a reading of this project's own; its test checks
+the stated rule, not anything the paper fixes.
 """
 from __future__ import annotations
 

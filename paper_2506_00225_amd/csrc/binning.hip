@@ -110,9 +110,10 @@ __device__ __forceinline__ uint32_t project_pair(const ProjectArgs& a, const Vie
     if (chi > vw.width - 1) chi = vw.width - 1;
     if (rlo < 0) rlo = 0;
     if (rhi > vw.height - 1) rhi = vw.height - 1;
-    // |mean| beyond 2^30 px cannot be represented in the record; such a
-    // Gaussian would need an astronomically large footprint to reach the
-    // image and is treated as culled on both sides of the parity check.
+    // Reading: a projected mean 2^30 px or more from the image origin is
+    // culled (the record's integer part could not hold it; such a Gaussian
+    // reaches the image only through a footprint of the same size).  The
+    // FP64 reference applies the same test.
     if (!(clo <= chi && rlo <= rhi && fabs(mx) < 1073741824.0 && fabs(my) < 1073741824.0)) return 0;
     const int c0 = (int)clo, c1 = (int)chi, r0 = (int)rlo, r1 = (int)rhi;
     count = (uint32_t)((c1 / kTile - c0 / kTile + 1) * (r1 / kTile - r0 / kTile + 1));

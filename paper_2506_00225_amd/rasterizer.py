@@ -63,13 +63,35 @@ class Gaussians:
     def k(self) -> int:
         return int(self.sem_val.shape[1])
 
-    def c_struct(self) -> L.sgr_gaussians:
-        for name in ("means", "scales", "quats", "opacity", "rgb", "sem_val"):
+    def validate(self, n: int | None = None, k: int | None = None, device=None):
+        """Raises ValueError unless every tensor is contiguous, on one CUDA
+        device, of the right dtype and of shape means/scales/rgb [n, 3],
+        quats [n, 4], opacity [n], sem_val/sem_idx [n, k] (n and k from the
+        means and sem_val unless given: a Frame passes its own)."""
+        n = self.n if n is None else int(n)
+        k = self.k if k is None else int(k)
+        dev = self.means.device if device is None else torch.device(device)
+        shapes = {"means": (n, 3), "scales": (n, 3), "quats": (n, 4), "opacity": (n,), "rgb": (n, 3),
+                  "sem_val": (n, k), "sem_idx": (n, k)}
+        for name, shape in shapes.items():
             t = getattr(self, name)
-            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
-                raise ValueError(f"{name}: need a contiguous float32 CUDA tensor")
-        if self.sem_idx.dtype != torch.uint8 or not self.sem_idx.is_contiguous():
-            raise ValueError("sem_idx: need a contiguous uint8 tensor")
+            want = torch.uint8 if name == "sem_idx" else torch.float32
+            if not isinstance(t, torch.Tensor) or t.dtype != want:
+                raise ValueError(f"{name}: need a {want} tensor")
+            if tuple(t.shape) != shape:
+                raise ValueError(f"{name}: shape {tuple(t.shape)}, need {shape}")
+            if not t.is_contiguous():
+                raise ValueError(f"{name}: need a contiguous tensor")
+        for name in shapes:
+            t = getattr(self, name)
+            if not t.is_cuda or t.device != dev:
+                raise ValueError(f"{name}: need a CUDA tensor on {dev}")
+
+    def c_struct(self, frame: "Frame | None" = None) -> L.sgr_gaussians:
+        if frame is None:
+            self.validate()
+        else:
+            self.validate(frame.n, frame.cfg.top_k, frame.device)
         return L.sgr_gaussians(self.n, _ptr(self.means), _ptr(self.scales), _ptr(self.quats), _ptr(self.opacity),
                                _ptr(self.rgb), _ptr(self.sem_val), _ptr(self.sem_idx))
 
@@ -97,6 +119,9 @@ class Frame:
         for p in self.pix:
             self.pix_off.append(self.pix_off[-1] + p)
         self.key_capacity = int(key_capacity or max(1 << 16, 2 * self.n * self.V))
+        # bumped by every call that rewrites the workspace state a backward
+        # reads (projection, sort, per-pixel transmittance and last index)
+        self.generation = 0
         self._alloc()
 
     def _alloc(self):
@@ -116,11 +141,16 @@ class Frame:
     # ------------------------------------------------------------ pipeline steps
 
     def project(self, g: Gaussians):
-        L.check(L.sgr_project(g.c_struct(), *self._args(), _ptr(self.ws), self.ws.numel(), self.stream), "sgr_project")
+        self.generation += 1
+        L.check(L.sgr_project(g.c_struct(self), *self._args(), _ptr(self.ws), self.ws.numel(), self.stream),
+                "sgr_project")
 
     def bin(self, g: Gaussians, d_num_keys=None):
-        L.check(L.sgr_bin(g.c_struct(), *self._args(), _ptr(d_num_keys), _ptr(self.ws), self.ws.numel(), self.stream),
-                "sgr_bin")
+        self.generation += 1
+        if d_num_keys is not None:
+            self._check_tensor("d_num_keys", d_num_keys, torch.int64, 1)
+        L.check(L.sgr_bin(g.c_struct(self), *self._args(), _ptr(d_num_keys), _ptr(self.ws), self.ws.numel(),
+                          self.stream), "sgr_bin")
 
     def status(self):
         """(status, visible pairs, keys); synchronises the stream."""
@@ -156,22 +186,40 @@ class Frame:
         }
         return maps
 
-    def _view_ptrs(self, flat, ch, elem):
+    def _check_tensor(self, name, t, dtype, numel):
+        if not isinstance(t, torch.Tensor) or t.dtype != dtype:
+            raise ValueError(f"{name}: need a {dtype} tensor")
+        if t.numel() < numel:
+            raise ValueError(f"{name}: {t.numel()} elements, need {numel}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous tensor")
+        if not t.is_cuda or t.device != self.device:
+            raise ValueError(f"{name}: need a CUDA tensor on {self.device}")
+
+    def _view_ptrs(self, flat, ch, elem, name="map", dtype=torch.float32):
+        """Per-view pointers into a flat [sum HW, ch] tensor (checked first)."""
         if flat is None:
             return [None] * self.V
+        self._check_tensor(name, flat, dtype, self.pix_off[-1] * ch)
         base = flat.data_ptr()
         return [ctypes.c_void_p(base + self.pix_off[v] * ch * elem) for v in range(self.V)]
 
-    def forward(self, g: Gaussians, maps=None):
-        maps = maps if maps is not None else self.alloc_maps()
+    def _map_table(self, maps):
         C = self.cfg.num_classes
         cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C, "t_final": 1, "n_contrib": 1}
-        ptrs = {key: self._view_ptrs(maps.get(key), cols[key], 4) for key in cols}
+        ptrs = {key: self._view_ptrs(maps.get(key), cols[key], 4, name=key,
+                                     dtype=torch.int32 if key == "n_contrib" else torch.float32) for key in cols}
         arr = (L.sgr_maps * self.V)()
         for v in range(self.V):
             arr[v] = L.sgr_maps(ptrs["rgb"][v], ptrs["depth"][v], ptrs["sil"][v], ptrs["sem"][v],
                                 ptrs["t_final"][v], ptrs["n_contrib"][v])
-        L.check(L.sgr_render_forward(g.c_struct(), *self._args(), arr, _ptr(self.ws), self.ws.numel(), self.stream),
+        return arr
+
+    def forward(self, g: Gaussians, maps=None):
+        maps = maps if maps is not None else self.alloc_maps()
+        arr = self._map_table(maps)
+        self.generation += 1
+        L.check(L.sgr_render_forward(g.c_struct(self), *self._args(), arr, _ptr(self.ws), self.ws.numel(), self.stream),
                 "sgr_render_forward")
         return maps
 
@@ -183,13 +231,9 @@ class Frame:
         C = self.cfg.num_classes
         if dense_sem.shape != (self.n, C):
             raise ValueError(f"dense_sem must be [{self.n}, {C}]")
-        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C, "t_final": 1, "n_contrib": 1}
-        ptrs = {key: self._view_ptrs(maps.get(key), cols[key], 4) for key in cols}
-        arr = (L.sgr_maps * self.V)()
-        for v in range(self.V):
-            arr[v] = L.sgr_maps(ptrs["rgb"][v], ptrs["depth"][v], ptrs["sil"][v], ptrs["sem"][v],
-                                ptrs["t_final"][v], ptrs["n_contrib"][v])
-        L.check(L.sgr_render_forward_dense(g.c_struct(), _ptr(dense_sem), *self._args(), arr, _ptr(self.ws),
+        arr = self._map_table(maps)
+        self.generation += 1
+        L.check(L.sgr_render_forward_dense(g.c_struct(self), _ptr(dense_sem), *self._args(), arr, _ptr(self.ws),
                                            self.ws.numel(), self.stream), "sgr_render_forward_dense")
         return maps
 
@@ -223,32 +267,30 @@ class Frame:
                      torch.full((self.pix[v],), -1, dtype=torch.int32, device=dev)) for v, t in enumerate(targets)])
             else:
                 grads["sem"] = torch.empty((P, C), device=dev)
-        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C, "t_final": 1, "n_contrib": 1}
-        arr = None
-        if maps is not None:
-            ptrs = {key: self._view_ptrs(maps.get(key), cols[key], 4) for key in cols}
-            arr = (L.sgr_maps * self.V)()
-            for v in range(self.V):
-                arr[v] = L.sgr_maps(ptrs["rgb"][v], ptrs["depth"][v], ptrs["sil"][v], ptrs["sem"][v],
-                                    ptrs["t_final"][v], ptrs["n_contrib"][v])
-        gp = {key: self._view_ptrs(grads.get(key), cols[key], 4) for key in ("rgb", "depth", "sil", "sem")}
-        gp["sem_at_label"] = self._view_ptrs(grads.get("sem_at_label"), 1, 4)
+        cols = {"rgb": 3, "depth": 1, "sil": 1, "sem": C}
+        arr = self._map_table(maps) if maps is not None else None
+        gp = {key: self._view_ptrs(grads.get(key), cols[key], 4, name="grad " + key)
+              for key in ("rgb", "depth", "sil", "sem")}
+        gp["sem_at_label"] = self._view_ptrs(grads.get("sem_at_label"), 1, 4, name="grad sem_at_label")
         keep = []
         lv = (L.sgr_loss_view * self.V)()
         for v, t in enumerate(targets):
             tp = {}
-            for key, dt in (("rgb", torch.float32), ("depth", torch.float32), ("label", torch.int32),
-                            ("sem", torch.float32)):
+            for key, dt, ch in (("rgb", torch.float32, 3), ("depth", torch.float32, 1), ("label", torch.int32, 1),
+                                ("sem", torch.float32, C)):
                 x = t.get(key)
                 if x is not None:
                     x = x.to(device=dev, dtype=dt).contiguous()
+                    if x.numel() != self.pix[v] * ch:
+                        raise ValueError(f"target {key} of view {v}: {x.numel()} elements, need {self.pix[v] * ch}")
                     keep.append(x)
                 tp[key] = _ptr(x)
             lv[v] = L.sgr_loss_view(tp["rgb"], tp["depth"], tp["label"], tp["sem"], gp["rgb"][v], gp["depth"][v],
                                     gp["sil"][v], gp["sem"][v], gp["sem_at_label"][v])
         loss = torch.empty(self.V, dtype=torch.float64, device=dev)
         lc = loss_cfg if loss_cfg is not None else loss_config()
-        L.check(L.sgr_render_forward_loss(g.c_struct(), *self._args(), arr, lv, lc, _ptr(loss), _ptr(self.ws),
+        self.generation += 1
+        L.check(L.sgr_render_forward_loss(g.c_struct(self), *self._args(), arr, lv, lc, _ptr(loss), _ptr(self.ws),
                                           self.ws.numel(), self.stream), "sgr_render_forward_loss")
         return grads, loss
 
@@ -267,7 +309,8 @@ class Frame:
                 if t.dtype != want:
                     t = t.to(want)
                 grads[key] = t
-            gp[key] = self._view_ptrs(t, cols[key], 4)
+            gp[key] = self._view_ptrs(t, cols[key], 4, name="grad " + key,
+                                      dtype=torch.int32 if key == "sem_label" else torch.float32)
         arr = (L.sgr_map_grads * self.V)()
         for v in range(self.V):
             arr[v] = L.sgr_map_grads(gp["rgb"][v], gp["depth"][v], gp["sil"][v], gp["sem"][v], gp["sem_label"][v],
@@ -276,29 +319,37 @@ class Frame:
 
     @staticmethod
     def _grads(g: Gaussians, out: dict | None):
+        names = ("means", "scales", "quats", "opacity", "rgb", "sem_val")
         if out is None:
-            out = {name: torch.empty_like(getattr(g, name)) for name in
-                   ("means", "scales", "quats", "opacity", "rgb", "sem_val")}
+            out = {name: torch.empty_like(getattr(g, name)) for name in names}
+        for name in names:
+            t, ref = out.get(name), getattr(g, name)
+            if t is None:
+                continue
+            if (not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.shape != ref.shape
+                    or t.device != ref.device or not t.is_contiguous()):
+                raise ValueError(f"gradient {name}: need a contiguous float32 tensor of shape {tuple(ref.shape)} "
+                                 f"on {ref.device}")
         gr = L.sgr_grads(*[_ptr(out[name]) for name in ("means", "scales", "quats", "opacity", "rgb", "sem_val")])
         return out, gr
 
     def backward(self, g: Gaussians, grads: dict, out: dict | None = None):
         arr = self._map_grads(grads)
         out, gr = self._grads(g, out)
-        L.check(L.sgr_render_backward(g.c_struct(), *self._args(), arr, gr, _ptr(self.ws), self.ws.numel(),
+        L.check(L.sgr_render_backward(g.c_struct(self), *self._args(), arr, gr, _ptr(self.ws), self.ws.numel(),
                                       self.stream), "sgr_render_backward")
         return out
 
     def backward_tiles(self, g: Gaussians, grads: dict):
         """First half of backward: per-key gradient slots (kept in the workspace)."""
         arr = self._map_grads(grads)
-        L.check(L.sgr_render_backward_tiles(g.c_struct(), *self._args(), arr, _ptr(self.ws), self.ws.numel(),
+        L.check(L.sgr_render_backward_tiles(g.c_struct(self), *self._args(), arr, _ptr(self.ws), self.ws.numel(),
                                             self.stream), "sgr_render_backward_tiles")
 
     def backward_gather(self, g: Gaussians, out: dict | None = None):
         """Second half of backward: per-Gaussian gradients from the key slots."""
         out, gr = self._grads(g, out)
-        L.check(L.sgr_render_backward_gather(g.c_struct(), *self._args(), gr, _ptr(self.ws), self.ws.numel(),
+        L.check(L.sgr_render_backward_gather(g.c_struct(self), *self._args(), gr, _ptr(self.ws), self.ws.numel(),
                                              self.stream), "sgr_render_backward_gather")
         return out
 
@@ -306,7 +357,10 @@ class Frame:
         n_empty = n_empty if n_empty is not None else torch.empty(self.V, dtype=torch.int32, device=self.device)
         entropy_sum = entropy_sum if entropy_sum is not None else torch.empty(self.V, dtype=torch.float64,
                                                                                 device=self.device)
-        L.check(L.sgr_score_views(g.c_struct(), *self._args(), _ptr(n_empty), _ptr(entropy_sum), _ptr(self.ws),
+        self._check_tensor("n_empty", n_empty, torch.int32, self.V)
+        self._check_tensor("entropy_sum", entropy_sum, torch.float64, self.V)
+        self.generation += 1
+        L.check(L.sgr_score_views(g.c_struct(self), *self._args(), _ptr(n_empty), _ptr(entropy_sum), _ptr(self.ws),
                                   self.ws.numel(), self.stream), "sgr_score_views")
         return n_empty, entropy_sum
 
@@ -356,6 +410,13 @@ def score_maps(sem: torch.Tensor, n_contrib: torch.Tensor, num_classes: int, scr
 
 
 class _Render(torch.autograd.Function):
+    """The backward reads what the forward left in the frame's workspace
+    (sorted keys, per-pixel final transmittance and last index): the frame's
+    generation is recorded, and a backward after another call rewrote that
+    state raises instead of returning wrong gradients.  The parameters are
+    saved for backward, so autograd also rejects an in-place update made
+    between the two."""
+
     @staticmethod
     def forward(ctx, frame, sem_idx, check, means, scales, quats, opacity, rgb, sem_val):
         g = Gaussians(means.detach(), scales.detach(), quats.detach(), opacity.detach(), rgb.detach(),
@@ -363,13 +424,21 @@ class _Render(torch.autograd.Function):
         frame.prepare(g, check=check)
         maps = frame.forward(g)
         ctx.frame = frame
-        ctx.g = g
+        ctx.generation = frame.generation
+        ctx.sem_idx = sem_idx
+        ctx.save_for_backward(means, scales, quats, opacity, rgb, sem_val)
         ctx.mark_non_differentiable(maps["t_final"], maps["n_contrib"])
         return maps["rgb"], maps["depth"], maps["sil"], maps["sem"], maps["t_final"], maps["n_contrib"]
 
     @staticmethod
     def backward(ctx, g_rgb, g_depth, g_sil, g_sem, _gt, _gn):
-        grads = ctx.frame.backward(ctx.g, {"rgb": g_rgb, "depth": g_depth, "sil": g_sil, "sem": g_sem})
+        if ctx.frame.generation != ctx.generation:
+            raise RuntimeError("render backward: the frame was used by another call (project, bin, forward or "
+                               "score) after this render's forward; its workspace no longer holds this render")
+        means, scales, quats, opacity, rgb, sem_val = ctx.saved_tensors
+        g = Gaussians(means.detach(), scales.detach(), quats.detach(), opacity.detach(), rgb.detach(),
+                      sem_val.detach(), ctx.sem_idx)
+        grads = ctx.frame.backward(g, {"rgb": g_rgb, "depth": g_depth, "sil": g_sil, "sem": g_sem})
         return (None, None, None, grads["means"], grads["scales"], grads["quats"], grads["opacity"], grads["rgb"],
                 grads["sem_val"])
 

@@ -33,8 +33,8 @@ def test_dense_forward_matches_oracle():
     # the oracle with every class listed: k = C, indices 0..C-1, values the dense rows
     arrays = (sc.means, sc.scales, sc.quats, sc.opacity, sc.rgb, dense,
               np.tile(np.arange(C, dtype=np.uint8), (sc.n, 1)))
-    _, want = O.forward(arrays, sc.cameras[0], U.oracle_cfg(), C)
-    U.compare_maps(got, want, want["flags"])
+    rep = U.compare_maps(got, U.OracleView(arrays, sc.cameras[0], U.oracle_cfg(), C))
+    assert rep["unresolved"] == 0, rep
 
 
 def test_dense_forward_equals_top_k_forward_on_sparse_rows():

@@ -92,17 +92,17 @@ def _forward_case(sc, lowpass=None):
     maps = fr.forward(g)
     torch.cuda.synchronize()
     got = {k: fr.split(v)[0].cpu().numpy() for k, v in maps.items()}
-    pr, want = O.forward(O.scene_arrays(sc), sc.cameras[0], U.oracle_cfg(lowpass=lowpass), sc.num_classes)
-    return fr, got, pr, want
+    view = U.OracleView.of_scene(sc, cfg=U.oracle_cfg(lowpass=lowpass))
+    return fr, got, view.pr, view
 
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_forward_tiny_scene(seed):
     _say("forward tiny", seed)
     sc = scenes.tiny_scene(seed=seed)
-    _, got, _, want = _forward_case(sc)
-    rep = U.compare_maps(got, want, want["flags"])
-    assert rep["flagged"] <= 10
+    _, got, _, view = _forward_case(sc)
+    rep = U.compare_maps(got, view)
+    assert rep["flagged"] <= 10 and rep["unresolved"] == 0, rep
 
 
 def test_forward_ragged_view_and_brute_force():
@@ -110,9 +110,12 @@ def test_forward_ragged_view_and_brute_force():
     oracle (no rectangles, no binning)."""
     _say("forward ragged brute")
     sc = scenes.tiny_scene(seed=3, n=1500, width=70, height=45, f=50.0)
-    fr, got, pr, _ = _forward_case(sc)
-    _, want = O.forward(O.scene_arrays(sc), sc.cameras[0], U.oracle_cfg(), sc.num_classes, brute=True)
-    U.compare_maps(got, want, want["flags"])
+    fr, got, pr, view = _forward_case(sc)
+    _, brute = O.forward(O.scene_arrays(sc), sc.cameras[0], U.oracle_cfg(), sc.num_classes, brute=True)
+    for key in ("rgb", "depth", "sil", "sem", "t_final", "n_contrib", "flags"):
+        assert np.array_equal(brute[key], view.mp[key]), key
+    rep = U.compare_maps(got, view)
+    assert rep["unresolved"] == 0, rep
 
 
 def test_forward_thin_rotated_gaussians():
@@ -129,10 +132,10 @@ def test_forward_thin_rotated_gaussians():
     q = rng.standard_normal((sc.n, 4))
     sc.quats[:] = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
     sc.opacity[:] = rng.uniform(0.3, 0.99, sc.n).astype(np.float32)
-    fr, got, pr, want = _forward_case(sc)
-    rep = U.compare_maps(got, want, want["flags"])
-    assert rep["flagged"] <= 20, rep
-    assert int(want["n_contrib"].sum()) > 20 * sc.cameras[0].width  # the needles do overlap pixels
+    fr, got, pr, view = _forward_case(sc)
+    rep = U.compare_maps(got, view)
+    assert rep["flagged"] <= 20 and rep["unresolved"] == 0, rep
+    assert int(view.mp["n_contrib"].sum()) > 20 * sc.cameras[0].width  # the needles do overlap pixels
     _backward_case(sc, 0)
 
 
@@ -140,9 +143,10 @@ def test_forward_room_full_frame():
     """200k Gaussians in the room at 1200x680 (the forward+backward workload)."""
     _say("forward room 200k 1200x680")
     sc = _room_crop()
-    fr, got, pr, want = _forward_case(sc)
-    rep = U.compare_maps(got, want, want["flags"])
-    assert rep["flagged"] <= 0.002 * want["flags"].size, rep
+    fr, got, pr, view = _forward_case(sc)
+    rep = U.compare_maps(got, view)
+    assert rep["flagged"] <= 0.002 * view.flags.size and rep["unresolved"] == 0, rep
+    print("forward room report", rep, flush=True)
     s = got["sil"].astype(np.float64) + got["t_final"]
     assert np.abs(s - 1).max() < 2e-5
     assert (got["sem"].sum(-1) - got["sil"]).__abs__().max() < 2e-5
@@ -173,17 +177,17 @@ def _backward_case(sc, semgeo, seed=0):
     fr = U.frame_for(sc, semgeo=semgeo)
     g = Gaussians.from_scene(sc)
     fr.prepare(g)
-    fr.forward(g)
     gg = {k: torch.from_numpy(v).cuda().reshape(cam.height * cam.width, -1).squeeze(-1).contiguous()
           for k, v in dl.items()}
+    maps = fr.forward(g)
     out = fr.backward(g, gg)
     torch.cuda.synchronize()
     got = {k: U.to_np(v) for k, v in out.items()}
-    cfg = U.oracle_cfg(semgeo=semgeo)
-    pr, mp = O.forward(O.scene_arrays(sc), cam, cfg, sc.num_classes)
-    want, _ = O.backward(O.scene_arrays(sc), cam, cfg, sc.num_classes, dl, proj=pr)
-    bad = U.tainted_gaussians(pr, mp["flags"])
-    return U.compare_grads(got, want, bad)
+    view = U.OracleView.of_scene(sc, cfg=U.oracle_cfg(semgeo=semgeo))
+    mrep = U.compare_maps({k: fr.split(v)[0].cpu().numpy() for k, v in maps.items()}, view)
+    want = view.backward(dl)
+    grep = U.compare_grads(got, want, view.excluded(), visible=view.pr["visible"])
+    return {"maps": mrep, "grads": grep}
 
 
 @pytest.mark.parametrize("semgeo", [0, 1])
@@ -226,6 +230,32 @@ def test_autograd_matches_frame_backward():
     ref = fr2.backward(g2, dict(w))
     for name, p in zip(("means", "scales", "quats", "opacity", "rgb", "sem_val"), params):
         assert torch.equal(p.grad, ref[name]), name
+
+
+def test_render_backward_after_another_call_raises():
+    """The autograd backward reads what its forward left in the frame's
+    workspace: after another render on the same frame it raises instead of
+    returning the other render's gradients, and an in-place update of a
+    parameter between forward and backward is rejected by autograd."""
+    _say("stale backward")
+    sc = scenes.tiny_scene(seed=6)
+    g = Gaussians.from_scene(sc)
+    for p in (g.means, g.scales, g.quats, g.opacity, g.rgb, g.sem_val):
+        p.requires_grad_(True)
+    fr = U.frame_for(sc)
+    first = render(g, fr)
+    second = render(g, fr)
+    with pytest.raises(RuntimeError, match="frame was used"):
+        first["rgb"].sum().backward()
+    second["rgb"].sum().backward()  # the latest render still differentiates
+    assert g.means.grad is not None
+    fr2 = U.frame_for(sc)
+    out = render(g, fr2)
+    with torch.no_grad():
+        g.opacity.mul_(0.5)
+    with pytest.raises(RuntimeError):
+        out["sil"].sum().backward()
+    torch.cuda.synchronize()
 
 
 # ---------------------------------------------------------------- determinism and edge cases
@@ -376,8 +406,8 @@ def test_duplicate_top_k_classes_add(acc):
     maps = fr.forward(g)
     torch.cuda.synchronize()
     got = {k: fr.split(v)[0].cpu().numpy() for k, v in maps.items()}
-    _, want = O.forward(O.scene_arrays(sc), sc.cameras[0], U.oracle_cfg(), sc.num_classes)
-    U.compare_maps(got, want, want["flags"])
+    rep = U.compare_maps(got, U.OracleView.of_scene(sc))
+    assert rep["unresolved"] == 0, rep
 
 
 @pytest.mark.parametrize("case", ["tiny_c16", "room_c102", "tiny_c110"])
@@ -509,14 +539,15 @@ def test_multiview_forward_backward_sums_over_views():
     torch.cuda.synchronize()
     got = {k: U.to_np(v) for k, v in out.items()}
     cfg = U.oracle_cfg()
-    want, bad = None, np.zeros(sc.n, bool)
+    want, bad, vis = None, np.zeros(sc.n, bool), np.zeros(sc.n, bool)
     for v, (c, dl) in enumerate(zip(cams, dls)):
-        pr, mp = O.forward(O.scene_arrays(sc), c, cfg, sc.num_classes)
-        U.compare_maps({k: fr.split(maps[k])[v].cpu().numpy() for k in maps}, mp, mp["flags"])
-        gv, _ = O.backward(O.scene_arrays(sc), c, cfg, sc.num_classes, dl, proj=pr)
+        view = U.OracleView.of_scene(sc, cam=c, cfg=cfg)
+        U.compare_maps({k: fr.split(maps[k])[v].cpu().numpy() for k in maps}, view)
+        gv = view.backward(dl)
         want = gv if want is None else {k: want[k] + gv[k] for k in want}
-        bad |= U.tainted_gaussians(pr, mp["flags"])
-    U.compare_grads(got, want, bad)
+        bad |= view.excluded()
+        vis |= view.pr["visible"] == 1
+    print("multiview report", U.compare_grads(got, want, bad, visible=vis), flush=True)
 
 
 def test_full_size_mapping_frame_1m():
@@ -543,13 +574,13 @@ def test_full_size_mapping_frame_1m():
     out = fr.backward(g, gg)
     torch.cuda.synchronize()
     got_maps = {k: fr.split(v)[0].cpu().numpy() for k, v in maps.items()}
-    cfg = U.oracle_cfg()
-    pr, mp = O.forward(O.scene_arrays(sc), cam, cfg, sc.num_classes)
-    rep = U.compare_maps(got_maps, mp, mp["flags"])
-    assert rep["flagged"] <= 0.002 * mp["flags"].size, rep
-    want, _ = O.backward(O.scene_arrays(sc), cam, cfg, sc.num_classes, dl, proj=pr)
+    view = U.OracleView.of_scene(sc)
+    rep = U.compare_maps(got_maps, view)
+    assert rep["flagged"] <= 0.002 * view.flags.size, rep
+    want = view.backward(dl)
     got = {k: U.to_np(v) for k, v in out.items()}
-    print("full size report", rep, U.compare_grads(got, want, U.tainted_gaussians(pr, mp["flags"])), flush=True)
+    print("full size report", rep, U.compare_grads(got, want, view.excluded(), visible=view.pr["visible"]),
+          flush=True)
 
 
 def test_score_views_graph_replay_matches_eager():
