@@ -457,7 +457,9 @@ sgr_status sgr_combine_scores(int32_t num_views, const uint32_t *n_empty, const 
  * and the key count of the workspace (host outputs; any may be NULL). */
 sgr_status sgr_read_status(const void *workspace, void *stream, int64_t *num_visible, int64_t *num_keys);
 
-const char *sgr_status_string(sgr_status s);
+/* A static, NUL-terminated description of a status code; any int is
+ * accepted (a value that is not an sgr_status gives "unknown status"). */
+const char *sgr_status_string(int32_t status);
 
 #ifdef __cplusplus
 }

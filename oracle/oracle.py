@@ -17,7 +17,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c (the sanitizer job of the CPU
+# tests loads an ASan/UBSan build this way); it is used as built.
+_LIB_ENV = os.environ.get("ORACLE_LIB")
+_LIB = _LIB_ENV or os.path.join(_HERE, "liboracle.so")
 
 # Default renderer constants (readings of the paper; see the design notes).
 ALPHA_MIN = float(np.float32(1.0 / 255.0))
@@ -29,6 +32,8 @@ LOWPASS = float(np.float32(0.3))
 
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (plain gcc, -O2, OpenMP)."""
+    if _LIB_ENV:
+        return _LIB
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
@@ -43,7 +48,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not _LIB_ENV and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p

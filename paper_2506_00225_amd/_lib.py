@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libsgr.so")
+# SGR_LIB names another build of the same library (the sanitizer job of the
+# CPU tests loads a host-sanitized build this way).
+LIB_PATH = os.environ.get("SGR_LIB") or os.path.join(_PKG, "libsgr.so")
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
 P = ctypes.c_void_p

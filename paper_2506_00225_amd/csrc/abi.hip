@@ -406,7 +406,9 @@ sgr_status sgr_read_status(const void* workspace, void* stream, int64_t* num_vis
     return SGR_OK;
 }
 
-const char* sgr_status_string(sgr_status s) {
+const char* sgr_status_string(int32_t s) {
+    // an int, not the enum: a caller may hand in any code, and a value
+    // outside the enumerators is not a valid sgr_status in C++
     switch (s) {
         case SGR_OK: return "ok";
         case SGR_EINVAL: return "invalid argument";

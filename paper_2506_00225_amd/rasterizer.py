@@ -45,6 +45,15 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _device(device) -> torch.device:
+    """torch.device with the index filled in ("cuda" means the current
+    device), so it compares equal to a tensor's device."""
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device() if torch.cuda.is_available() else 0)
+    return d
+
+
 @dataclass
 class Gaussians:
     means: torch.Tensor
@@ -70,7 +79,7 @@ class Gaussians:
         means and sem_val unless given: a Frame passes its own)."""
         n = self.n if n is None else int(n)
         k = self.k if k is None else int(k)
-        dev = self.means.device if device is None else torch.device(device)
+        dev = self.means.device if device is None else _device(device)
         shapes = {"means": (n, 3), "scales": (n, 3), "quats": (n, 4), "opacity": (n,), "rgb": (n, 3),
                   "sem_val": (n, k), "sem_idx": (n, k)}
         for name, shape in shapes.items():
@@ -112,7 +121,7 @@ class Frame:
         self.cams = camera_array(self.cam_list)
         self.V = len(self.cam_list)
         self.cfg = cfg
-        self.device = torch.device(device)
+        self.device = _device(device)
         self.sizes = [(int(c.height), int(c.width)) for c in self.cam_list]
         self.pix = [h * w for h, w in self.sizes]
         self.pix_off = [0]

@@ -80,3 +80,13 @@ def test_gradient_outputs_checked():
         Frame._grads(g, {"sem_val": torch.zeros(10, 2)})
     with pytest.raises(ValueError, match="gradient means"):
         Frame._grads(g, {"means": torch.zeros(10, 3, dtype=torch.float64)})
+
+
+def test_device_without_index_means_the_current_device():
+    """A frame made for "cuda" compares equal to tensors on the current
+    device (a bare "cuda" device differs from "cuda:0" in torch)."""
+    from paper_2506_00225_amd.rasterizer import _device
+    d = _device("cuda")
+    assert d.type == "cuda" and d.index is not None
+    assert _device("cuda:0") == torch.device("cuda", 0)
+    assert _device("cpu") == torch.device("cpu")
