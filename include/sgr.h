@@ -318,6 +318,25 @@ sgr_status sgr_score_maps(const float *sem, const int32_t *n_contrib, int32_t wi
                           int32_t num_classes, uint32_t *n_empty, double *entropy_sum, void *workspace,
                           size_t workspace_bytes, void *stream);
 
+/*
+ * sgr_score_maps_noalloc -- sgr_score_maps for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): it takes no workspace and allocates
+ * nothing.  Its per-block partial sums live in a static device array of
+ * SGR_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, so it accepts at most SGR_NOALLOC_MAX_PIXELS
+ * pixels (width * height); a larger view returns SGR_EUNSUPPORTED before
+ * anything is enqueued.  Other arguments and outputs as sgr_score_maps
+ * (device arrays; SGR_EINVAL for a bad argument; SGR_EHIP if the array's
+ * device address cannot be found).  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (two streams, or two threads) race
+ * and give wrong results; calls ordered on one stream are fine.
+ */
+#define SGR_NOALLOC_SCRATCH_BYTES (1u << 20)
+#define SGR_NOALLOC_MAX_PIXELS (16 * 1024 * 1024)
+sgr_status sgr_score_maps_noalloc(const float *sem, const int32_t *n_contrib, int32_t width, int32_t height,
+                                  int32_t num_classes, uint32_t *n_empty, double *entropy_sum, void *stream);
+
 /* ------------------------------------------------------------------------
  * Mapping-iteration helpers (used by a mapping step around the rasterizer).
  * ------------------------------------------------------------------------ */

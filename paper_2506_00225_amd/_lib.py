@@ -96,7 +96,7 @@ EXPORTS = (
     "sgr_render_backward", "sgr_render_backward_tiles", "sgr_render_backward_gather", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
     "sgr_read_status", "sgr_status_string", "sgr_mapping_loss_grad", "sgr_adam_step",
     "sgr_candidates_workspace_size", "sgr_generate_candidates", "sgr_score_poses", "sgr_combine_scores",
-    "sgr_topk_select", "sgr_topk_update",
+    "sgr_topk_select", "sgr_topk_update", "sgr_score_maps_noalloc",
 )
 
 _lib = None
@@ -162,6 +162,8 @@ def lib():
     L.sgr_topk_select.restype = i32
     L.sgr_topk_update.argtypes = [P, P, i64, i32, i32, P, ctypes.c_float, P, P]
     L.sgr_topk_update.restype = i32
+    L.sgr_score_maps_noalloc.argtypes = [P, P, i32, i32, i32, P, P, P]
+    L.sgr_score_maps_noalloc.restype = i32
     L.sgr_status_string.argtypes = [i32]
     L.sgr_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -248,6 +250,15 @@ def sgr_score_maps(sem, n_contrib, width, height, num_classes, n_empty, entropy_
                    stream):
     return lib().sgr_score_maps(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, workspace,
                                 workspace_bytes, stream)
+
+
+# the static scratch of sgr_score_maps_noalloc (include/sgr.h) holds the
+# partial sums of at most this many pixels
+SGR_NOALLOC_MAX_PIXELS = 16 * 1024 * 1024
+
+
+def sgr_score_maps_noalloc(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, stream):
+    return lib().sgr_score_maps_noalloc(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, stream)
 
 
 def sgr_read_status(workspace, stream):

@@ -211,6 +211,34 @@ size_t score_maps_scratch_bytes(int W, int H) {
     return align_up((sizeof(double) + sizeof(uint32_t)) * grid + sizeof(uint32_t), 256);
 }
 
+// Scratch of sgr_score_maps_noalloc: one static device array per GPU (the
+// runtime gives each device its own copy), so that entry point never
+// allocates.  Host code must not pass `scratch` itself to a kernel (in host
+// code the name is a host-side stand-in, not a device address): the address
+// is looked up once per device with hipGetSymbolAddress and kept here.
+static __device__ __align__(256) unsigned char scratch[SGR_NOALLOC_SCRATCH_BYTES];
+static void* g_scratch_ptr[64];
+static_assert((sizeof(double) + sizeof(uint32_t)) * (SGR_NOALLOC_MAX_PIXELS / kBlock) + sizeof(uint32_t) + 255 <=
+                  SGR_NOALLOC_SCRATCH_BYTES,
+              "the static scratch holds the partial sums of the largest view it accepts");
+
+// Device address of this device's `scratch`, looked up on the first call on
+// the device (with that device current); nullptr if the lookup fails.
+static void* noalloc_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace sgr
 
 using namespace sgr;
@@ -391,6 +419,20 @@ sgr_status sgr_score_maps(const float* sem, const int32_t* n_contrib, int32_t wi
     if (!workspace || workspace_bytes < score_maps_scratch_bytes(width, height) || ((uintptr_t)workspace & 255u))
         return SGR_EINVAL;
     return launch_score_maps(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, (char*)workspace,
+                             (hipStream_t)stream);
+}
+
+sgr_status sgr_score_maps_noalloc(const float* sem, const int32_t* n_contrib, int32_t width, int32_t height,
+                                  int32_t num_classes, uint32_t* n_empty, double* entropy_sum, void* stream) {
+    if (!sem || !n_contrib || !n_empty || !entropy_sum || width < 1 || height < 1 || num_classes < 1 ||
+        num_classes > kMaxC)
+        return SGR_EINVAL;
+    if ((int64_t)width * height > SGR_NOALLOC_MAX_PIXELS) return SGR_EUNSUPPORTED;
+    void* ptr = noalloc_scratch();
+    if (!ptr) return SGR_EHIP;
+    // the same launches as sgr_score_maps; its counter is cleared by a kernel
+    // at the start of every call, the partial sums are written before read
+    return launch_score_maps(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, (char*)ptr,
                              (hipStream_t)stream);
 }
 

@@ -418,6 +418,27 @@ def score_maps(sem: torch.Tensor, n_contrib: torch.Tensor, num_classes: int, scr
     return n_empty, entropy_sum
 
 
+def score_maps_noalloc(sem: torch.Tensor, n_contrib: torch.Tensor, num_classes: int, n_empty: torch.Tensor,
+                       entropy_sum: torch.Tensor):
+    """score_maps without a workspace (sgr_score_maps_noalloc): the library
+    allocates nothing, and neither does this wrapper; the caller passes
+    n_empty (int32 [1]) and entropy_sum (float64 [1]) on sem's device.  At
+    most L.SGR_NOALLOC_MAX_PIXELS pixels; calls that overlap on one GPU race
+    on the library's static scratch."""
+    H, W = int(n_contrib.shape[0]), int(n_contrib.shape[1])
+    if W * H > L.SGR_NOALLOC_MAX_PIXELS:
+        raise ValueError(f"{W}x{H} view: score_maps_noalloc takes at most {L.SGR_NOALLOC_MAX_PIXELS} pixels")
+    for name, t, dt, numel in (("sem", sem, torch.float32, W * H * int(num_classes)),
+                               ("n_contrib", n_contrib, torch.int32, W * H), ("n_empty", n_empty, torch.int32, 1),
+                               ("entropy_sum", entropy_sum, torch.float64, 1)):
+        if t.dtype != dt or not t.is_cuda or t.device != sem.device or not t.is_contiguous() or t.numel() < numel:
+            raise ValueError(f"{name}: need a contiguous {dt} tensor of {numel} elements on {sem.device}")
+    stream = ctypes.c_void_p(torch.cuda.current_stream(sem.device).cuda_stream)
+    L.check(L.sgr_score_maps_noalloc(_ptr(sem), _ptr(n_contrib), W, H, int(num_classes), _ptr(n_empty),
+                                     _ptr(entropy_sum), stream), "sgr_score_maps_noalloc")
+    return n_empty, entropy_sum
+
+
 class _Render(torch.autograd.Function):
     """The backward reads what the forward left in the frame's workspace
     (sorted keys, per-pixel final transmittance and last index): the frame's

@@ -134,6 +134,11 @@ def test_calls_validate_before_any_device_work(L):
     assert L.sgr_score_views(g, cams, 1, cfg, 100, None, None, addr, size, None) == L.SGR_EINVAL
     assert L.sgr_score_maps(None, None, 4, 4, 16, None, None, None, 0, None) == L.SGR_EINVAL
     assert L.sgr_score_maps_workspace_size(0, 4) == 0
+    assert L.sgr_score_maps_noalloc(None, None, 4, 4, 16, None, None, None) == L.SGR_EINVAL
+    one = ctypes.c_void_p(256)  # never dereferenced: each call below returns before any device work
+    assert L.sgr_score_maps_noalloc(one, one, 0, 4, 16, one, one, None) == L.SGR_EINVAL
+    assert L.sgr_score_maps_noalloc(one, one, 4, 4, 0, one, one, None) == L.SGR_EINVAL
+    assert L.sgr_score_maps_noalloc(one, one, 4097, 4096, 16, one, one, None) == L.SGR_EUNSUPPORTED
     # fused forward + loss: missing views, config or loss output; negative weights
     lv = (L.sgr_loss_view * 1)()
     lc = L.sgr_loss_config(1.0, 0.5, 1.0, 1.0, 0.99, 1e-6, 0.8, 0.2, 0.0, 1e-8)
