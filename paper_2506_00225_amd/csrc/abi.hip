@@ -95,6 +95,8 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     P->scol = take(16 * vns);
     P->ssv = take(4 * (size_t)P->k * vns);
     P->ssi = take((size_t)P->kpad * vns);
+    P->ranked = P->k == 16 && P->C <= 128;
+    if (P->ranked) P->srk = take(4 * (size_t)kRankWords * vns);
     P->tcount = take(4 * vns);
     P->toff = take(4 * vns);
     P->keys0 = take(4 * caps);

@@ -302,6 +302,33 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
             if (4 * w + b < KM) word |= cout[4 * w + b] << (8 * b);
         if (w < kw) di[w] = word;
     }
+    if constexpr (KT == 16) {
+        if (a.srk) {
+            // class-rank table of the stored list (classes < 128 here)
+            uint32_t mk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const uint32_t c = cout[q] & 127u;
+#pragma unroll
+                for (int w = 0; w < 4; w++) mk[w] |= (c >> 5) == (uint32_t)w ? 1u << (c & 31u) : 0u;
+            }
+            const uint32_t n0 = __builtin_popcount(mk[0]), n1 = n0 + __builtin_popcount(mk[1]),
+                           n2 = n1 + __builtin_popcount(mk[2]);
+            const uint32_t below = (n0 << 8) | (n1 << 16) | (n2 << 24);
+            uint64_t perm = 0;
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const uint32_t c = cout[q] & 127u, w = c >> 5;
+                const uint32_t base = w == 0 ? 0u : (w == 1 ? n0 : (w == 2 ? n1 : n2));
+                const uint32_t mw = w == 0 ? mk[0] : (w == 1 ? mk[1] : (w == 2 ? mk[2] : mk[3]));
+                const uint32_t rank = base + __builtin_popcount(mw & ((1u << (c & 31u)) - 1u));
+                perm |= dup ? 0ull : (uint64_t)q << (4 * (rank & 15u));
+            }
+            uint4* dst = (uint4*)(a.srk + (size_t)g * kRankWords);
+            dst[0] = make_uint4(mk[0], mk[1], mk[2], mk[3]);
+            dst[1] = make_uint4(below, (uint32_t)perm, (uint32_t)(perm >> 32), 0u);
+        }
+    }
     if (bad) atomicOr(&a.counters[kStatus], Plan::kBadIndex);
     p.r2.w = __uint_as_float(__float_as_uint(p.r2.w) | (dup ? 0x80000000u : 0u));
     a.srec[g] = p;
@@ -448,7 +475,7 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
     ga.rgb = g->rgb; ga.sem_val = g->sem_val; ga.sem_idx = g->sem_idx;
     ga.n = P.n; ga.k = P.k; ga.kpad = P.kpad; ga.C = P.C; ga.counters = counters;
     ga.srec = (Proj*)(ws + P.srec); ga.scol = (float4*)(ws + P.scol); ga.ssv = (float*)(ws + P.ssv);
-    ga.ssi = (uint8_t*)(ws + P.ssi); ga.tcount = (uint32_t*)(ws + P.tcount); ga.gp_of_lin = pa.gp_of_lin;
+    ga.ssi = (uint8_t*)(ws + P.ssi); ga.srk = P.ranked ? (uint32_t*)(ws + P.srk) : nullptr; ga.tcount = (uint32_t*)(ws + P.tcount); ga.gp_of_lin = pa.gp_of_lin;
     const unsigned ggrid = (unsigned)div_up(P.vn, 256);
     if (P.k == 16) gather_sorted<16><<<ggrid, 256, 0, st>>>(ga);
     else if (P.k == 3) gather_sorted<3><<<ggrid, 256, 0, st>>>(ga);

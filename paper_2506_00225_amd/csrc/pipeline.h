@@ -26,6 +26,10 @@ struct Plan {
     size_t count = 0, zbits = 0, gp_of_lin = 0;
     size_t vis_k0 = 0, vis_v0 = 0, vis_k1 = 0, vis_v1 = 0, order = 0;
     size_t srec = 0, scol = 0, ssv = 0, ssi = 0, tcount = 0, toff = 0;
+    // class-rank table of each visible pair (kRankWords words), kept when the
+    // top-k lists have 16 entries over at most 128 classes
+    bool ranked = false;
+    size_t srk = 0;
     size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, sgp = 0, ranges = 0, heads = 0;
     size_t sorted_keys = 0, sorted_vals = 0;
     size_t hist = 0, partial = 0;
@@ -59,6 +63,7 @@ struct GatherArgs {
     float4* scol;
     float* ssv;
     uint8_t* ssi;
+    uint32_t* srk;  // class-rank table [vis][kRankWords], or nullptr
     uint32_t *tcount, *gp_of_lin;
 };
 

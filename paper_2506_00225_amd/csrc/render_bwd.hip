@@ -113,17 +113,31 @@ __device__ __forceinline__ int transposed_value_index(int lane) {
     return NP == 32 ? 16 * b1 + 8 * b2 + 4 * b3 + 2 * b4 + b5 : 8 * b2 + 4 * b3 + 2 * b4 + b5;
 }
 
-// Per-key value layout (slots): 0,1 mean2d; 2,3,4 conic (a, b, c);
-// 5 opacity; 6,7,8 rgb; 9 depth; 10.. semantic values.  Per pixel the first
-// five are dQ dx, dQ dy, dQ dx^2, dQ dx dy, dQ dy^2 (dQ the gradient of the
-// exponent); the key's mean and conic gradients are formed from their sums.
+// Per-key value layout (slots): 0,1 mean2d; 2,3,4 the 2D covariance
+// Sigma2 (xx, both off-diagonal entries together, yy); 5 opacity; 6,7,8 rgb;
+// 9 depth; 10.. semantic values.  With Q = d^T A d (A = Sigma2^-1, d the
+// offset from the mean) and u = A d, dQ/dmean = -2 u and dQ/dSigma2 = -u u^T,
+// so per pixel the first five are dQ ux, dQ uy, dQ ux^2, dQ ux uy, dQ uy^2
+// (u in units of 2 ln 2, dQ = dL/dQ), scaled once per key.  Summing in this
+// whitened frame keeps float32 rounding relative to the gradient itself:
+// summing dQ d d^T and multiplying by A on both sides afterwards would scale
+// the sum's rounding by the conic's condition number (thousands for the
+// thin, long splats of a room scene).
 // SPARSE: no view has a dense dL/dsem; each pixel's semantic gradient is one
 // (class, value) pair (or none), held in registers instead of a 257-float
 // LDS column per class, which leaves room for more workgroups per CU.
+// RANKED (SPARSE, k = 16, C <= 128, semantic gradient kept off geometry): a
+// pixel finds its label's position in a key's list through the key's class
+// rank table (mask word, popcount, nibble) and adds its value into that
+// position's per-wave LDS bin; bins of one wave are written by one wave
+// only, one add instruction per key, which the LDS applies in a fixed lane
+// order, so sums are reproducible bit for bit.  The wave reduction then
+// carries only the ten geometry values.
 // With k fixed at compile time the one-class kernel is held to 80 VGPRs for
 // six waves per SIMD, matching the six workgroups its LDS allows.
-template <int KT, bool SPARSE>
+template <int KT, bool SPARSE, bool RANKED = false>
 __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 5) : 1) void render_bwd_kernel(BwdArgs b) {
+    static_assert(!RANKED || (KT == 16 && SPARSE), "the rank lookup needs k = 16 and a one-class gradient");
     extern __shared__ __align__(16) float smem[];
     const TileArgs& a = b.t;
     const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
@@ -135,9 +149,11 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
     const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
     const int C = a.C;
     constexpr int NVMAX = 10 + (KT > 0 ? KT : kMaxK);
-    // padded value count of the transposed reduction (0: per-value DPP sums)
-    constexpr int NP = (KT > 0 && NVMAX <= 16) ? 16 : ((KT > 0 && NVMAX <= 32) ? 32 : 0);
+    // padded value count of the transposed reduction (0: per-value DPP sums);
+    // RANKED reduces the ten geometry values only
+    constexpr int NP = RANKED ? 16 : ((KT > 0 && NVMAX <= 16) ? 16 : ((KT > 0 && NVMAX <= 32) ? 32 : 0));
     constexpr int NREG = NP > 0 ? NP : NVMAX;
+    constexpr int NRED = RANKED ? 10 : NVMAX;  // values that go through the wave reduction
     const int NV = 10 + k;
 
     constexpr int KM = KT > 0 ? KT : kMaxK;  // register bound on k
@@ -148,9 +164,11 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
     float4* s_r2 = s_r1 + kBwdBatch;
     float4* s_col = s_r2 + kBwdBatch;
     uint32_t* s_e = (uint32_t*)(s_col + kBwdBatch);                   // emission index of each key
-    float* s_sv = (float*)(s_e + kBwdBatch);
-    uint32_t* s_si = (uint32_t*)(s_sv + kBwdBatch * k);
-    float* part = (float*)(s_si + kBwdBatch * kw);                    // [waves][kBwdBatch][NV]
+    float* s_sv = (float*)(s_e + kBwdBatch);                          // top-k values (not RANKED)
+    uint32_t* s_si = (uint32_t*)(s_sv + (RANKED ? 0 : kBwdBatch * k));
+    uint2* s_lm = (uint2*)(s_si + kBwdBatch * kw);                    // RANKED: [kBwdBatch][4] (mask word, classes below)
+    uint2* s_pm = s_lm + (RANKED ? 4 * kBwdBatch : 0);                // RANKED: [kBwdBatch] rank -> list position
+    float* part = (float*)(s_pm + (RANKED ? kBwdBatch : 0));          // [waves][kBwdBatch][NV]
     uint32_t* flag = (uint32_t*)(part + kBwdWaves * kBwdBatch * NV);  // [waves][kBwdBatch]
     __shared__ uint32_t s_maxlast;
 
@@ -181,6 +199,11 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
         lab = gr.sem_label[pix];
         gl = gr.sem_at_label ? gr.sem_at_label[pix] : 0.f;
     }
+    // RANKED: the label's mask word, its bit and the bits below it (a label
+    // of 128 or more is in no list: classes are below C <= 128 here)
+    const bool haslab = lab >= 0 && lab < 128;
+    const int lword = haslab ? (lab >> 5) : 0;
+    const uint32_t lbit = (uint32_t)lab & 31u, lbelow = (1u << lbit) - 1u;
     if (tid == 0) s_maxlast = start;
     if constexpr (!SPARSE) {
         const int x0 = tx * kTile, y0 = ty * kTile;
@@ -215,7 +238,8 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
     for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
     wlast = __builtin_amdgcn_readfirstlane(wlast);
     const float amin = a.alpha_min, amax = a.alpha_max;
-    const float k2ln2 = 1.38629436111989061883f;  // 2 ln 2
+    const float k2ln2 = 1.38629436111989061883f;    // 2 ln 2
+    const float k2ln2sq = 1.92181205567280529356f;  // (2 ln 2)^2
     const int wx0 = tx * kTile + (wv & 1) * 8, wy0 = ty * kTile + (wv >> 1) * 8;  // this wave's 8x8 block
     float R = 0.f;
 
@@ -249,6 +273,19 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
             put4(0, rp[2]);
             put4(4, a.scol[g]);
             stg[8] = b.svals[f0 + rl];
+        } else if constexpr (RANKED) {
+            // wave 2: the class words and the rank -> position nibbles; wave 3: the mask
+            const uint32_t* rk = a.srk + (size_t)g * kRankWords;
+            if (role == 2) {
+                const uint4 w4 = *(const uint4*)((const uint32_t*)(a.ssi) + (size_t)g * 4);
+                stg[0] = w4.x; stg[1] = w4.y; stg[2] = w4.z; stg[3] = w4.w;
+                stg[4] = rk[5];
+                stg[5] = rk[6];
+            } else {
+                const uint4 m4 = *(const uint4*)rk;
+                stg[0] = m4.x; stg[1] = m4.y; stg[2] = m4.z; stg[3] = m4.w;
+                stg[4] = rk[4];
+            }
         } else {
             const int v0 = role == 2 ? 0 : VH, w0 = role == 2 ? 0 : WH;
             const float* sv = a.ssv + (size_t)g * k;
@@ -275,6 +312,15 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                 s_r2[rl] = get4(0);
                 s_col[rl] = get4(4);
                 s_e[rl] = stg[8];
+            } else if constexpr (RANKED) {
+                if (role == 2) {
+#pragma unroll
+                    for (int m = 0; m < 4; m++) s_si[rl * 4 + m] = stg[m];
+                    s_pm[rl] = make_uint2(stg[4], stg[5]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) s_lm[rl * 4 + q] = make_uint2(stg[q], (stg[4] >> (8 * q)) & 0xffu);
+                }
             } else {
                 const int v0 = role == 2 ? 0 : VH, w0 = role == 2 ? 0 : WH;
 #pragma unroll
@@ -309,8 +355,8 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
             const uint32_t s = b0 + j;
             const float4 q0 = s_r0[j], q1 = s_r1[j], q2 = s_r2[j];
             const uint32_t rx = __float_as_uint(q2.x), ry = __float_as_uint(q2.y);
-            float G, dx, dy;
-            const float alpha = eval_alpha(q0, q1, px, py, amax, &G, &dx, &dy);
+            float G, dx, dy, uu;
+            const float alpha = eval_alpha_u(q0, q1, px, py, amax, &G, &dx, &dy, &uu);
             const bool act = s < last && px >= (int)(rx & 0xffffu) && px <= (int)(rx >> 16) &&
                              py >= (int)(ry & 0xffffu) && py <= (int)(ry >> 16) && alpha >= amin;
             const uint64_t any = __ballot(act);
@@ -323,7 +369,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                 // classes (dense form) and their sum weighted by the key's
                 // values (only when the semantic loss reaches alpha)
                 uint32_t cw[KWM];
-                const float* sv = s_sv + j * k;
+                const float* sv = s_sv + (RANKED ? 0 : j * k);
                 {
                     const uint32_t* si = s_si + j * kw;
 #pragma unroll
@@ -340,7 +386,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                             es += sv[m] * sg[m];
                         }
                     }
-                } else if (b.semgeo) {
+                } else if (!RANKED && b.semgeo) {
 #pragma unroll
                     for (int m = 0; m < KM; m++) {
                         if (m < k) {
@@ -365,19 +411,23 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                 const bool free = act && alpha < amax;
                 const float dQ = free ? dalpha * (-0.5f * alpha) : 0.f;
                 val[5] = free ? dalpha * G : 0.f;
-                // per pixel: dQ dx, dQ dy, dQ dx^2, dQ dx dy, dQ dy^2; the
-                // key's conic and mean gradients are formed from their sums
-                // (the conic is the same for all of the key's pixels)
-                val[0] = dQ * dx;
-                val[1] = dQ * dy;
-                val[2] = val[0] * dx;
-                val[3] = val[0] * dy;
-                val[4] = val[1] * dy;
+                // per pixel, with u = A d / (2 ln 2) = (ca uu, cb ux + cc dy):
+                // dQ ux, dQ uy, dQ ux^2, dQ ux uy, dQ uy^2; the key's mean
+                // and Sigma2 gradients are these sums, scaled once
+                const float ux = q1.x * uu;
+                const float uy = fmaf(q1.y, ux, q1.z * dy);
+                val[0] = dQ * ux;
+                val[1] = dQ * uy;
+                val[2] = val[0] * ux;
+                val[3] = val[0] * uy;
+                val[4] = val[1] * uy;
                 val[6] = w * gC0;
                 val[7] = w * gC1;
                 val[8] = w * gC2;
                 val[9] = w * gD;
-                if constexpr (SPARSE) {
+                if constexpr (RANKED) {
+                    // semantic values go to the per-wave bins below
+                } else if constexpr (SPARSE) {
                     // one class per pixel: w gl where the key's class is the
                     // label (no class where the pixel does not blend); the
                     // label is kept in one register, so each class costs a
@@ -400,7 +450,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                     if (act) {
 #pragma unroll
                         for (int q = 0; q < NREG; q++)
-                            if (q < NV) dst[q] = val[q];
+                            if (q < NV && q < NRED) dst[q] = val[q];
                     }
                 }
                 // Two separate regions, the single-lane one first: the
@@ -409,15 +459,41 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                 __builtin_amdgcn_sched_barrier(0);
                 if (one) {
                 } else if constexpr (NP > 0) {
-                    const float sum = wave_transpose_sum<NP, (KT > 0 ? 10 + KT : NP)>(val, lane);
+                    const float sum = wave_transpose_sum<NP, (RANKED ? 10 : (KT > 0 ? 10 + KT : NP))>(val, lane);
                     const int q = transposed_value_index<NP>(lane);
-                    if ((lane & (NP == 32 ? 1 : 3)) == 0 && q < NV) dst[q] = sum;
+                    if ((lane & (NP == 32 ? 1 : 3)) == 0 && q < NV && q < NRED) dst[q] = sum;
                 } else {
 #pragma unroll
                     for (int q = 0; q < NREG; q++) {
                         if (q < NV) {
                             const float sum = wave_sum_lane63(val[q]);
                             if (lane == 63) dst[q] = sum;
+                        }
+                    }
+                }
+                if constexpr (RANKED) {
+                    // the wave's semantic bins of this key: cleared, then each
+                    // blending lane whose label is in the key's list adds w gl
+                    // at that class's list position (in order: one wave's LDS
+                    // operations complete in issue order)
+                    float* sb = dst + 10;
+                    if (lane < 16) sb[lane] = 0.f;
+                    const float wg = w * gl;
+                    if ((__float_as_uint(q2.w) >> 31) == 0u) {  // distinct classes
+                        const uint2 mw = s_lm[j * 4 + lword];
+                        const uint2 pm = s_pm[j];
+                        const uint32_t rank = mw.y + __builtin_popcount(mw.x & lbelow);
+                        const uint64_t perm = ((uint64_t)pm.y << 32) | pm.x;
+                        const uint32_t slot = (uint32_t)(perm >> ((4u * rank) & 63u)) & 15u;
+                        if (act && haslab && ((mw.x >> lbit) & 1u)) atomicAdd(sb + slot, wg);
+                    } else {
+                        // a list with a repeated class: each of its positions
+                        // that holds the label gets w gl
+                        const uint32_t* si = s_si + j * 4;
+#pragma unroll
+                        for (int m = 0; m < 16; m++) {
+                            const uint32_t cls = (si[m >> 2] >> (8 * (m & 3))) & 0xffu;
+                            if (act && (int)cls == lab) atomicAdd(sb + m, wg);
                         }
                     }
                 }
@@ -440,22 +516,12 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
 #pragma unroll
                 for (int w = 0; w < kBwdWaves; w++)
                     if (fl[w]) sum += part[(w * kBwdBatch + j) * NV + q];
-                if (q < 2) {
-                    // mean: dL/dmu = -2 [[a, b], [b, c]] (sum dQ dx, sum dQ dy),
-                    // with the conic (a, b, c) of this key
-                    float other = 0.f;
-#pragma unroll
-                    for (int w = 0; w < kBwdWaves; w++)
-                        if (fl[w]) other += part[(w * kBwdBatch + j) * NV + (q ^ 1)];
-                    const float4 c1 = s_r1[j];
-                    const float ca = c1.x * k2ln2;
-                    const float cb = c1.y * ca;
-                    const float cc = c1.z * k2ln2 + c1.y * cb;
-                    const float sx = q == 0 ? sum : other, sy = q == 0 ? other : sum;
-                    sum = -2.f * (q == 0 ? fmaf(ca, sx, cb * sy) : fmaf(cb, sx, cc * sy));
-                } else if (q == 3) {
-                    sum *= 2.f;  // the conic's off-diagonal term carries 2 dx dy
-                }
+                // with u in units of 2 ln 2: dL/dmean = -2 (2 ln 2) sum dQ u;
+                // dL/dSigma2 = -(2 ln 2)^2 sum dQ u u^T, its two off-diagonal
+                // entries together in slot 3
+                if (q < 2) sum *= -2.f * k2ln2;
+                else if (q == 3) sum *= -2.f * k2ln2sq;
+                else if (q < 5) sum *= -k2ln2sq;
                 b.slots[(size_t)e * NV + q] = sum;
             }
             if (q == 0) b.touched[e] = t ? 1 : 0;
@@ -598,19 +664,8 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
         for (int r = 0; r < 2; r++)
             for (int c = 0; c < 3; c++)
                 TS3[3 * r + c] = T[3 * r] * S3[c] + T[3 * r + 1] * S3[3 + c] + T[3 * r + 2] * S3[6 + c];
-        double S2[4];
-        for (int r = 0; r < 2; r++)
-            for (int c = 0; c < 2; c++)
-                S2[2 * r + c] = TS3[3 * r] * T[3 * c] + TS3[3 * r + 1] * T[3 * c + 1] + TS3[3 * r + 2] * T[3 * c + 2];
-        const double sxx = S2[0] + a.lowpass, sxy = 0.5 * (S2[1] + S2[2]), syy = S2[3] + a.lowpass;
-        const double det = sxx * syy - sxy * sxy;
-        const double A[4] = {syy / det, -sxy / det, -sxy / det, sxx / det};
-        const double dA[4] = {d2[2], 0.5 * d2[3], 0.5 * d2[3], d2[4]};
-        double tmp[4], dS2[4];
-        for (int r = 0; r < 2; r++)
-            for (int c = 0; c < 2; c++) tmp[2 * r + c] = A[2 * r] * dA[c] + A[2 * r + 1] * dA[2 + c];
-        for (int r = 0; r < 2; r++)
-            for (int c = 0; c < 2; c++) dS2[2 * r + c] = -(tmp[2 * r] * A[c] + tmp[2 * r + 1] * A[2 + c]);
+        // the slots carry dL/dSigma2 itself (the low-pass term is a constant)
+        const double dS2[4] = {d2[2], 0.5 * d2[3], 0.5 * d2[3], d2[4]};
         for (int r = 0; r < 3; r++)
             for (int c = 0; c < 3; c++)
                 dS3[3 * r + c] += T[r] * (dS2[0] * T[c] + dS2[1] * T[3 + c]) + T[3 + r] * (dS2[2] * T[c] + dS2[3] * T[3 + c]);
@@ -684,8 +739,11 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
 
 // ------------------------------------------------------------------ launcher
 
-static size_t bwd_lds_bytes(int C, int k, int kpad, bool sparse) {
-    size_t b = (size_t)kBwdBatch * (4 * sizeof(float4) + sizeof(uint32_t) + k * sizeof(float) + kpad);
+static size_t bwd_lds_bytes(int C, int k, int kpad, bool sparse, bool ranked) {
+    size_t b = (size_t)kBwdBatch * (4 * sizeof(float4) + sizeof(uint32_t) + kpad);
+    // the top-k values (not kept by the ranked kernel), or the class rank
+    // tables: four (mask word, classes below) pairs and the position nibbles
+    b += ranked ? (size_t)kBwdBatch * 5 * sizeof(uint2) : (size_t)kBwdBatch * k * sizeof(float);
     b += (size_t)kBwdWaves * kBwdBatch * (10 + k) * sizeof(float) + kBwdWaves * kBwdBatch * sizeof(uint32_t);
     if (!sparse) b += (size_t)acc_floats(C) * sizeof(float);
     return b;
@@ -697,10 +755,10 @@ static void set_lds_b(K kernel, size_t bytes) {
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int KT, bool SPARSE>
+template <int KT, bool SPARSE, bool RANKED = false>
 static void bwd_launch(const BwdArgs& b, unsigned grid, size_t lds, hipStream_t st) {
-    set_lds_b(render_bwd_kernel<KT, SPARSE>, lds);
-    render_bwd_kernel<KT, SPARSE><<<grid, kBwdThreads, lds, st>>>(b);
+    set_lds_b(render_bwd_kernel<KT, SPARSE, RANKED>, lds);
+    render_bwd_kernel<KT, SPARSE, RANKED><<<grid, kBwdThreads, lds, st>>>(b);
 }
 
 sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* ws, hipStream_t st) {
@@ -719,11 +777,16 @@ sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* w
     b.svals = (const uint32_t*)(ws + P.sorted_vals);
     b.nvals = 10 + P.k;
     b.semgeo = P.cfg.sem_grad_to_geometry;
-    const size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad, sparse);
+    // one-class semantic gradient kept off geometry, k = 16, C <= 128: the
+    // label's list position comes from the class rank tables
+    const bool ranked = sparse && P.ranked && !b.semgeo;
+    const size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad, sparse, ranked);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
     if (P.k == 16) {
-        if (sparse) bwd_launch<16, true>(b, grid, lds, st); else bwd_launch<16, false>(b, grid, lds, st);
+        if (ranked) bwd_launch<16, true, true>(b, grid, lds, st);
+        else if (sparse) bwd_launch<16, true>(b, grid, lds, st);
+        else bwd_launch<16, false>(b, grid, lds, st);
     } else if (P.k == 3) {
         if (sparse) bwd_launch<3, true>(b, grid, lds, st); else bwd_launch<3, false>(b, grid, lds, st);
     } else {

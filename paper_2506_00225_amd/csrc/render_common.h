@@ -118,6 +118,7 @@ struct TileArgs {
     const float4* scol;
     const float* ssv;
     const uint8_t* ssi;
+    const uint32_t* srk;  // class-rank table [vis][kRankWords] (k = 16, C <= 128), or nullptr
     uint32_t* counters;
     float* pix_T;
     uint32_t* pix_last;
@@ -179,6 +180,22 @@ __device__ __forceinline__ float eval_alpha(const float4& q0, const float4& q1, 
     *G = g;
     *dx = ddx;
     *dy = ddy;
+    return fminf(amax, q1.w * g);
+}
+
+// eval_alpha that also returns u = dx + cb dy (the backward's whitened
+// offsets start from it).
+__device__ __forceinline__ float eval_alpha_u(const float4& q0, const float4& q1, int px, int py, float amax,
+                                              float* G, float* dx, float* dy, float* u) {
+    const float ddx = (float)(px - __float_as_int(q0.x)) + q0.z;
+    const float ddy = (float)(py - __float_as_int(q0.y)) + q0.w;
+    const float uu = fmaf(q1.y, ddy, ddx);
+    const float e = fmaf(q1.x * uu, uu, q1.z * ddy * ddy);
+    const float g = __builtin_amdgcn_exp2f(-e);  // v_exp_f32; e >= 0 here
+    *G = g;
+    *dx = ddx;
+    *dy = ddy;
+    *u = uu;
     return fminf(amax, q1.w * g);
 }
 

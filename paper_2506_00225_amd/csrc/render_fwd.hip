@@ -933,6 +933,7 @@ TileArgs make_tile_args(const Plan& P, char* ws) {
     a.scol = (const float4*)(ws + P.scol);
     a.ssv = (const float*)(ws + P.ssv);
     a.ssi = (const uint8_t*)(ws + P.ssi);
+    a.srk = P.ranked ? (const uint32_t*)(ws + P.srk) : nullptr;
     a.counters = (uint32_t*)(ws + P.counters);
     a.pix_T = (float*)(ws + P.pix_T);
     a.pix_last = (uint32_t*)(ws + P.pix_last);

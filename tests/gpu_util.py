@@ -190,21 +190,11 @@ def tainted_gaussians(proj, flags):
     return bad
 
 
-def compare_grads(got: dict, want: dict, exclude: np.ndarray, rtol=1e-3, visible=None, max_excluded=0.01,
-                  magnitude: dict | None = None, cond=64 * 2.0 ** -24):
+def compare_grads(got: dict, want: dict, exclude: np.ndarray, rtol=1e-3, visible=None, max_excluded=0.01):
     """Per parameter tensor: relative L2 error over all Gaussians <= rtol, and
     element-wise |d| <= rtol |ref| + rtol rms(ref) on every Gaussian but the
     excluded ones (those covering a flagged pixel whose outcome could not be
-    resolved), which may be at most max_excluded of the visible ones.
-
-    `magnitude` (optional): the oracle's gradient for |dL/dmaps| in place of
-    dL/dmaps.  A gradient summed over a large footprint from per-pixel terms
-    of random sign can be a small residual of large terms, which no float32
-    summation can give to 1e-3 of itself; the element-wise bar then also
-    allows cond * |magnitude| (cond = 64 float32 unit roundoffs, the depth of
-    the kernels' per-tile, per-wave and per-Gaussian sums).  Where the terms
-    do not cancel that term is below 4e-6 |ref|, far under the 1e-3 bar.  The
-    report counts the Gaussians whose check needed it ("cond_limited")."""
+    resolved), which may be at most max_excluded of the visible ones."""
     keep = ~exclude
     report = {"excluded": int(exclude.sum())}
     if visible is not None:
@@ -218,12 +208,8 @@ def compare_grads(got: dict, want: dict, exclude: np.ndarray, rtol=1e-3, visible
         nrm = float(np.linalg.norm(dall) / (np.linalg.norm(ref) + 1e-30))
         d, r = dall[keep], ref[keep]
         rms = float(np.sqrt(np.mean(ref * ref))) + 1e-30
-        base = rtol * np.abs(r) + rtol * rms
-        tol = base if magnitude is None else base + cond * np.abs(magnitude[name][keep])
-        worst = float(np.max(np.abs(d) - tol)) if d.size else -1.0
+        worst = float(np.max(np.abs(d) - rtol * np.abs(r) - rtol * rms)) if d.size else -1.0
         report[name] = (nrm, worst)
-        if magnitude is not None:
-            report[name + "_cond_limited"] = int(np.count_nonzero(np.abs(d) > base))
         assert nrm <= rtol, (name, report)
         assert worst <= 0, (name, report)
     return report

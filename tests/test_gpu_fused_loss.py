@@ -129,10 +129,25 @@ def test_fused_loss_per_view_values_multiview():
             assert torch.equal(fr.split(grads[key])[v].reshape(-1), g1[key].reshape(-1)), (v, key)
 
 
+def _same_sem_grad(dense_g, sparse_g, mag):
+    """Top-k value gradients of the one-class kernel against the dense one.
+    With the semantic loss kept off geometry (k = 16, C <= 128) the one-class
+    kernel sums each key's semantic values in per-wave LDS bins, lane by
+    lane, where the dense kernel sums them in a tree over the wave: the same
+    terms in another order, so equal to float32 summation error, at most 64
+    unit roundoffs of the sum of the terms' magnitudes (`mag`, the same
+    gradient for |dL/dsem|)."""
+    d = (dense_g.double() - sparse_g.double()).abs()
+    bound = 64 * 2.0 ** -24 * mag.double().abs() + 1e-30
+    assert bool((d <= bound).all()), (float((d - bound).max()), int((d > bound).sum()))
+
+
 def test_sparse_semantic_gradient_equals_dense():
     """One (class, value) per pixel in registers gives the bits of the same
-    gradient written out densely and staged in LDS; the fused loss's sparse
-    output gives the bits of its dense output."""
+    gradient written out densely and staged in LDS (the top-k value
+    gradients of the ranked one-class kernel to float32 summation order, see
+    _same_sem_grad); the fused loss's sparse output gives the bits of its
+    dense output."""
     _say("sparse semantic gradient")
     sc = _scene(n=50_000, w=320, h=240)
     cam = sc.cameras[0]
@@ -151,10 +166,14 @@ def test_sparse_semantic_gradient_equals_dense():
         base = {"rgb": torch.randn(P, 3, device="cuda"), "depth": torch.randn(P, device="cuda"),
                 "sil": torch.randn(P, device="cuda")}
         gd = {k: v.clone() for k, v in fr.backward(g, dict(base, sem=torch.from_numpy(dense).cuda())).items()}
+        mag = fr.backward(g, dict(base, sem=torch.from_numpy(np.abs(dense)).cuda()))["sem_val"].clone()
         gs = fr.backward(g, dict(base, sem_label=torch.from_numpy(lab).cuda(), sem_at_label=torch.from_numpy(val).cuda()))
         torch.cuda.synchronize()
         for k in gd:
-            assert torch.equal(gd[k], gs[k]), (semgeo, k)
+            if k == "sem_val" and semgeo == 0:
+                _same_sem_grad(gd[k], gs[k], mag)
+            else:
+                assert torch.equal(gd[k], gs[k]), (semgeo, k)
     # fused loss: sparse output == dense output, and the backward agrees bitwise
     tg = _targets(rng, P, C, "label", sc.k)
     fr = U.frame_for(sc)
@@ -162,6 +181,7 @@ def test_sparse_semantic_gradient_equals_dense():
     tt = {kk: torch.from_numpy(v) for kk, v in tg.items()}
     gdn, l1 = fr.forward_loss(g, tt)
     ref = {k: v.clone() for k, v in fr.backward(g, dict(gdn)).items()}
+    mag = fr.backward(g, dict(gdn, sem=gdn["sem"].abs()))["sem_val"].clone()
     gsp, l2 = fr.forward_loss(g, tt, sparse_sem=True)
     got = fr.backward(g, dict(gsp))
     torch.cuda.synchronize()
@@ -169,7 +189,10 @@ def test_sparse_semantic_gradient_equals_dense():
     lab = torch.from_numpy(tg["label"]).cuda().long()
     assert torch.equal(gdn["sem"].gather(1, lab[:, None])[:, 0], gsp["sem_at_label"])
     for k in ref:
-        assert torch.equal(ref[k], got[k]), k
+        if k == "sem_val":
+            _same_sem_grad(ref[k], got[k], mag)
+        else:
+            assert torch.equal(ref[k], got[k]), k
 
 
 def test_label_only_lookup_with_repeated_classes():

@@ -121,11 +121,10 @@ def test_benchmarked_mapping_step_1m():
 def test_large_scene_two_portrait_keyframes():
     """Two 1024x1280 keyframes of the 3M-Gaussian multi-room scene (C = 40)
     in one batch, forward and backward: each view's maps against the oracle
-    and the gradients against the sum of the per-view oracle gradients.
-    With random-sign dL/dmaps, Gaussians near the camera (footprints up to
-    the whole 1.3M-pixel view) have gradients that are residuals of terms up
-    to 2e5 times larger, so the element-wise bar carries the float32
-    conditioning term of compare_grads."""
+    and the gradients against the sum of the per-view oracle gradients,
+    element-wise on every visible Gaussian (Gaussians near the camera cover
+    up to the whole 1.3M-pixel view, thin ones have conics of condition
+    number in the thousands)."""
     _say("large scene 3M, 2 x 1024x1280, C=40")
     sc = scenes.large_scene()
     cams = sc.cameras[:2]
@@ -143,7 +142,7 @@ def test_large_scene_two_portrait_keyframes():
     torch.cuda.synchronize()
     assert fr.status()[0] == 0
     got = {kk: U.to_np(v) for kk, v in out.items()}
-    want, mag, bad, vis = None, None, np.zeros(sc.n, bool), np.zeros(sc.n, bool)
+    want, bad, vis = None, np.zeros(sc.n, bool), np.zeros(sc.n, bool)
     reps = []
     for v, (c, dl) in enumerate(zip(cams, dls)):
         view = U.OracleView.of_scene(sc, cam=c)
@@ -151,10 +150,7 @@ def test_large_scene_two_portrait_keyframes():
         assert rep["unresolved"] == 0, rep
         reps.append(rep)
         gv = view.backward(dl)
-        # the same gradient for |dL/dmaps|: the size of the terms each sum cancels
-        gm = view.backward({kk: np.abs(x) for kk, x in dl.items()})
         want = gv if want is None else {kk: want[kk] + gv[kk] for kk in want}
-        mag = gm if mag is None else {kk: mag[kk] + gm[kk] for kk in mag}
         bad |= view.excluded()
         vis |= view.pr["visible"] == 1
-    print("large scene report", reps, U.compare_grads(got, want, bad, visible=vis, magnitude=mag), flush=True)
+    print("large scene report", reps, U.compare_grads(got, want, bad, visible=vis), flush=True)
