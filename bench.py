@@ -28,8 +28,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd ms/iter & Gaussian-pixel blends/s @1M G 1200x680; views/s"
 HBM_PEAK_GBS = 8000.0
-# fp32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed pair) x 2 flops (FMA) x 2.4 GHz
+# fp32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed pair) x 2 flops (FMA) x 2.4 GHz; the HIP
+# code here is built without packed fp32, which halves what it can reach
 FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_TFLOPS = 78.6
+# Algorithmic fp32 flops per blend (an FMA counts as 2, exp2 and rcp as 1):
+#   evaluation of a blended pair: offset 2, u = dx + cb dy 2, exponent ca u^2 + cc dy^2 5, exp2 1,
+#     alpha = min(alpha_max, o G) 2                                                          = 12
+#   forward blend: w = alpha T 1, T (1 - alpha) 2, colour 6, depth 2, silhouette 1, the label's
+#     class sum 2                                                                             = 14
+#   backward blend (one-class semantic gradient): T in front 3, w 1, e over the channels 8,
+#     dL/dalpha 3, suffix sum 2, dL/dQ and dL/do 3, whitened offset 4, its products 5, colour
+#     and depth terms 4, semantic term 1, the per-key sums of the 11 values 11              = 45
+FLOPS_PER_BLEND = {"fwd": 12 + 14, "bwd_tiles": 12 + 45}
 
 
 def parse():
@@ -45,6 +56,12 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain streaming kernel over this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--no-mapping", action="store_true",
+                    help="skip the mapping leg (then only the other legs' results are printed; for profiling them)")
+    ap.add_argument("--no-plan", action="store_true", help="skip the planning leg")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-vs-sparse leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the legs of the other workloads (64x64 forward, 200k fwd+bwd, 3M large scene)")
     return ap.parse_args()
 
 
@@ -208,16 +225,13 @@ def roofline(out):
     """Roofline of the stage with the longest HIP-event time.
 
     The compositing stages are bound by vector ALU issue, not HBM, so they
-    are reported against the fp32 vector peak with the algorithmic
-    operation count per blend (B blends per launch, the same B as the
-    oracle's): per evaluation of a blended pair 12 fp32 operations and one
-    exponential; per forward blend 6 + k accumulations; per backward blend
-    40 + 3k operations (transmittance, dL/dalpha over the channels, the
-    colour, opacity, conic and mean terms and the top-k semantic terms).
-    An FMA counts as one operation, so the figure is a lower bound.
-    Their algorithmic bytes (every input read once, every output and
-    compulsory intermediate written once) are reported beside it.  Other
-    stages are HBM-bound and reported against the HBM peak."""
+    are reported against the fp32 vector peak with the algorithmic flops
+    per blend of FLOPS_PER_BLEND (an FMA counts as 2; B blends per launch,
+    the same B as the oracle's), and beside it against the unpacked fp32
+    ceiling the code is built for.  Their algorithmic bytes (every input
+    read once, every output and compulsory intermediate written once) are
+    reported beside it.  Other stages are HBM-bound and reported against
+    the HBM peak."""
     P, C, k, K, Nv, n = out["pixels"], out["C"], out["k"], out["keys"], out["nvis"], out["n"]
     B = out["blends"]
     rec = 48 + 16 + 4 * k + ((k + 3) // 4) * 4  # projected record + rgb/z + top-k values + indices
@@ -235,7 +249,7 @@ def roofline(out):
         # read 2D gradients and parameters once; write per-Gaussian gradients once
         "bwd_gather": g2d * Nv + 44 * n + (14 + k) * 4 * n,
     }
-    ops_per_blend = {"fwd": 13 + 6 + k, "bwd_tiles": 13 + 40 + 3 * k}
+    ops_per_blend = FLOPS_PER_BLEND
     stage = out["stage_ms"]
     dom = max(alg, key=lambda s: stage[s])
     sec = stage[dom] * 1e-3
@@ -247,10 +261,36 @@ def roofline(out):
         tf = flops / sec / 1e12
         return dom, {"bound": "alu", "achieved": round(tf, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(tf / FP32_PEAK_TFLOPS, 4), **common, "alg_flops": int(flops),
-                     "ops_per_blend": ops_per_blend[dom], "hbm_gbs": round(gbs, 2),
+                     "flops_per_blend": ops_per_blend[dom], "peak_unpacked": FP32_UNPACKED_TFLOPS,
+                     "frac_unpacked": round(tf / FP32_UNPACKED_TFLOPS, 4), "hbm_gbs": round(gbs, 2),
                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     return dom, {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(gbs / HBM_PEAK_GBS, 4), **common}
+
+
+def hbm_path(out):
+    """Forward + backward of the mapping iteration (proj, bin, fwd, bwd_tiles,
+    bwd_gather) against the HBM roofline, with two byte counts:
+    * the compulsory-byte formula of the hot-path scope (every input read
+      once, every output and intermediate written once and read once, the
+      dense C-class maps and their gradients included), with the measured
+      key count K and visible pairs N_v;
+    * this path's own algorithmic bytes (the fused loss keeps the class maps
+      and their gradients on chip), the sum of the per-stage figures."""
+    P, C, k, K, Nv, n = out["pixels"], out["C"], out["k"], out["keys"], out["nvis"], out["n"]
+    b_fwd = 44 * n + 36 * n + 8 * n + 36 * K + 4 * K + (36 + 12 + 5 * k) * Nv + P * (5 + C) * 4 + 8 * P
+    b_bwd = P * (5 + C) * 4 + 8 * P + 4 * K + (48 + 5 * k) * Nv + (40 + 4 * k) * n + 72 * n + 44 * n
+    rec = 48 + 16 + 4 * k + ((k + 3) // 4) * 4
+    g2d = (10 + k) * 4
+    fused = (44 * n + 8 * n + 12 * Nv) + (12 * K * 3 + 8 * Nv) + (rec * Nv + 4 * K + 20 * P + 6 * 4 * P + 12 * P) + \
+            (7 * 4 * P + 8 * P + 4 * K + rec * Nv + g2d * Nv) + (g2d * Nv + 44 * n + (14 + k) * 4 * n)
+    sec = out["fwd_bwd_ms"] * 1e-3
+    return {"fwd_bwd_ms": round(out["fwd_bwd_ms"], 4),
+            "scope_formula_bytes": int(b_fwd + b_bwd), "scope_formula_gbs": round((b_fwd + b_bwd) / sec / 1e9, 1),
+            "scope_formula_frac": round((b_fwd + b_bwd) / sec / 1e9 / HBM_PEAK_GBS, 4),
+            "fused_path_bytes": int(fused), "fused_path_gbs": round(fused / sec / 1e9, 1),
+            "fused_path_frac": round(fused / sec / 1e9 / HBM_PEAK_GBS, 4),
+            "target_ms_at_half_peak": round((b_fwd + b_bwd) / (0.5 * HBM_PEAK_GBS * 1e9) * 1e3, 4)}
 
 
 def score_bench(args, torch, out):
@@ -404,7 +444,117 @@ def dense_bench(args, torch, out):
     out["dense_vs_sparse"] = res
 
 
-def cpu_baseline(sc, rows=None):
+def _sized_frame(torch, sc, cams, slack=1.3):
+    """A frame whose key capacity is the measured key count times slack."""
+    from paper_2506_00225_amd import Frame, Gaussians, make_config
+    g = Gaussians.from_scene(sc)
+    fr = Frame(sc.n, cams, make_config(sc.num_classes, sc.k))
+    fr.prepare(g, check=True)
+    _, _, nk = fr.status()
+    fr.key_capacity = int(nk * slack) + 4096
+    fr._alloc()
+    fr.prepare(g, check=True)
+    return g, fr
+
+
+def _l1_step(torch, fr, g, maps, t_rgb, t_depth, onehot):
+    """project, bin, forward (every map), the gradient of the mean L1 loss
+    of each map (rgb, depth, silhouette against 1, semantics against the
+    one-hot label), backward; returns the per-Gaussian gradients."""
+    fr.project(g)
+    fr.bin(g)
+    fr.forward(g, maps)
+    P = maps["depth"].numel()
+    grads = {"rgb": torch.sign(maps["rgb"] - t_rgb) / (3 * P), "depth": torch.sign(maps["depth"] - t_depth) / P,
+             "sil": torch.sign(maps["sil"] - 1.0) / P, "sem": torch.sign(maps["sem"] - onehot) / onehot.numel()}
+    return fr.backward(g, grads)
+
+
+def _time(torch, fn, reps):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def config_legs(args, torch, out):
+    """The other workloads, one line each:
+    * 64x64 forward: 2,000 Gaussians, C = 16, k = 3 (project, bin, forward
+      with every map);
+    * 200k fwd+bwd: 200k room Gaussians at 1200x680, C = 102, k = 16, the
+      mean L1 loss of each map (its gradient computed by torch between the
+      two library calls, inside the timed step);
+    * large scene: 3M Gaussians, C = 40, 8 keyframes at 1024x1280 rendered
+      forward and backward in one batch (gradients summed per Gaussian, L1
+      loss as above), then 128 candidate views at 320x240 scored in batches
+      of 16 views."""
+    from paper_2506_00225_amd import scenes
+    res = {}
+    # 64x64 forward
+    sc = scenes.tiny_scene()
+    g, fr = _sized_frame(torch, sc, sc.cameras)
+    maps = fr.alloc_maps()
+
+    def fwd0():
+        fr.project(g)
+        fr.bin(g)
+        fr.forward(g, maps)
+    ms = _time(torch, fwd0, 200)
+    B = int(maps["n_contrib"].sum())
+    res["forward_64x64_2k"] = {"ms": round(ms, 4), "blends": B, "blends_per_s": round(B / (ms * 1e-3), 1)}
+    log("config 64x64", json.dumps(res["forward_64x64_2k"]))
+    # 200k fwd+bwd with the L1 loss
+    for name, sc, ncams in (("fwd_bwd_200k_1200x680", scenes.room_scene(n=200_000), 1),
+                            ("large_3m_8x1024x1280", scenes.large_scene(), 8)):
+        cams = sc.cameras[:ncams]
+        g, fr = _sized_frame(torch, sc, cams)
+        maps = fr.alloc_maps()
+        dev = g.means.device
+        if ncams == 1:
+            tr = {k_: torch.from_numpy(v).to(dev) for k_, v in sc.targets.items()}
+        else:
+            rng = np.random.default_rng(1)
+            tl = [scenes.l1_targets(rng, c, sc.num_classes) for c in cams]
+            tr = {k_: torch.from_numpy(np.concatenate([t[k_].reshape(c.width * c.height, -1) for t, c in zip(tl, cams)])
+                                       ).to(dev).squeeze(-1) for k_ in ("rgb", "depth", "label")}
+        P = fr.pix_off[-1]
+        t_rgb, t_depth = tr["rgb"].reshape(P, 3), tr["depth"].reshape(P)
+        onehot = torch.nn.functional.one_hot(tr["label"].reshape(P).long(), sc.num_classes).float()
+        step = lambda: _l1_step(torch, fr, g, maps, t_rgb, t_depth, onehot)
+        ms = _time(torch, step, 10 if ncams == 1 else 3)
+        st, nvis, nk = fr.status()
+        assert st == 0, st
+        B = int(maps["n_contrib"].sum())
+        r = {"views": ncams, "gaussians": sc.n, "classes": sc.num_classes, "ms": round(ms, 4), "blends": B,
+             "blends_per_s": round(B / (ms * 1e-3), 1), "keys": nk, "visible": nvis}
+        del maps, onehot, fr
+        if ncams > 1:
+            # candidate scoring from device poses, in launches of 16 views (the
+            # planner's chunked path; a status read after each launch)
+            from paper_2506_00225_amd import make_config
+            from paper_2506_00225_amd.planner import Grid, Planner
+            cands = sc.candidates
+            pl = Planner(Grid((1, 1, 1), 1.0, (0.0, 0.0, 0.0)), cands[0], make_config(sc.num_classes, sc.k),
+                         capacity=len(cands), chunk=16)
+            poses = np.stack([np.concatenate([np.asarray(c.R, np.float32).reshape(9),
+                                              np.asarray(c.t, np.float32).reshape(3)]) for c in cands])
+            pl.poses[:len(cands)].copy_(torch.from_numpy(poses))
+            sms = _time(torch, lambda: pl.score_views(g, len(cands)), 3)
+            r.update({"candidates": len(cands), "score_ms": round(sms, 3),
+                      "views_per_s": round(len(cands) / (sms * 1e-3), 1)})
+            del pl
+        res[name] = r
+        log("config", name, json.dumps(r))
+        torch.cuda.empty_cache()
+    out["configs"] = res
+
+
+def cpu_baseline(sc, rows=None, min_s=10.0):
     """The FP64 oracle (as it stands) on the same keyframe and the same 1M
     Gaussians: projection of all Gaussians, forward render and analytic
     backward of `rows` image rows through the middle (all of them by
@@ -422,7 +572,7 @@ def cpu_baseline(sc, rows=None):
              "sem": rng.standard_normal((rows, cam.width, sc.num_classes))}
     # repeat the whole fwd+bwd until about 10 s of host work (at most 16 times)
     reps, t = 0, 0.0
-    while reps < 16 and (reps == 0 or t < 10.0):
+    while reps < 16 and (reps == 0 or t < min_s):
         t0 = time.perf_counter()
         pr, mp = O.forward(O.scene_arrays(sc), band, cfg, sc.num_classes)
         O.backward(O.scene_arrays(sc), band, cfg, sc.num_classes, grads, proj=pr)
@@ -434,6 +584,36 @@ def cpu_baseline(sc, rows=None):
             "sample": (f"{reps} x fwd+bwd of the full {cam.width}x{rows} keyframe" if rows == cam.height else
                        f"{reps} x fwd+bwd of a {cam.width}x{rows} band through the keyframe centre") +
                       f", all {sc.n} Gaussians projected each time; {B} blends in {t:.2f} s"}
+
+
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline_one_thread(n, rows):
+    """The same oracle pass on one host thread (a child process with
+    OMP_NUM_THREADS=1: the thread count of the oracle's OpenMP runtime is
+    fixed when it starts), over a band of `rows` rows."""
+    import subprocess
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; from paper_2506_00225_amd import scenes; "
+            "print(json.dumps(bench.cpu_baseline(scenes.room_scene(n=%d, targets=False), rows=%d, min_s=0.0)))"
+            % (ROOT, n, rows))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        log("one-thread oracle failed", r.stderr[-500:])
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
@@ -448,11 +628,20 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     out = {}
+    if args.no_mapping:
+        if not args.no_score:
+            score_bench(args, torch, out)
+        print(json.dumps({k: v for k, v in out.items() if not k.startswith("autotune")}), flush=True)
+        return
     sc = mapping_bench(args, torch, out)
     if not args.no_score:
         score_bench(args, torch, out)
-        plan_bench(args, torch, out)
-        dense_bench(args, torch, out)
+        if not args.no_plan:
+            plan_bench(args, torch, out)
+        if not args.no_dense:
+            dense_bench(args, torch, out)
+    if not args.no_configs:
+        config_legs(args, torch, out)
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         src = torch.ones(n, device="cuda")
@@ -465,6 +654,11 @@ def main():
     if not args.no_cpu:
         log("cpu baseline")
         cpu = cpu_baseline(sc)
+        cpu.update(cpu_info())
+        log("cpu baseline, one thread")
+        one = cpu_baseline_one_thread(sc.n, rows=68)
+        if one is not None:
+            cpu["one_thread"] = {"value": one["value"], "unit": one["unit"], "sample": one["sample"]}
     dom, roof = roofline(out)
     value = out["blends"] / (out["step_ms"] * 1e-3)
     line = {
@@ -483,11 +677,13 @@ def main():
         "stage_ms": {k_: round(v, 4) for k_, v in out["stage_ms"].items()},
         "loss_first_last": out["loss_first_last"],
         "roofline": roof,
+        "hbm_fwd_bwd": hbm_path(out),
         "cpu_baseline": cpu,
     }
     for key in ("views_per_s_batched", "views_per_s_graph", "views_per_s_plain", "score_batched_ms", "score_graph_ms",
                 "score_graph_equal", "score_plain_ms",
-                "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views", "plan", "dense_vs_sparse"):
+                "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views", "plan", "dense_vs_sparse",
+                "configs"):
         if key in out:
             line[key] = out[key]
     tuned = {k: out[k]["chosen"] for k in ("autotune_mapping", "autotune_score") if k in out and "chosen" in out[k]}

@@ -89,6 +89,12 @@ typedef struct {
                                      class-sum LDS, so more fit on a CU).  Speed only.  The fused
                                      loss uses one pass whenever a view has a dense semantic
                                      target or asks for the dense semantic gradient. */
+    int32_t bwd_batch;            /* keys the backward stages per batch (k = 16 only): 0 = 44,
+                                     or 32, 44, 56 (less LDS per workgroup, so more of them
+                                     per CU, against more barriers per key).  Speed only. */
+    int32_t radix_bits;           /* widest digit of the radix sorts: 0 = 8, or 6 or 8 (the
+                                     key bits are spread evenly over the passes this needs).
+                                     Speed only: the sorts are stable, so the order is the same. */
 } sgr_config;
 
 enum { SGR_ACC_AUTO = 0, SGR_ACC_LDS = 1, SGR_ACC_REGISTERS = 2 };

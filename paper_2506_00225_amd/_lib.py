@@ -31,7 +31,8 @@ class sgr_config(ctypes.Structure):
                 ("z_near", ctypes.c_float), ("lowpass", ctypes.c_float), ("num_classes", ctypes.c_int32),
                 ("top_k", ctypes.c_int32), ("sem_grad_to_geometry", ctypes.c_int32), ("tile_w", ctypes.c_int32),
                 ("tile_h", ctypes.c_int32), ("sem_accumulators", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("score_workgroups", ctypes.c_int32), ("sem_passes", ctypes.c_int32)]
+                ("score_workgroups", ctypes.c_int32), ("sem_passes", ctypes.c_int32), ("bwd_batch", ctypes.c_int32),
+                ("radix_bits", ctypes.c_int32)]
 
 
 SGR_ACC_AUTO, SGR_ACC_LDS, SGR_ACC_REGISTERS = 0, 1, 2

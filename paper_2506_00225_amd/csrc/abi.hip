@@ -34,6 +34,9 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     if (cfg->tile_order < SGR_TILES_AUTO || cfg->tile_order > SGR_TILES_LINEAR || cfg->score_workgroups < 0)
         return SGR_EINVAL;
     if (cfg->sem_passes < 0 || cfg->sem_passes > kMaxPasses) return SGR_EINVAL;
+    if (cfg->bwd_batch != 0 && cfg->bwd_batch != 32 && cfg->bwd_batch != 44 && cfg->bwd_batch != 56)
+        return SGR_EINVAL;
+    if (cfg->radix_bits != 0 && cfg->radix_bits != 6 && cfg->radix_bits != 8) return SGR_EINVAL;
     const int64_t vn = n * (int64_t)V;
     if (vn >= (int64_t)1 << 31 || cap >= (int64_t)1 << 31) return SGR_EINVAL;
     P->n = n;
@@ -68,7 +71,8 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     int bits = 1;
     while (((int64_t)1 << bits) < tiles) bits++;
     P->tile_bits = bits;
-    P->tile_passes = (bits + 7) / 8;
+    P->radix_bits = cfg->radix_bits > 0 ? cfg->radix_bits : 8;
+    P->tile_passes = radix_passes(bits, P->radix_bits);
 
     const int NV = 10 + P->k;
     const size_t vns = (size_t)vn, caps = (size_t)cap;
@@ -95,6 +99,7 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     P->scol = take(16 * vns);
     P->ssv = take(4 * (size_t)P->k * vns);
     P->ssi = take((size_t)P->kpad * vns);
+    P->sorig = take((size_t)P->kpad * vns);
     P->ranked = P->k == 16 && P->C <= 128;
     if (P->ranked) P->srk = take(4 * (size_t)kRankWords * vns);
     P->tcount = take(4 * vns);

@@ -270,11 +270,12 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
             if (q < m && m < k) dup |= cls[q] == cls[m];
     // store grouped by accumulator block
     float vout[KM];
-    uint32_t cout[KM];
+    uint32_t cout[KM], oout[KM];
 #pragma unroll
     for (int p = 0; p < KM; p++) {
         vout[p] = 0.f;
         cout[p] = 0u;
+        oout[p] = 0u;
     }
 #pragma unroll
     for (int m = 0; m < KM; m++) {
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
             if (p == pos) {
                 vout[p] = vin[m];
                 cout[p] = cls[m];
+                oout[p] = (uint32_t)m;
             }
     }
     float* dv = a.ssv + (size_t)g * k;
@@ -302,6 +304,17 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
             if (4 * w + b < KM) word |= cout[4 * w + b] << (8 * b);
         if (w < kw) di[w] = word;
     }
+    // the list index each stored position came from (the projection
+    // backward writes the top-k value gradients back in list order)
+    uint32_t* dorig = (uint32_t*)(a.sorig + (size_t)g * a.kpad);
+#pragma unroll
+    for (int w = 0; w < KWM; w++) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+            if (4 * w + b < KM) word |= oout[4 * w + b] << (8 * b);
+        if (w < kw) dorig[w] = word;
+    }
     if constexpr (KT == 16) {
         if (a.srk) {
             // class-rank table of the stored list (classes < 128 here)
@@ -314,7 +327,6 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
             }
             const uint32_t n0 = __builtin_popcount(mk[0]), n1 = n0 + __builtin_popcount(mk[1]),
                            n2 = n1 + __builtin_popcount(mk[2]);
-            const uint32_t below = (n0 << 8) | (n1 << 16) | (n2 << 24);
             uint64_t perm = 0;
 #pragma unroll
             for (int q = 0; q < 16; q++) {
@@ -326,7 +338,7 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
             }
             uint4* dst = (uint4*)(a.srk + (size_t)g * kRankWords);
             dst[0] = make_uint4(mk[0], mk[1], mk[2], mk[3]);
-            dst[1] = make_uint4(below, (uint32_t)perm, (uint32_t)(perm >> 32), 0u);
+            dst[1] = make_uint4((uint32_t)perm, (uint32_t)(perm >> 32), 0u, 0u);
         }
     }
     if (bad) atomicOr(&a.counters[kStatus], Plan::kBadIndex);
@@ -468,14 +480,17 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
     }
     const int passes = radix_sort((uint32_t*)(ws + P.vis_k0), (uint32_t*)(ws + P.vis_v0), (uint32_t*)(ws + P.vis_k1),
                                   (uint32_t*)(ws + P.vis_v1), false, device_count(counters + kNumVisible, 0),
-                                  (uint32_t)P.vn, 32, (uint32_t*)(ws + P.hist), partial, st);
-    (void)passes;  // 4 passes: the result is back in the *0 buffers (P.order)
+                                  (uint32_t)P.vn, 32, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits);
+    // 32 bits in 4 (8-bit digits) or 6 (6-bit digits) passes: the result is
+    // back in the *0 buffers (P.order)
+    if (passes & 1) return SGR_EUNSUPPORTED;
     GatherArgs ga;
     ga.order = (const uint32_t*)(ws + P.order); ga.proj = pa; ga.count = pa.count;
     ga.rgb = g->rgb; ga.sem_val = g->sem_val; ga.sem_idx = g->sem_idx;
     ga.n = P.n; ga.k = P.k; ga.kpad = P.kpad; ga.C = P.C; ga.counters = counters;
     ga.srec = (Proj*)(ws + P.srec); ga.scol = (float4*)(ws + P.scol); ga.ssv = (float*)(ws + P.ssv);
-    ga.ssi = (uint8_t*)(ws + P.ssi); ga.srk = P.ranked ? (uint32_t*)(ws + P.srk) : nullptr; ga.tcount = (uint32_t*)(ws + P.tcount); ga.gp_of_lin = pa.gp_of_lin;
+    ga.ssi = (uint8_t*)(ws + P.ssi); ga.srk = P.ranked ? (uint32_t*)(ws + P.srk) : nullptr;
+    ga.sorig = (uint8_t*)(ws + P.sorig); ga.tcount = (uint32_t*)(ws + P.tcount); ga.gp_of_lin = pa.gp_of_lin;
     const unsigned ggrid = (unsigned)div_up(P.vn, 256);
     if (P.k == 16) gather_sorted<16><<<ggrid, 256, 0, st>>>(ga);
     else if (P.k == 3) gather_sorted<3><<<ggrid, 256, 0, st>>>(ga);
@@ -502,7 +517,7 @@ sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t 
     if (P.vn > 0) emit_keys<<<(unsigned)div_up(P.cap, kKeyChunk), 256, 0, st>>>(ka);
     const int passes = radix_sort((uint32_t*)(ws + P.keys0), (uint32_t*)(ws + P.vals0), (uint32_t*)(ws + P.keys1),
                                   (uint32_t*)(ws + P.vals1), true, device_count(counters + kKeysLo, (uint32_t)P.cap),
-                                  (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st);
+                                  (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits);
     if (passes != P.tile_passes) return SGR_EUNSUPPORTED;
     tile_ranges<<<(unsigned)div_up(P.cap, 256), 256, 0, st>>>(
         (const uint32_t*)(ws + P.sorted_keys), (const uint32_t*)(ws + P.sorted_vals), (const uint32_t*)(ws + P.owner),

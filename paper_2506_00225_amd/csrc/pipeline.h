@@ -17,6 +17,7 @@ struct Plan {
     int64_t n = 0, vn = 0, cap = 0, num_tiles = 0, num_pixels = 0;
     int V = 0, k = 0, kpad = 0, C = 0, nv_slot = 0;
     int tile_bits = 0, tile_passes = 0;
+    int radix_bits = 8;  // widest radix digit (6 or 8)
     // status bit set on the device when a semantic index is >= C
     static constexpr uint32_t kBadIndex = 8u;
     sgr_config cfg{};
@@ -30,6 +31,7 @@ struct Plan {
     // top-k lists have 16 entries over at most 128 classes
     bool ranked = false;
     size_t srk = 0;
+    size_t sorig = 0;  // original list index of each stored top-k position [vis][kpad] (bytes)
     size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, sgp = 0, ranges = 0, heads = 0;
     size_t sorted_keys = 0, sorted_vals = 0;
     size_t hist = 0, partial = 0;
@@ -64,6 +66,7 @@ struct GatherArgs {
     float* ssv;
     uint8_t* ssi;
     uint32_t* srk;  // class-rank table [vis][kRankWords], or nullptr
+    uint8_t* sorig; // original list index of each stored position [vis][kpad]
     uint32_t *tcount, *gp_of_lin;
 };
 

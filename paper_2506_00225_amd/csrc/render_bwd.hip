@@ -135,9 +135,10 @@ __device__ __forceinline__ int transposed_value_index(int lane) {
 // carries only the ten geometry values.
 // With k fixed at compile time the one-class kernel is held to 80 VGPRs for
 // six waves per SIMD, matching the six workgroups its LDS allows.
-template <int KT, bool SPARSE, bool RANKED = false>
+template <int KT, bool SPARSE, bool RANKED = false, int NB = kBwdBatch>
 __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 5) : 1) void render_bwd_kernel(BwdArgs b) {
     static_assert(!RANKED || (KT == 16 && SPARSE), "the rank lookup needs k = 16 and a one-class gradient");
+    static_assert(NB <= 64, "the backward culls a batch with one 64-lane ballot");
     extern __shared__ __align__(16) float smem[];
     const TileArgs& a = b.t;
     const int gt = tile_of_block(blockIdx.x, gridDim.x, a.linear_tiles);
@@ -160,16 +161,16 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
     constexpr int KWM = (KM + 3) / 4;         // ... and on the index words
     float* gp = smem;  // [C][257] dL/dsem of the tile's pixels, column = owning thread (dense mode)
     float4* s_r0 = (float4*)(smem + (SPARSE ? 0 : acc_floats(C)));
-    float4* s_r1 = s_r0 + kBwdBatch;
-    float4* s_r2 = s_r1 + kBwdBatch;
-    float4* s_col = s_r2 + kBwdBatch;
-    uint32_t* s_e = (uint32_t*)(s_col + kBwdBatch);                   // emission index of each key
-    float* s_sv = (float*)(s_e + kBwdBatch);                          // top-k values (not RANKED)
-    uint32_t* s_si = (uint32_t*)(s_sv + (RANKED ? 0 : kBwdBatch * k));
-    uint2* s_lm = (uint2*)(s_si + kBwdBatch * kw);                    // RANKED: [kBwdBatch][4] (mask word, classes below)
-    uint2* s_pm = s_lm + (RANKED ? 4 * kBwdBatch : 0);                // RANKED: [kBwdBatch] rank -> list position
-    float* part = (float*)(s_pm + (RANKED ? kBwdBatch : 0));          // [waves][kBwdBatch][NV]
-    uint32_t* flag = (uint32_t*)(part + kBwdWaves * kBwdBatch * NV);  // [waves][kBwdBatch]
+    float4* s_r1 = s_r0 + NB;
+    float4* s_r2 = s_r1 + NB;
+    float4* s_col = s_r2 + NB;
+    uint32_t* s_e = (uint32_t*)(s_col + NB);                   // emission index of each key
+    float* s_sv = (float*)(s_e + NB);                          // top-k values (not RANKED)
+    uint32_t* s_si = (uint32_t*)(s_sv + (RANKED ? 0 : NB * k));
+    uint2* s_lm = (uint2*)(s_si + NB * kw);                    // RANKED: [NB][4] (mask word, classes below)
+    uint2* s_pm = s_lm + (RANKED ? 4 * NB : 0);                // RANKED: [NB] rank -> list position
+    float* part = (float*)(s_pm + (RANKED ? NB : 0));          // [waves][NB][NV]
+    uint32_t* flag = (uint32_t*)(part + kBwdWaves * NB * NV);  // [waves][NB]
     __shared__ uint32_t s_maxlast;
 
     const int v = view_of_tile(a.views, a.V, gt);
@@ -279,12 +280,11 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
             if (role == 2) {
                 const uint4 w4 = *(const uint4*)((const uint32_t*)(a.ssi) + (size_t)g * 4);
                 stg[0] = w4.x; stg[1] = w4.y; stg[2] = w4.z; stg[3] = w4.w;
-                stg[4] = rk[5];
-                stg[5] = rk[6];
+                stg[4] = rk[4];
+                stg[5] = rk[5];
             } else {
                 const uint4 m4 = *(const uint4*)rk;
                 stg[0] = m4.x; stg[1] = m4.y; stg[2] = m4.z; stg[3] = m4.w;
-                stg[4] = rk[4];
             }
         } else {
             const int v0 = role == 2 ? 0 : VH, w0 = role == 2 ? 0 : WH;
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
     };
 
     int64_t bend = maxlast;
-    uint32_t b0 = (uint32_t)max((int64_t)start, bend - kBwdBatch);
+    uint32_t b0 = (uint32_t)max((int64_t)start, bend - NB);
     if (bend > (int64_t)start) fetch(b0, (int)(bend - b0));
     while (bend > (int64_t)start) {
         const int nb = (int)(bend - b0);
@@ -318,8 +318,12 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                     for (int m = 0; m < 4; m++) s_si[rl * 4 + m] = stg[m];
                     s_pm[rl] = make_uint2(stg[4], stg[5]);
                 } else {
+                    uint32_t below = 0u;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) s_lm[rl * 4 + q] = make_uint2(stg[q], (stg[4] >> (8 * q)) & 0xffu);
+                    for (int q = 0; q < 4; q++) {
+                        s_lm[rl * 4 + q] = make_uint2(stg[q], below);
+                        below += __builtin_popcount(stg[q]);
+                    }
                 }
             } else {
                 const int v0 = role == 2 ? 0 : VH, w0 = role == 2 ? 0 : WH;
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
         }
         __syncthreads();
         const int64_t nend = b0;
-        const uint32_t nb0 = (uint32_t)max((int64_t)start, nend - kBwdBatch);
+        const uint32_t nb0 = (uint32_t)max((int64_t)start, nend - NB);
         if (nend > (int64_t)start) fetch(nb0, (int)(nend - nb0));
 
         // Keys of this batch that can touch this wave's pixels: before the
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
             const int by0 = max(wy0, (int)(ry & 0xffffu)), by1 = min(wy0 + 7, (int)(ry >> 16));
             hit = b0 + lane < wlast && bx0 <= bx1 && by0 <= by1;
             if (hit) hit = conic_meets_block(s_r0[lane], s_r1[lane], bx0, bx1, by0, by1, amin);
-            if (!hit) flag[wv * kBwdBatch + lane] = 0u;
+            if (!hit) flag[wv * NB + lane] = 0u;
         }
         uint64_t todo = __ballot(hit);
         while (todo) {  // back to front
@@ -443,7 +447,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                     for (int m = 0; m < KM; m++)
                         if (m < k) val[10 + m] = w * sg[m];
                 }
-                float* dst = part + (wv * kBwdBatch + j) * NV;
+                float* dst = part + (wv * NB + j) * NV;
                 const bool one = (any & (any - 1)) == 0;
                 if (one) {
                     // one active lane: its values are the wave's sums
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                     }
                 }
             }
-            if (lane == 0) flag[wv * kBwdBatch + j] = any ? 1u : 0u;
+            if (lane == 0) flag[wv * NB + j] = any ? 1u : 0u;
         }
         __syncthreads();
         for (int idx = tid; idx < nb * NV; idx += kBwdThreads) {
@@ -508,14 +512,14 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
             bool t = false;
 #pragma unroll
             for (int w = 0; w < kBwdWaves; w++) {
-                fl[w] = flag[w * kBwdBatch + j];
+                fl[w] = flag[w * NB + j];
                 t |= fl[w] != 0u;
             }
             if (t) {
                 float sum = 0.f;
 #pragma unroll
                 for (int w = 0; w < kBwdWaves; w++)
-                    if (fl[w]) sum += part[(w * kBwdBatch + j) * NV + q];
+                    if (fl[w]) sum += part[(w * NB + j) * NV + q];
                 // with u in units of 2 ln 2: dL/dmean = -2 (2 ln 2) sum dQ u;
                 // dL/dSigma2 = -(2 ln 2)^2 sum dQ u u^T, its two off-diagonal
                 // entries together in slot 3
@@ -533,11 +537,11 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
     for (uint32_t s = maxlast + tid; s < end; s += kBwdThreads) b.touched[b.svals[s]] = 0;
 }
 
-// Sum of each visible pair's key slots.  A pair with a short key segment is
-// summed by its own lane in emission order; long segments (a Gaussian near
-// the camera can cover thousands of tiles) are taken one at a time by the
-// whole wave: lane l sums keys l, l+64, ... and the wave reduces in a fixed
-// pattern.  Either way the result does not depend on timing.
+// Sum of each visible pair's key slots.  A pair with a short key segment is summed by its own lane in
+// emission order; long segments (a Gaussian near the camera can cover
+// thousands of tiles) are taken one at a time by the whole wave: lane l sums
+// keys l, l+64, ... and the wave reduces in a fixed pattern.  Either way the
+// result does not depend on timing.
 constexpr uint32_t kShortSeg = 16;
 
 template <int KT>
@@ -610,141 +614,144 @@ struct ProjBwdArgs {
     int64_t n;
     int V, k, NV, C;
     float lowpass;
-    const uint8_t* sem_idx;    // [n][k], to undo the block grouping of the semantic values
     const uint32_t* gp_of_lin;
     const float* g2d;
+    const uint8_t* sorig;      // [vis][kpad]: list index of each stored top-k position
+    int kpad;
     const uint32_t* counters;
     float *d_means, *d_scales, *d_quats, *d_opacity, *d_rgb, *d_sem;
 };
 
 // Chain rule from each (view, Gaussian) pair's 2D gradient to the 3D
-// parameters, in double precision, summed over views in view order.
+// parameters, in float32 (the gradients need 1e-3; the binning, which must
+// match an FP64 reference bit for bit, is the part kept in FP64), summed
+// over views in view order.
 template <int KT>
 __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
     const int64_t i = blockIdx.x * 256ll + threadIdx.x;
     if (i >= a.n) return;
     const bool ok = !(a.counters[kStatus] & SGR_ECAPACITY);
-    double gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
+    float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
     float go = 0.f, grgb[3] = {0.f, 0.f, 0.f};
     constexpr int KM = KT > 0 ? KT : kMaxK;
     const int k = KT > 0 ? KT : a.k;
-    float gsem[KM];
-#pragma unroll
-    for (int m = 0; m < KM; m++) gsem[m] = 0.f;
-    const double m0 = a.means[3 * i], m1 = a.means[3 * i + 1], m2 = a.means[3 * i + 2];
-    const double q0 = a.quats[4 * i], q1 = a.quats[4 * i + 1], q2 = a.quats[4 * i + 2], q3 = a.quats[4 * i + 3];
-    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-    const double qw = q0 / qn, qx = q1 / qn, qy = q2 / qn, qz = q3 / qn;
-    double Rq[9];
+    const float m0 = a.means[3 * i], m1 = a.means[3 * i + 1], m2 = a.means[3 * i + 2];
+    const float q0 = a.quats[4 * i], q1 = a.quats[4 * i + 1], q2 = a.quats[4 * i + 2], q3 = a.quats[4 * i + 3];
+    const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const float qw = q0 / qn, qx = q1 / qn, qy = q2 / qn, qz = q3 / qn;
+    float Rq[9];
     Rq[0] = 1 - 2 * (qy * qy + qz * qz); Rq[1] = 2 * (qx * qy - qw * qz);     Rq[2] = 2 * (qx * qz + qw * qy);
     Rq[3] = 2 * (qx * qy + qw * qz);     Rq[4] = 1 - 2 * (qx * qx + qz * qz); Rq[5] = 2 * (qy * qz - qw * qx);
     Rq[6] = 2 * (qx * qz - qw * qy);     Rq[7] = 2 * (qy * qz + qw * qx);     Rq[8] = 1 - 2 * (qx * qx + qy * qy);
-    const double s[3] = {(double)a.scales[3 * i], (double)a.scales[3 * i + 1], (double)a.scales[3 * i + 2]};
-    double M[9], S3[9];
+    const float s[3] = {a.scales[3 * i], a.scales[3 * i + 1], a.scales[3 * i + 2]};
+    float M[9], S3[9];
     for (int r = 0; r < 3; r++)
         for (int c = 0; c < 3; c++) M[3 * r + c] = Rq[3 * r + c] * s[c];
     for (int r = 0; r < 3; r++)
         for (int c = 0; c < 3; c++) S3[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
-    double dS3[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float dS3[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int v = 0; v < a.V && ok; v++) {
         const uint32_t g = a.gp_of_lin[(int64_t)v * a.n + i];
         if (g == kInvalid) continue;
         const float* d2 = a.g2d + (size_t)g * a.NV;
         const ViewDev& vw = a.views[v];
-        double W[9];
+        float W[9];
         for (int r = 0; r < 9; r++) W[r] = vw.R[r];
-        double p[3];
-        for (int r = 0; r < 3; r++) p[r] = W[3 * r] * m0 + W[3 * r + 1] * m1 + W[3 * r + 2] * m2 + (double)vw.t[r];
-        const double fx = vw.fx, fy = vw.fy, x = p[0], y = p[1], z = p[2];
-        const double J[6] = {fx / z, 0, -fx * x / (z * z), 0, fy / z, -fy * y / (z * z)};
-        double T[6];
+        float p[3];
+        for (int r = 0; r < 3; r++) p[r] = W[3 * r] * m0 + W[3 * r + 1] * m1 + W[3 * r + 2] * m2 + vw.t[r];
+        const float fx = vw.fx, fy = vw.fy, x = p[0], y = p[1], z = p[2];
+        const float J[6] = {fx / z, 0, -fx * x / (z * z), 0, fy / z, -fy * y / (z * z)};
+        float T[6];
         for (int r = 0; r < 2; r++)
             for (int c = 0; c < 3; c++) T[3 * r + c] = J[3 * r] * W[c] + J[3 * r + 1] * W[3 + c] + J[3 * r + 2] * W[6 + c];
-        double TS3[6];
+        float TS3[6];
         for (int r = 0; r < 2; r++)
             for (int c = 0; c < 3; c++)
                 TS3[3 * r + c] = T[3 * r] * S3[c] + T[3 * r + 1] * S3[3 + c] + T[3 * r + 2] * S3[6 + c];
         // the slots carry dL/dSigma2 itself (the low-pass term is a constant)
-        const double dS2[4] = {d2[2], 0.5 * d2[3], 0.5 * d2[3], d2[4]};
+        const float dS2[4] = {d2[2], 0.5f * d2[3], 0.5f * d2[3], d2[4]};
         for (int r = 0; r < 3; r++)
             for (int c = 0; c < 3; c++)
                 dS3[3 * r + c] += T[r] * (dS2[0] * T[c] + dS2[1] * T[3 + c]) + T[3 + r] * (dS2[2] * T[c] + dS2[3] * T[3 + c]);
-        double dT[6];
+        float dT[6];
         for (int r = 0; r < 2; r++)
-            for (int c = 0; c < 3; c++) dT[3 * r + c] = 2.0 * (dS2[2 * r] * TS3[c] + dS2[2 * r + 1] * TS3[3 + c]);
-        double dJ[6];
+            for (int c = 0; c < 3; c++) dT[3 * r + c] = 2.0f * (dS2[2 * r] * TS3[c] + dS2[2 * r + 1] * TS3[3 + c]);
+        float dJ[6];
         for (int r = 0; r < 2; r++)
             for (int c = 0; c < 3; c++) dJ[3 * r + c] = dT[3 * r] * W[3 * c] + dT[3 * r + 1] * W[3 * c + 1] + dT[3 * r + 2] * W[3 * c + 2];
-        const double z2 = z * z, z3 = z2 * z;
-        double dp[3];
+        const float z2 = z * z, z3 = z2 * z;
+        float dp[3];
         dp[0] = dJ[2] * (-fx / z2);
         dp[1] = dJ[5] * (-fy / z2);
-        dp[2] = dJ[0] * (-fx / z2) + dJ[2] * (2.0 * fx * x / z3) + dJ[4] * (-fy / z2) + dJ[5] * (2.0 * fy * y / z3);
-        const double gmx = d2[0], gmy = d2[1];
+        dp[2] = dJ[0] * (-fx / z2) + dJ[2] * (2.0f * fx * x / z3) + dJ[4] * (-fy / z2) + dJ[5] * (2.0f * fy * y / z3);
+        const float gmx = d2[0], gmy = d2[1];
         dp[0] += gmx * fx / z;
         dp[1] += gmy * fy / z;
-        dp[2] += -gmx * fx * x / z2 - gmy * fy * y / z2 + (double)d2[9];
+        dp[2] += -gmx * fx * x / z2 - gmy * fy * y / z2 + d2[9];
         for (int c = 0; c < 3; c++) gm[c] += W[c] * dp[0] + W[3 + c] * dp[1] + W[6 + c] * dp[2];
         go += d2[5];
         grgb[0] += d2[6];
         grgb[1] += d2[7];
         grgb[2] += d2[8];
-#pragma unroll
-        for (int m = 0; m < KM; m++)
-            if (m < k) gsem[m] += d2[10 + m];
     }
     // Sigma3 = M M^T, M = Rq diag(s): dM = 2 dS3 M
-    double dM[9];
+    float dM[9];
     for (int r = 0; r < 3; r++)
-        for (int c = 0; c < 3; c++) dM[3 * r + c] = 2.0 * (dS3[3 * r] * M[c] + dS3[3 * r + 1] * M[3 + c] + dS3[3 * r + 2] * M[6 + c]);
+        for (int c = 0; c < 3; c++) dM[3 * r + c] = 2.0f * (dS3[3 * r] * M[c] + dS3[3 * r + 1] * M[3 + c] + dS3[3 * r + 2] * M[6 + c]);
     for (int c = 0; c < 3; c++) gs[c] = dM[c] * Rq[c] + dM[3 + c] * Rq[3 + c] + dM[6 + c] * Rq[6 + c];
-    double dR[9];
+    float dR[9];
     for (int r = 0; r < 3; r++)
         for (int c = 0; c < 3; c++) dR[3 * r + c] = dM[3 * r + c] * s[c];
-    double dq[4];
-    dq[0] = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-    dq[1] = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] + qw * dR[7] - 2.0 * qx * dR[8]);
-    dq[2] = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] + qz * dR[7] - 2.0 * qy * dR[8]);
-    dq[3] = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] + qy * dR[5] + qx * dR[6] + qy * dR[7]);
-    const double dot = dq[0] * qw + dq[1] * qx + dq[2] * qy + dq[3] * qz;
-    const double qh[4] = {qw, qx, qy, qz};
+    float dq[4];
+    dq[0] = 2.0f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+    dq[1] = 2.0f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0f * qx * dR[4] - qw * dR[5] + qz * dR[6] + qw * dR[7] - 2.0f * qx * dR[8]);
+    dq[2] = 2.0f * (-2.0f * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] + qz * dR[7] - 2.0f * qy * dR[8]);
+    dq[3] = 2.0f * (-2.0f * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0f * qz * dR[4] + qy * dR[5] + qx * dR[6] + qy * dR[7]);
+    const float dot = dq[0] * qw + dq[1] * qx + dq[2] * qy + dq[3] * qz;
+    const float qh[4] = {qw, qx, qy, qz};
     for (int c = 0; c < 4; c++) gq[c] = (dq[c] - qh[c] * dot) / qn;
-    if (a.d_means) for (int c = 0; c < 3; c++) a.d_means[3 * i + c] = (float)gm[c];
-    if (a.d_scales) for (int c = 0; c < 3; c++) a.d_scales[3 * i + c] = (float)gs[c];
-    if (a.d_quats) for (int c = 0; c < 4; c++) a.d_quats[4 * i + c] = (float)gq[c];
+    if (a.d_means) for (int c = 0; c < 3; c++) a.d_means[3 * i + c] = gm[c];
+    if (a.d_scales) for (int c = 0; c < 3; c++) a.d_scales[3 * i + c] = gs[c];
+    if (a.d_quats) for (int c = 0; c < 4; c++) a.d_quats[4 * i + c] = gq[c];
     if (a.d_opacity) a.d_opacity[i] = go;
     if (a.d_rgb) for (int c = 0; c < 3; c++) a.d_rgb[3 * i + c] = grgb[c];
     if (a.d_sem) {
-        // slot values are in grouped order: entry m sits at grouped_pos(m)
-        uint32_t blk[KM];
+        // the top-k value gradients in stored order, summed over views (after
+        // the chain rule, so its registers are free), then written to the list
+        // positions they came from (the same for every view of a Gaussian)
+        float gsem[KM];
 #pragma unroll
-        for (int m = 0; m < KM; m++) {
-            uint32_t c = m < k ? (uint32_t)a.sem_idx[i * k + m] : 0u;
-            if ((int)c >= a.C) c = 0u;
-            blk[m] = c / kRegBlock;
+        for (int p = 0; p < KM; p++) gsem[p] = 0.f;
+        uint32_t gany = kInvalid;
+        for (int v = 0; v < a.V && ok; v++) {
+            const uint32_t g = a.gp_of_lin[(int64_t)v * a.n + i];
+            if (g == kInvalid) continue;
+            gany = g;
+            const float* d2 = a.g2d + (size_t)g * a.NV + 10;
+#pragma unroll
+            for (int p = 0; p < KM; p++)
+                if (p < k) gsem[p] += d2[p];
         }
+        float* ds = a.d_sem + i * k;
+        if (gany == kInvalid) {
+            for (int m = 0; m < k; m++) ds[m] = 0.f;
+        } else {
+            const uint32_t* so = (const uint32_t*)(a.sorig + (size_t)gany * a.kpad);
 #pragma unroll
-        for (int m = 0; m < KM; m++) {
-            if (m < k) {
-                const int pos = grouped_pos<KM>(blk, k, m);
-                float gv = 0.f;
-#pragma unroll
-                for (int p = 0; p < KM; p++)
-                    if (p == pos) gv = gsem[p];
-                a.d_sem[i * k + m] = gv;
-            }
+            for (int p = 0; p < KM; p++)
+                if (p < k) ds[(so[p >> 2] >> (8 * (p & 3))) & 0xffu] = gsem[p];
         }
     }
 }
 
 // ------------------------------------------------------------------ launcher
 
-static size_t bwd_lds_bytes(int C, int k, int kpad, bool sparse, bool ranked) {
-    size_t b = (size_t)kBwdBatch * (4 * sizeof(float4) + sizeof(uint32_t) + kpad);
+static size_t bwd_lds_bytes(int C, int k, int kpad, bool sparse, bool ranked, int nb) {
+    size_t b = (size_t)nb * (4 * sizeof(float4) + sizeof(uint32_t) + kpad);
     // the top-k values (not kept by the ranked kernel), or the class rank
     // tables: four (mask word, classes below) pairs and the position nibbles
-    b += ranked ? (size_t)kBwdBatch * 5 * sizeof(uint2) : (size_t)kBwdBatch * k * sizeof(float);
-    b += (size_t)kBwdWaves * kBwdBatch * (10 + k) * sizeof(float) + kBwdWaves * kBwdBatch * sizeof(uint32_t);
+    b += ranked ? (size_t)nb * 5 * sizeof(uint2) : (size_t)nb * k * sizeof(float);
+    b += (size_t)kBwdWaves * nb * (10 + k) * sizeof(float) + kBwdWaves * nb * sizeof(uint32_t);
     if (!sparse) b += (size_t)acc_floats(C) * sizeof(float);
     return b;
 }
@@ -755,10 +762,22 @@ static void set_lds_b(K kernel, size_t bytes) {
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <int KT, bool SPARSE, bool RANKED = false, int NB = kBwdBatch>
+static void bwd_launch_nb(const BwdArgs& b, unsigned grid, size_t lds, hipStream_t st) {
+    set_lds_b(render_bwd_kernel<KT, SPARSE, RANKED, NB>, lds);
+    render_bwd_kernel<KT, SPARSE, RANKED, NB><<<grid, kBwdThreads, lds, st>>>(b);
+}
+
+// The staging batch is a speed choice (cfg.bwd_batch): 32, 44 (the default)
+// or 56 keys, trading LDS per workgroup (workgroups per CU) against barriers
+// per key.  Only the common k = 16 kernels carry the three sizes.
 template <int KT, bool SPARSE, bool RANKED = false>
-static void bwd_launch(const BwdArgs& b, unsigned grid, size_t lds, hipStream_t st) {
-    set_lds_b(render_bwd_kernel<KT, SPARSE, RANKED>, lds);
-    render_bwd_kernel<KT, SPARSE, RANKED><<<grid, kBwdThreads, lds, st>>>(b);
+static void bwd_launch(const BwdArgs& b, unsigned grid, size_t lds, int nb, hipStream_t st) {
+    if constexpr (KT == 16) {
+        if (nb == 32) return bwd_launch_nb<KT, SPARSE, RANKED, 32>(b, grid, lds, st);
+        if (nb == 56) return bwd_launch_nb<KT, SPARSE, RANKED, 56>(b, grid, lds, st);
+    }
+    bwd_launch_nb<KT, SPARSE, RANKED, kBwdBatch>(b, grid, lds, st);
 }
 
 sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* ws, hipStream_t st) {
@@ -780,17 +799,18 @@ sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* w
     // one-class semantic gradient kept off geometry, k = 16, C <= 128: the
     // label's list position comes from the class rank tables
     const bool ranked = sparse && P.ranked && !b.semgeo;
-    const size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad, sparse, ranked);
+    const int nb = (P.k == 16 && P.cfg.bwd_batch > 0) ? P.cfg.bwd_batch : kBwdBatch;
+    const size_t lds = bwd_lds_bytes(P.C, P.k, P.kpad, sparse, ranked, nb);
     if (lds > device_max_lds()) return SGR_EUNSUPPORTED;
     const unsigned grid = (unsigned)(div_up(P.num_tiles, 8) * 8);
     if (P.k == 16) {
-        if (ranked) bwd_launch<16, true, true>(b, grid, lds, st);
-        else if (sparse) bwd_launch<16, true>(b, grid, lds, st);
-        else bwd_launch<16, false>(b, grid, lds, st);
+        if (ranked) bwd_launch<16, true, true>(b, grid, lds, nb, st);
+        else if (sparse) bwd_launch<16, true>(b, grid, lds, nb, st);
+        else bwd_launch<16, false>(b, grid, lds, nb, st);
     } else if (P.k == 3) {
-        if (sparse) bwd_launch<3, true>(b, grid, lds, st); else bwd_launch<3, false>(b, grid, lds, st);
+        if (sparse) bwd_launch<3, true>(b, grid, lds, nb, st); else bwd_launch<3, false>(b, grid, lds, nb, st);
     } else {
-        if (sparse) bwd_launch<0, true>(b, grid, lds, st); else bwd_launch<0, false>(b, grid, lds, st);
+        if (sparse) bwd_launch<0, true>(b, grid, lds, nb, st); else bwd_launch<0, false>(b, grid, lds, nb, st);
     }
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }
@@ -814,10 +834,11 @@ sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const s
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opacity = g->opacity;
     pa.views = (const ViewDev*)(ws + P.views);
     pa.n = P.n; pa.V = P.V; pa.k = P.k; pa.NV = nvals; pa.C = P.C;
-    pa.sem_idx = g->sem_idx;
     pa.lowpass = P.cfg.lowpass;
     pa.gp_of_lin = (const uint32_t*)(ws + P.gp_of_lin);
     pa.g2d = (const float*)(ws + P.g2d);
+    pa.sorig = (const uint8_t*)(ws + P.sorig);
+    pa.kpad = P.kpad;
     pa.counters = counters;
     pa.d_means = out->means; pa.d_scales = out->scales; pa.d_quats = out->quats;
     pa.d_opacity = out->opacity; pa.d_rgb = out->rgb; pa.d_sem = out->sem_val;

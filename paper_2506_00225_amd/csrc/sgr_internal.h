@@ -18,12 +18,12 @@ constexpr int kRegBlock = 32;      // classes per register accumulator vector
 constexpr int kMaxRegC = 128;      // classes that fit the register accumulators (4 vectors)
 constexpr int kMaxPasses = 4;      // class ranges the LDS class sums may be split into
 // Class-rank table of a visible pair whose top-k list has 16 entries over at
-// most 128 classes, 8 words: the 128-bit class mask (words 0-3); in word 4,
-// byte q = number of classes in mask words below q; words 5-6, nibble r =
-// stored list position of the class of rank r (its r-th smallest class).
-// A pixel finds its label's list position with one mask lookup, a popcount
-// and a nibble shift (lists with a repeated class are flagged in the record
-// and never looked up this way).
+// most 128 classes, 8 words: the 128-bit class mask (words 0-3); words 4-5,
+// nibble r = stored list position of the class of rank r (its r-th
+// smallest class); words 6-7 unused (padding).  A pixel finds its label's
+// rank with one mask lookup and a popcount, and from it the list position
+// (lists with a repeated class are flagged in the record, have zero
+// nibbles, and are never looked up).
 constexpr int kRankWords = 8;
 
 // Top-k entries are stored grouped by accumulator block (class / 32), in

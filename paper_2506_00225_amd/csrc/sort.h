@@ -45,13 +45,19 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t ma
 // non-zero items in block b (blocks of kScanTile).
 void scan_flag_sums(const uint32_t* in, uint32_t n, uint32_t* partial, hipStream_t st);
 
+// Passes of a radix sort of `bits` key bits with digits of at most
+// max_digit (<= 8) bits.
+inline int radix_passes(int bits, int max_digit) { return (bits + max_digit - 1) / max_digit; }
+
 // Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
-// at most 8 bits per pass (spread evenly), ping-ponging between the a and b
-// buffers.  Returns the
-// pass count: the result is in the a buffers when it is even, else in b.
-// vals_identity: the a values are not read; value i is taken to be i.
+// at most max_digit (<= 8) bits per pass (spread evenly), ping-ponging
+// between the a and b buffers.  Returns the pass count
+// (radix_passes(bits, max_digit)): the result is in the a buffers when it is
+// even, else in b.  vals_identity: the a values are not read; value i is
+// taken to be i.
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
-               CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st);
+               CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st,
+               int max_digit = 8);
 
 inline size_t radix_hist_words(uint32_t max_n) {
     return 256u * (size_t)std::max(div_up(max_n, kRadixTile), div_up(max_n, kRadixTileSmall));

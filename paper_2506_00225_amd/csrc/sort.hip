@@ -233,14 +233,16 @@ void scan_flag_sums(const uint32_t* in, uint32_t n, uint32_t* partial, hipStream
 }
 
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
-               CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st) {
+               CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st,
+               int max_digit) {
     const uint32_t nblk_max = (uint32_t)div_up(max_n, kRadixTile);
     if (nblk_max == 0) return 0;
     // few: small tiles (more workgroups for a small sort) and offsets formed in the scatter
     const uint32_t nblk_small = (uint32_t)div_up(max_n, kRadixTileSmall);
-    // passes of at most 8 bits, the bits spread evenly (12 bits: two 6-bit
-    // digits, whose 64 buckets keep the scatter's writes in longer runs)
-    const int passes = (bits + 7) / 8;
+    // passes of at most max_digit bits, the bits spread evenly (12 bits in
+    // 8-bit digits: two 6-bit digits, whose 64 buckets keep the scatter's
+    // writes in longer runs)
+    const int passes = radix_passes(bits, max_digit);
     const int dbits = passes > 0 ? (bits + passes - 1) / passes : 8;
     const uint32_t bins = 1u << dbits;
     uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;

@@ -18,17 +18,19 @@ DEFAULTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, z_near=0.2, l
 
 
 def make_config(num_classes: int, top_k: int, sem_grad_to_geometry: int = 0, sem_accumulators: int = 0,
-                tile_order: int = 0, score_workgroups: int = 0, sem_passes: int = 0, **kw) -> L.sgr_config:
+                tile_order: int = 0, score_workgroups: int = 0, sem_passes: int = 0, bwd_batch: int = 0,
+                radix_bits: int = 0, **kw) -> L.sgr_config:
     """sem_accumulators (0 automatic, 1 LDS, 2 registers for C <= 128),
     tile_order (0 automatic, 1 XCD-contiguous, 2 linear),
-    score_workgroups (0 = all resident) and sem_passes (0 automatic, 1..4
-    class ranges of the LDS class sums) change speed only, not the bits of
-    any output (see autotune)."""
+    score_workgroups (0 = all resident), sem_passes (0 automatic, 1..4
+    class ranges of the LDS class sums), bwd_batch (0 = 44, or 32, 44, 56
+    keys per backward batch) and radix_bits (0 = 8, or 6 or 8 bits per
+    sort pass) change speed only, not the bits of any output (see autotune)."""
     d = dict(DEFAULTS)
     d.update(kw)
     return L.sgr_config(d["alpha_min"], d["alpha_max"], d["t_min"], d["z_near"], d["lowpass"], int(num_classes),
                         int(top_k), int(sem_grad_to_geometry), 16, 16, int(sem_accumulators), int(tile_order),
-                        int(score_workgroups), int(sem_passes))
+                        int(score_workgroups), int(sem_passes), int(bwd_batch), int(radix_bits))
 
 
 def camera_array(cams):

@@ -606,30 +606,35 @@ def test_score_views_graph_replay_matches_eager():
     assert st == 0
 
 
-def test_autotuner_choices_keep_outputs():
+def test_autotuner_choices_keep_outputs(tmp_path, monkeypatch):
     """The autotuner times every candidate on the frame's own data, checks
     that all candidates give the same bits, and leaves the fastest in the
-    config; the tuned frame reproduces the default frame's outputs."""
+    config (also in its JSON cache, keyed by architecture and shape); the
+    tuned frame reproduces the default frame's outputs."""
     _say("autotune")
+    monkeypatch.setenv("SGR_AUTOTUNE_CACHE", str(tmp_path / "autotune.json"))
     autotune.clear_cache()
     sc = scenes.candidate_scene(n=30_000, nviews=4)
     g = Gaussians.from_scene(sc)
     fr = U.frame_for(sc)
     fr.prepare(g)
     rep = autotune.tune_mapping(fr, g, reps=1)
-    # placements: LDS in 1, 2 or 3 class ranges, registers; two tile orders
-    assert len(rep["candidates"]) == 8 and rep["chosen"] in rep["candidates"]
+    # stage one: placements (LDS in 1, 2 or 3 class ranges, registers) x two
+    # tile orders; stage two: three backward batches x two digit widths
+    assert len(rep["candidates"]) == 8 + 6 and rep["chosen"] in rep["candidates"]
     rep2 = autotune.tune_score(fr, g, reps=1, workgroups=(0, 64))
-    assert len(rep2["candidates"]) == 16
-    assert autotune.tune_score(fr, g)["cached"] == (fr.cfg.sem_accumulators, fr.cfg.tile_order,
-                                                    fr.cfg.score_workgroups, fr.cfg.sem_passes)
+    assert len(rep2["candidates"]) == 16 + 2
+    knobs = {k: int(getattr(fr.cfg, k)) for k in autotune.KNOBS}
+    assert autotune.tune_score(fr, g)["cached"] == knobs
+    autotune.clear_cache()  # the JSON file still has it
+    assert autotune.tune_score(fr, g)["cached"] == knobs
     rng = np.random.default_rng(2)
     tg = [{"rgb": torch.from_numpy(rng.random((c.width * c.height, 3)).astype(np.float32)),
            "depth": torch.from_numpy(rng.random(c.width * c.height).astype(np.float32) + 1.0),
            "label": torch.from_numpy(rng.integers(0, sc.num_classes, c.width * c.height).astype(np.int32))}
           for c in sc.cameras]
     rep3 = autotune.tune_mapping(fr, g, reps=1, targets=tg)
-    assert rep3["what"] == "mapping_loss" and len(rep3["candidates"]) == 8
+    assert rep3["what"] == "mapping_loss" and len(rep3["candidates"]) == 8 + 6
     ref = U.frame_for(sc)
     ref.prepare(g)
     fr.prepare(g)
