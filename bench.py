@@ -1,8 +1,9 @@
 """Benchmark of the semantic Gaussian rasterizer on one MI355X.
 
 Step = one mapping iteration on 1M Gaussians in a 10x8x3 m room seen by one
-1200x680 keyframe (fx=fy=600): project -> bin -> render_forward -> loss
-gradient -> render_backward -> Adam.  The loss is the mapping loss with the
+1200x680 keyframe (fx=fy=600): project -> bin -> render_forward with the
+fused loss gradient -> render_backward, whose gather applies the Adam step
+where each Gaussian's gradient is formed.  The loss is the mapping loss with the
 silhouette mask (S > 0.99: L1 depth + 0.5 L1 colour), plus L1(S, 1) and a
 cross-entropy on the semantic map.  Throughput is Gaussian-pixel blends per
 second (blends = sum of n_contrib, exact).  Candidate-view scoring (500k
@@ -133,7 +134,11 @@ def mapping_bench(args, torch, out):
     names = ["s0", "proj", "bin", "fwd", "bwd_tiles", "bwd_gather", "adam"]
     tm = Timer(torch, names)
 
-    def step(i, marked):
+    def step(i, marked, fused=True):
+        """One mapping iteration.  fused: the gather and the Adam step in one
+        pass (sgr_render_backward_gather_adam), as the timed steps run it;
+        the steps with stage events run them apart, so the breakdown shows
+        each."""
         mk = tm.mark if marked else (lambda _n: None)
         mk("s0")
         fr.project(g)
@@ -144,9 +149,12 @@ def mapping_bench(args, torch, out):
         mk("fwd")
         fr.backward_tiles(g, grads_in)
         mk("bwd_tiles")
-        fr.backward_gather(g, gout)
-        mk("bwd_gather")
-        opt.step()
+        if fused and not marked:
+            fr.backward_gather_adam(g, opt)
+        else:
+            fr.backward_gather(g, gout)
+            mk("bwd_gather")
+            opt.step()
         mk("adam")
         if marked:  # bookkeeping, after the step's last event
             blends[i].copy_(ncon["n_contrib"].sum(dtype=torch.int64))
@@ -158,8 +166,19 @@ def mapping_bench(args, torch, out):
     torch.cuda.synchronize()
     # The timed steps carry no events between stages (each event costs a few
     # microseconds of idle GPU); the per-stage breakdown, the blend count B
-    # and the losses come from as many further steps with an event at every
-    # stage boundary.
+    # and the losses come from the same steps run again with an event at
+    # every stage boundary.  Each run starts from the parameters and moments
+    # left by the warmup, and the gather with Adam gives the bits of the
+    # gather followed by Adam, so all three runs take the same trajectory and
+    # B is the timed steps' own blend count.
+    snap = [x.clone() for x in params + opt.m + opt.v]
+    t_snap = opt.t
+
+    def restore():
+        for x, y in zip(params + opt.m + opt.v, snap):
+            x.copy_(y)
+        opt.t = t_snap
+
     log("timed", args.steps)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -171,7 +190,16 @@ def mapping_bench(args, torch, out):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = e0.elapsed_time(e1) / args.steps
+    # the same steps with the gather and Adam as two launches
+    restore()
+    e0.record()
+    for i in range(args.steps):
+        step(args.warmup + i, False, fused=False)
+    e1.record()
+    torch.cuda.synchronize()
+    step_unfused_ms = e0.elapsed_time(e1) / args.steps
     log("breakdown", args.steps)
+    restore()
     for i in range(args.steps):
         step(args.warmup + args.steps + i, True)
     torch.cuda.synchronize()
@@ -185,7 +213,8 @@ def mapping_bench(args, torch, out):
     marked_ms = float(np.mean(tm.pairs_ms("s0", "adam")))
     B = blends[args.warmup + args.steps:].double().mean().item()
     fwd_bwd_ms = stage["proj"] + stage["bin"] + stage["fwd"] + stage["bwd"]
-    out.update(dict(step_ms=step_ms, step_ms_with_stage_events=marked_ms, wall_ms=wall * 1e3 / args.steps,
+    out.update(dict(step_ms=step_ms, step_unfused_ms=step_unfused_ms, step_ms_with_stage_events=marked_ms,
+                    wall_ms=wall * 1e3 / args.steps,
                     enqueue_ms=enqueue * 1e3 / args.steps,
                     stage_ms=stage, blends=B, nvis=nvis, keys=nkeys, fwd_bwd_ms=fwd_bwd_ms, pixels=P, C=C, k=k,
                     n=sc.n, loss_first_last=[float(losses[args.warmup + args.steps]), float(losses[-1])]))
@@ -665,6 +694,7 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "blends/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(out["step_ms"], 4),
         "ms_per_step_with_stage_events": round(out["step_ms_with_stage_events"], 4),
+        "ms_per_step_gather_and_adam_apart": round(out["step_unfused_ms"], 4),
         "host_wall_ms_per_step": round(out["wall_ms"], 4), "host_enqueue_ms_per_step": round(out["enqueue_ms"], 4),
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",

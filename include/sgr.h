@@ -385,6 +385,27 @@ typedef struct {
 sgr_status sgr_adam_step(const sgr_adam_segment *segments, int32_t num_segments, float lr, float beta1, float beta2,
                          float eps, int32_t step, void *stream);
 
+/*
+ * sgr_render_backward_gather_adam -- sgr_render_backward_gather and then
+ * one sgr_adam_step of the six parameter tensors, in one pass: each
+ * Gaussian's gradient (the chain rule through the EWA projection of
+ * Sec. 3.1, summed over views) updates its parameters where it is formed
+ * and is never written out, so the gradient tensors' write and re-read are
+ * saved.  The result is bitwise that of the two calls.  `segments` is a
+ * HOST array of exactly 6 segments in the order means, scales, quats,
+ * opacity, rgb, sem_val, with n = 3n, 3n, 4n, n, 3n and k n elements (the
+ * Gaussians' n and the config's k), p the parameter tensor (it may be the
+ * array the Gaussians struct points to: each element is read before it is
+ * written, by the same thread), m and v its moments, lo/hi its clamp; their
+ * g is ignored.  Adam arguments as sgr_adam_step.  Must follow
+ * sgr_render_backward_tiles.
+ */
+sgr_status sgr_render_backward_gather_adam(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views,
+                                           const sgr_config *cfg, int64_t key_capacity,
+                                           const sgr_adam_segment *segments, float lr, float beta1, float beta2,
+                                           float eps, int32_t step, void *workspace, size_t workspace_bytes,
+                                           void *stream);
+
 /* ------------------------------------------------------------------ sparse semantic state
  * Sec. 3.1, sparse semantic representation: a Gaussian keeps the top-k
  * classes of the distribution it is initialised from; later observations

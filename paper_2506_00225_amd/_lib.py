@@ -97,7 +97,7 @@ EXPORTS = (
     "sgr_render_backward", "sgr_render_backward_tiles", "sgr_render_backward_gather", "sgr_score_views", "sgr_score_maps_workspace_size", "sgr_score_maps",
     "sgr_read_status", "sgr_status_string", "sgr_mapping_loss_grad", "sgr_adam_step",
     "sgr_candidates_workspace_size", "sgr_generate_candidates", "sgr_score_poses", "sgr_combine_scores",
-    "sgr_topk_select", "sgr_topk_update", "sgr_score_maps_noalloc",
+    "sgr_topk_select", "sgr_topk_update", "sgr_score_maps_noalloc", "sgr_render_backward_gather_adam",
 )
 
 _lib = None
@@ -163,6 +163,10 @@ def lib():
     L.sgr_topk_select.restype = i32
     L.sgr_topk_update.argtypes = [P, P, i64, i32, i32, P, ctypes.c_float, P, P]
     L.sgr_topk_update.restype = i32
+    L.sgr_render_backward_gather_adam.argtypes = [g_p, cam_p, i32, cfg_p, i64, ctypes.POINTER(sgr_adam_segment),
+                                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, i32,
+                                                  P, sz, P]
+    L.sgr_render_backward_gather_adam.restype = i32
     L.sgr_score_maps_noalloc.argtypes = [P, P, i32, i32, i32, P, P, P]
     L.sgr_score_maps_noalloc.restype = i32
     L.sgr_status_string.argtypes = [i32]
@@ -260,6 +264,13 @@ SGR_NOALLOC_MAX_PIXELS = 16 * 1024 * 1024
 
 def sgr_score_maps_noalloc(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, stream):
     return lib().sgr_score_maps_noalloc(sem, n_contrib, width, height, num_classes, n_empty, entropy_sum, stream)
+
+
+def sgr_render_backward_gather_adam(g, cams, num_views, cfg, key_capacity, segments, lr, beta1, beta2, eps, step,
+                                    workspace, workspace_bytes, stream):
+    return lib().sgr_render_backward_gather_adam(ctypes.byref(g), cams, num_views, ctypes.byref(cfg), key_capacity,
+                                                 segments, lr, beta1, beta2, eps, step, workspace, workspace_bytes,
+                                                 stream)
 
 
 def sgr_read_status(workspace, stream):

@@ -381,6 +381,26 @@ sgr_status sgr_render_backward_gather(const sgr_gaussians* g, const sgr_camera* 
     return launch_backward_gather(P, g, out, (char*)workspace, (hipStream_t)stream);
 }
 
+sgr_status sgr_render_backward_gather_adam(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
+                                           const sgr_config* cfg, int64_t key_capacity,
+                                           const sgr_adam_segment* segments, float lr, float beta1, float beta2,
+                                           float eps, int32_t step, void* workspace, size_t workspace_bytes,
+                                           void* stream) {
+    if (!segments || step < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+        !(eps > 0.f))
+        return SGR_EINVAL;
+    Plan P;
+    sgr_status s = prepare(g, cams, num_views, cfg, key_capacity, workspace, workspace_bytes, &P);
+    if (s != SGR_OK) return s;
+    const int64_t want[6] = {3 * P.n, 3 * P.n, 4 * P.n, P.n, 3 * P.n, (int64_t)P.k * P.n};
+    for (int i = 0; i < 6; i++) {
+        const sgr_adam_segment& sg = segments[i];
+        if (sg.n != want[i] || (sg.n > 0 && (!sg.p || !sg.m || !sg.v)) || !(sg.lo <= sg.hi)) return SGR_EINVAL;
+    }
+    const AdamParams h = adam_params(lr, beta1, beta2, eps, step);
+    return launch_backward_gather(P, g, nullptr, (char*)workspace, (hipStream_t)stream, segments, &h);
+}
+
 sgr_status sgr_score_views(const sgr_gaussians* g, const sgr_camera* cams, int32_t num_views,
                            const sgr_config* cfg, int64_t key_capacity, uint32_t* n_empty, double* entropy_sum,
                            void* workspace, size_t workspace_bytes, void* stream) {

@@ -65,17 +65,13 @@ struct AdamSegs {
     int32_t count;
 };
 
-__global__ __launch_bounds__(256) void adam_kernel(AdamSegs segs, float lr, float b1, float b2, float eps, float bc1,
-                                                   float bc2) {
+__global__ __launch_bounds__(256) void adam_kernel(AdamSegs segs, AdamParams h) {
     const sgr_adam_segment& sg = segs.s[blockIdx.y];
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < sg.n; i += (int64_t)gridDim.x * 256) {
-        const float g = sg.g[i];
-        const float m = b1 * sg.m[i] + (1.f - b1) * g;
-        const float v = b2 * sg.v[i] + (1.f - b2) * g * g;
+        float m = sg.m[i], v = sg.v[i], p = sg.p[i];
+        adam_update(sg.g[i], m, v, p, sg.lo, sg.hi, h);
         sg.m[i] = m;
         sg.v[i] = v;
-        float p = sg.p[i] - lr * (m / bc1) / (sqrtf(v / bc2) + eps);
-        p = fminf(fmaxf(p, sg.lo), sg.hi);
         sg.p[i] = p;
     }
 }
@@ -99,9 +95,9 @@ sgr_status launch_adam(const sgr_adam_segment* segs, int n, float lr, float b1, 
     }
     as.count = n;
     if (mx == 0) return SGR_OK;
-    const float bc1 = 1.f - powf(b1, (float)step), bc2 = 1.f - powf(b2, (float)step);
+    const AdamParams h = adam_params(lr, b1, b2, eps, step);
     const unsigned gx = (unsigned)std::min<int64_t>(div_up(mx, 256), 4096);
-    adam_kernel<<<dim3(gx, (unsigned)n), 256, 0, st>>>(as, lr, b1, b2, eps, bc1, bc2);
+    adam_kernel<<<dim3(gx, (unsigned)n), 256, 0, st>>>(as, h);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }
 

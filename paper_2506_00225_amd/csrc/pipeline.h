@@ -2,6 +2,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -43,6 +44,23 @@ struct Plan {
 };
 
 sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_config* cfg, int64_t cap, Plan* P);
+
+// One bias-corrected Adam update (bc1 = 1 - b1^t, bc2 = 1 - b2^t) of a
+// parameter p with moments m, v and gradient g, the parameter clamped to
+// [lo, hi].  The Adam launch and the gather with Adam share it, so both give
+// the same bits.
+struct AdamParams {
+    float lr, b1, b2, eps, bc1, bc2;
+};
+inline AdamParams adam_params(float lr, float b1, float b2, float eps, int step) {
+    return AdamParams{lr, b1, b2, eps, 1.f - powf(b1, (float)step), 1.f - powf(b2, (float)step)};
+}
+__device__ __forceinline__ void adam_update(float g, float& m, float& v, float& p, float lo, float hi,
+                                            const AdamParams& h) {
+    m = h.b1 * m + (1.f - h.b1) * g;
+    v = h.b2 * v + (1.f - h.b2) * g * g;
+    p = fminf(fmaxf(p - h.lr * (m / h.bc1) / (sqrtf(v / h.bc2) + h.eps), lo), hi);
+}
 
 struct ProjectArgs {
     const float *means, *scales, *quats, *opacity;
@@ -87,8 +105,12 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
 sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t st);
 sgr_status launch_forward(const Plan& P, const sgr_maps* out, char* ws, hipStream_t st);
 sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* ws, hipStream_t st);
+// With adam (six segments: means, scales, quats, opacity, rgb, sem_val) the
+// per-Gaussian gradients update the parameters where they are formed
+// instead of being written to out.
 sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const sgr_grads* out, char* ws,
-                                  hipStream_t st);
+                                  hipStream_t st, const sgr_adam_segment* adam = nullptr,
+                                  const AdamParams* hp = nullptr);
 sgr_status launch_score(const Plan& P, uint32_t* n_empty, double* entropy_sum, char* ws, hipStream_t st);
 sgr_status launch_forward_dense(const Plan& P, const float* dense, const sgr_maps* out, char* ws, hipStream_t st);
 sgr_status launch_forward_loss(const Plan& P, const sgr_maps* out, const sgr_loss_view* lv, const sgr_loss_config* lc,

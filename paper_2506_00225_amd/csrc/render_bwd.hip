@@ -171,7 +171,9 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
     uint2* s_pm = s_lm + (RANKED ? 4 * NB : 0);                // RANKED: [NB] rank -> list position
     float* part = (float*)(s_pm + (RANKED ? NB : 0));          // [waves][NB][NV]
     uint32_t* flag = (uint32_t*)(part + kBwdWaves * NB * NV);  // [waves][NB]
+    uint32_t* s_tk = flag + kBwdWaves * NB;  // [NB]: the batch's blended keys (index | wave mask << 8)
     __shared__ uint32_t s_maxlast;
+    __shared__ int s_ntk;
 
     const int v = view_of_tile(a.views, a.V, gt);
     const ViewDev& vw = a.views[v];
@@ -505,30 +507,38 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
             if (lane == 0) flag[wv * NB + j] = any ? 1u : 0u;
         }
         __syncthreads();
-        for (int idx = tid; idx < nb * NV; idx += kBwdThreads) {
-            const int j = idx / NV, q = idx - j * NV;
-            const uint32_t e = s_e[j];
-            uint32_t fl[kBwdWaves];
-            bool t = false;
+        // The keys of the batch some wave blended, with the mask of those
+        // waves, listed once by wave 0 (it also writes every key's touched
+        // flag); then the block sums only those keys' partials.
+        if (wv == 0) {
+            uint32_t wm = 0u;
+            if (lane < nb) {
 #pragma unroll
-            for (int w = 0; w < kBwdWaves; w++) {
-                fl[w] = flag[w * NB + j];
-                t |= fl[w] != 0u;
+                for (int w = 0; w < kBwdWaves; w++) wm |= flag[w * NB + lane] != 0u ? 1u << w : 0u;
+                b.touched[s_e[lane]] = wm ? 1 : 0;
             }
-            if (t) {
-                float sum = 0.f;
+            const uint64_t tm = __ballot(wm != 0u);
+            if (wm) s_tk[__popcll(tm & ((1ull << lane) - 1ull))] = (uint32_t)lane | (wm << 8);
+            if (lane == 0) s_ntk = (int)__popcll(tm);
+        }
+        __syncthreads();
+        const int ntk = __builtin_amdgcn_readfirstlane(s_ntk);
+        for (int idx = tid; idx < ntk * NV; idx += kBwdThreads) {
+            const int at = idx / NV, q = idx - at * NV;
+            const uint32_t tk = s_tk[at];
+            const int j = (int)(tk & 0xffu);
+            const uint32_t wm = tk >> 8;
+            float sum = 0.f;
 #pragma unroll
-                for (int w = 0; w < kBwdWaves; w++)
-                    if (fl[w]) sum += part[(w * NB + j) * NV + q];
-                // with u in units of 2 ln 2: dL/dmean = -2 (2 ln 2) sum dQ u;
-                // dL/dSigma2 = -(2 ln 2)^2 sum dQ u u^T, its two off-diagonal
-                // entries together in slot 3
-                if (q < 2) sum *= -2.f * k2ln2;
-                else if (q == 3) sum *= -2.f * k2ln2sq;
-                else if (q < 5) sum *= -k2ln2sq;
-                b.slots[(size_t)e * NV + q] = sum;
-            }
-            if (q == 0) b.touched[e] = t ? 1 : 0;
+            for (int w = 0; w < kBwdWaves; w++)
+                if ((wm >> w) & 1u) sum += part[(w * NB + j) * NV + q];
+            // with u in units of 2 ln 2: dL/dmean = -2 (2 ln 2) sum dQ u;
+            // dL/dSigma2 = -(2 ln 2)^2 sum dQ u u^T, its two off-diagonal
+            // entries together in slot 3
+            if (q < 2) sum *= -2.f * k2ln2;
+            else if (q == 3) sum *= -2.f * k2ln2sq;
+            else if (q < 5) sum *= -k2ln2sq;
+            b.slots[(size_t)s_e[j] * NV + q] = sum;
         }
         __syncthreads();
         bend = nend;
@@ -618,6 +628,8 @@ struct ProjBwdArgs {
     const float* g2d;
     const uint8_t* sorig;      // [vis][kpad]: list index of each stored top-k position
     int kpad;
+    sgr_adam_segment seg[6];   // with Adam: means, scales, quats, opacity, rgb, sem_val
+    AdamParams h;
     const uint32_t* counters;
     float *d_means, *d_scales, *d_quats, *d_opacity, *d_rgb, *d_sem;
 };
@@ -626,24 +638,65 @@ struct ProjBwdArgs {
 // parameters, in float32 (the gradients need 1e-3; the binning, which must
 // match an FP64 reference bit for bit, is the part kept in FP64), summed
 // over views in view order.
-template <int KT>
+//
+// With ADAM the gradients are not written: each block stages its 256
+// Gaussians' gradients of one parameter tensor in LDS, a contiguous range of
+// that tensor, and the block applies the Adam update to the range with
+// coalesced loads of p, m and v, all of a thread's loads issued before its
+// stores.
+template <int WM>
+__device__ __forceinline__ void adam_rows(const sgr_adam_segment& sg, const float* st, int64_t i0, int cnt, int w,
+                                          const AdamParams& h) {
+    const int ws = w | 1;  // odd row stride: the rows were written without bank conflicts
+    const int tot = cnt * w;
+    const int64_t base = i0 * w;
+    float m[WM], v[WM], p[WM];
+    __syncthreads();  // the rows are staged, and every thread has read its parameters
+#pragma unroll
+    for (int u = 0; u < WM; u++) {
+        const int e = (int)threadIdx.x + 256 * u;
+        if (e < tot) {
+            m[u] = sg.m[base + e];
+            v[u] = sg.v[base + e];
+            p[u] = sg.p[base + e];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < WM; u++) {
+        const int e = (int)threadIdx.x + 256 * u;
+        if (e < tot) {
+            const int t = e / w, c = e - t * w;
+            adam_update(st[t * ws + c], m[u], v[u], p[u], sg.lo, sg.hi, h);
+            sg.m[base + e] = m[u];
+            sg.v[base + e] = v[u];
+            sg.p[base + e] = p[u];
+        }
+    }
+    __syncthreads();  // before the rows are overwritten
+}
+
+template <int KT, bool ADAM>
 __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
-    const int64_t i = blockIdx.x * 256ll + threadIdx.x;
-    if (i >= a.n) return;
-    const bool ok = !(a.counters[kStatus] & SGR_ECAPACITY);
+    const int64_t i0 = blockIdx.x * 256ll, i = i0 + threadIdx.x;
+    if (!ADAM && i >= a.n) return;
+    // with ADAM every thread reaches the block's barriers; one past the end
+    // reads the last Gaussian's parameters and takes no view
+    const bool live = i < a.n;
+    const int64_t il = live ? i : a.n - 1;
+    const bool ok = live && !(a.counters[kStatus] & SGR_ECAPACITY);
     float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
     float go = 0.f, grgb[3] = {0.f, 0.f, 0.f};
     constexpr int KM = KT > 0 ? KT : kMaxK;
     const int k = KT > 0 ? KT : a.k;
-    const float m0 = a.means[3 * i], m1 = a.means[3 * i + 1], m2 = a.means[3 * i + 2];
-    const float q0 = a.quats[4 * i], q1 = a.quats[4 * i + 1], q2 = a.quats[4 * i + 2], q3 = a.quats[4 * i + 3];
+    const float m0 = a.means[3 * il], m1 = a.means[3 * il + 1], m2 = a.means[3 * il + 2];
+    const float q0 = a.quats[4 * il], q1 = a.quats[4 * il + 1], q2 = a.quats[4 * il + 2], q3 = a.quats[4 * il + 3];
     const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
     const float qw = q0 / qn, qx = q1 / qn, qy = q2 / qn, qz = q3 / qn;
     float Rq[9];
     Rq[0] = 1 - 2 * (qy * qy + qz * qz); Rq[1] = 2 * (qx * qy - qw * qz);     Rq[2] = 2 * (qx * qz + qw * qy);
     Rq[3] = 2 * (qx * qy + qw * qz);     Rq[4] = 1 - 2 * (qx * qx + qz * qz); Rq[5] = 2 * (qy * qz - qw * qx);
     Rq[6] = 2 * (qx * qz - qw * qy);     Rq[7] = 2 * (qy * qz + qw * qx);     Rq[8] = 1 - 2 * (qx * qx + qy * qy);
-    const float s[3] = {a.scales[3 * i], a.scales[3 * i + 1], a.scales[3 * i + 2]};
+    const float s[3] = {a.scales[3 * il], a.scales[3 * il + 1], a.scales[3 * il + 2]};
     float M[9], S3[9];
     for (int r = 0; r < 3; r++)
         for (int c = 0; c < 3; c++) M[3 * r + c] = Rq[3 * r + c] * s[c];
@@ -710,12 +763,30 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
     const float dot = dq[0] * qw + dq[1] * qx + dq[2] * qy + dq[3] * qz;
     const float qh[4] = {qw, qx, qy, qz};
     for (int c = 0; c < 4; c++) gq[c] = (dq[c] - qh[c] * dot) / qn;
-    if (a.d_means) for (int c = 0; c < 3; c++) a.d_means[3 * i + c] = gm[c];
-    if (a.d_scales) for (int c = 0; c < 3; c++) a.d_scales[3 * i + c] = gs[c];
-    if (a.d_quats) for (int c = 0; c < 4; c++) a.d_quats[4 * i + c] = gq[c];
-    if (a.d_opacity) a.d_opacity[i] = go;
-    if (a.d_rgb) for (int c = 0; c < 3; c++) a.d_rgb[3 * i + c] = grgb[c];
-    if (a.d_sem) {
+    if (!ADAM) {
+        if (a.d_means) for (int c = 0; c < 3; c++) a.d_means[3 * i + c] = gm[c];
+        if (a.d_scales) for (int c = 0; c < 3; c++) a.d_scales[3 * i + c] = gs[c];
+        if (a.d_quats) for (int c = 0; c < 4; c++) a.d_quats[4 * i + c] = gq[c];
+        if (a.d_opacity) a.d_opacity[i] = go;
+        if (a.d_rgb) for (int c = 0; c < 3; c++) a.d_rgb[3 * i + c] = grgb[c];
+    }
+    constexpr int kRow = (KM | 1) > 5 ? (KM | 1) : 5;  // widest staged row: quats (4 | 1) or the top-k values
+    __shared__ float st[ADAM ? 256 * kRow : 1];
+    const int cnt = (int)min<int64_t>(256, a.n - i0);
+    const int tid = threadIdx.x;
+    if (ADAM) {
+        for (int c = 0; c < 3; c++) st[tid * 3 + c] = gm[c];
+        adam_rows<3>(a.seg[0], st, i0, cnt, 3, a.h);
+        for (int c = 0; c < 3; c++) st[tid * 3 + c] = gs[c];
+        adam_rows<3>(a.seg[1], st, i0, cnt, 3, a.h);
+        for (int c = 0; c < 4; c++) st[tid * 5 + c] = gq[c];
+        adam_rows<4>(a.seg[2], st, i0, cnt, 4, a.h);
+        st[tid] = go;
+        adam_rows<1>(a.seg[3], st, i0, cnt, 1, a.h);
+        for (int c = 0; c < 3; c++) st[tid * 3 + c] = grgb[c];
+        adam_rows<3>(a.seg[4], st, i0, cnt, 3, a.h);
+    }
+    if (ADAM || a.d_sem) {
         // the top-k value gradients in stored order, summed over views (after
         // the chain rule, so its registers are free), then written to the list
         // positions they came from (the same for every view of a Gaussian)
@@ -732,7 +803,7 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
             for (int p = 0; p < KM; p++)
                 if (p < k) gsem[p] += d2[p];
         }
-        float* ds = a.d_sem + i * k;
+        float* ds = ADAM ? st + tid * (k | 1) : a.d_sem + i * k;
         if (gany == kInvalid) {
             for (int m = 0; m < k; m++) ds[m] = 0.f;
         } else {
@@ -741,6 +812,7 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
             for (int p = 0; p < KM; p++)
                 if (p < k) ds[(so[p >> 2] >> (8 * (p & 3))) & 0xffu] = gsem[p];
         }
+        if (ADAM) adam_rows<KM>(a.seg[5], st, i0, cnt, k, a.h);
     }
 }
 
@@ -752,6 +824,7 @@ static size_t bwd_lds_bytes(int C, int k, int kpad, bool sparse, bool ranked, in
     // tables: four (mask word, classes below) pairs and the position nibbles
     b += ranked ? (size_t)nb * 5 * sizeof(uint2) : (size_t)nb * k * sizeof(float);
     b += (size_t)kBwdWaves * nb * (10 + k) * sizeof(float) + kBwdWaves * nb * sizeof(uint32_t);
+    b += (size_t)nb * sizeof(uint32_t);  // the list of blended keys
     if (!sparse) b += (size_t)acc_floats(C) * sizeof(float);
     return b;
 }
@@ -816,7 +889,7 @@ sgr_status launch_backward_tiles(const Plan& P, const sgr_map_grads* dL, char* w
 }
 
 sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const sgr_grads* out, char* ws,
-                                  hipStream_t st) {
+                                  hipStream_t st, const sgr_adam_segment* adam, const AdamParams* hp) {
     const uint32_t* counters = (const uint32_t*)(ws + P.counters);
     const int nvals = 10 + P.k;
     const unsigned ggrid = (unsigned)div_up(P.vn, 256);
@@ -839,14 +912,25 @@ sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const s
     pa.g2d = (const float*)(ws + P.g2d);
     pa.sorig = (const uint8_t*)(ws + P.sorig);
     pa.kpad = P.kpad;
+    memset(pa.seg, 0, sizeof(pa.seg));
+    pa.h = hp ? *hp : AdamParams{};
+    if (adam)
+        for (int s = 0; s < 6; s++) pa.seg[s] = adam[s];
     pa.counters = counters;
-    pa.d_means = out->means; pa.d_scales = out->scales; pa.d_quats = out->quats;
-    pa.d_opacity = out->opacity; pa.d_rgb = out->rgb; pa.d_sem = out->sem_val;
+    pa.d_means = out ? out->means : nullptr; pa.d_scales = out ? out->scales : nullptr;
+    pa.d_quats = out ? out->quats : nullptr; pa.d_opacity = out ? out->opacity : nullptr;
+    pa.d_rgb = out ? out->rgb : nullptr; pa.d_sem = out ? out->sem_val : nullptr;
     const unsigned pgrid = (unsigned)div_up(P.n, 256);
     if (pgrid > 0) {
-        if (P.k == 16) project_backward_kernel<16><<<pgrid, 256, 0, st>>>(pa);
-        else if (P.k == 3) project_backward_kernel<3><<<pgrid, 256, 0, st>>>(pa);
-        else project_backward_kernel<0><<<pgrid, 256, 0, st>>>(pa);
+        if (adam) {
+            if (P.k == 16) project_backward_kernel<16, true><<<pgrid, 256, 0, st>>>(pa);
+            else if (P.k == 3) project_backward_kernel<3, true><<<pgrid, 256, 0, st>>>(pa);
+            else project_backward_kernel<0, true><<<pgrid, 256, 0, st>>>(pa);
+        } else {
+            if (P.k == 16) project_backward_kernel<16, false><<<pgrid, 256, 0, st>>>(pa);
+            else if (P.k == 3) project_backward_kernel<3, false><<<pgrid, 256, 0, st>>>(pa);
+            else project_backward_kernel<0, false><<<pgrid, 256, 0, st>>>(pa);
+        }
     }
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }

@@ -364,6 +364,22 @@ class Frame:
                                              self.stream), "sgr_render_backward_gather")
         return out
 
+    def backward_gather_adam(self, g: Gaussians, opt: "FusedAdam"):
+        """backward_gather and opt.step() in one pass
+        (sgr_render_backward_gather_adam): the gradients update the
+        parameters where they are formed and are not written.  opt's six
+        groups are the means, scales, quats, opacity, rgb and sem_val
+        parameters, in this order (normally g's own tensors)."""
+        n, k = self.n, int(self.cfg.top_k)
+        want = (3 * n, 3 * n, 4 * n, n, 3 * n, k * n)
+        if len(opt.groups) != 6 or any(p.numel() != w for (p, _, _, _), w in zip(opt.groups, want)):
+            raise ValueError("backward_gather_adam: opt needs six groups (means, scales, quats, opacity, rgb, "
+                             f"sem_val) of {want} elements")
+        opt.t += 1
+        L.check(L.sgr_render_backward_gather_adam(g.c_struct(self), *self._args(), opt.segs, opt.lr, opt.b1, opt.b2,
+                                                  opt.eps, opt.t, _ptr(self.ws), self.ws.numel(), self.stream),
+                "sgr_render_backward_gather_adam")
+
     def score(self, g: Gaussians, n_empty=None, entropy_sum=None):
         n_empty = n_empty if n_empty is not None else torch.empty(self.V, dtype=torch.int32, device=self.device)
         entropy_sum = entropy_sum if entropy_sum is not None else torch.empty(self.V, dtype=torch.float64,

@@ -135,6 +135,20 @@ def test_calls_validate_before_any_device_work(L):
     assert L.sgr_score_maps(None, None, 4, 4, 16, None, None, None, 0, None) == L.SGR_EINVAL
     assert L.sgr_score_maps_workspace_size(0, 4) == 0
     assert L.sgr_score_maps_noalloc(None, None, 4, 4, 16, None, None, None) == L.SGR_EINVAL
+    # fused gather + Adam: no segments, a bad step, a segment of the wrong size
+    segs = (L.sgr_adam_segment * 6)()
+    gw = L.sgr_gaussians(10, *([ctypes.c_void_p(256)] * 7))
+    lib = L.lib()
+    assert lib.sgr_render_backward_gather_adam(gw, cams, 1, cfg, 100, None, 1e-3, 0.9, 0.999, 1e-8, 1,
+                                               addr, size, None) == L.SGR_EINVAL
+    assert lib.sgr_render_backward_gather_adam(gw, cams, 1, cfg, 100, segs, 1e-3, 0.9, 0.999, 1e-8, 0,
+                                               addr, size, None) == L.SGR_EINVAL
+    one = ctypes.c_void_p(256)
+    for i, n in enumerate((30, 30, 40, 10, 30, 30)):
+        segs[i] = L.sgr_adam_segment(one, None, one, one, n, 0.0, 1.0)
+    segs[5].n = 29  # k n = 30 expected
+    assert lib.sgr_render_backward_gather_adam(gw, cams, 1, cfg, 100, segs, 1e-3, 0.9, 0.999, 1e-8, 1,
+                                               addr, size, None) == L.SGR_EINVAL
     one = ctypes.c_void_p(256)  # never dereferenced: each call below returns before any device work
     assert L.sgr_score_maps_noalloc(one, one, 0, 4, 16, one, one, None) == L.SGR_EINVAL
     assert L.sgr_score_maps_noalloc(one, one, 4, 4, 0, one, one, None) == L.SGR_EINVAL

@@ -154,3 +154,50 @@ def test_large_scene_two_portrait_keyframes():
         bad |= view.excluded()
         vis |= view.pr["visible"] == 1
     print("large scene report", reps, U.compare_grads(got, want, bad, visible=vis), flush=True)
+
+
+def test_gather_with_adam_equals_gather_then_adam():
+    """The gather with the Adam step fused (sgr_render_backward_gather_adam)
+    gives, bit for bit, the parameters and moments of the gather followed by
+    sgr_adam_step, over two mapping iterations of a 200k room (the second
+    starts from nonzero moments)."""
+    from paper_2506_00225_amd import FusedAdam
+    _say("gather + Adam fused vs separate, 200k")
+    sc = scenes.room_scene(n=200_000)
+    cam = sc.cameras[0]
+    P = cam.width * cam.height
+    g0, fr = _bench_frame(sc, [cam])
+    dev = g0.means.device
+    label = torch.from_numpy(sc.targets["label"]).to(dev).reshape(P).int().contiguous()
+    targets = {"rgb": torch.from_numpy(sc.targets["rgb"]).to(dev).reshape(P, 3),
+               "depth": torch.from_numpy(sc.targets["depth"]).to(dev).reshape(P), "label": label}
+    names = ("means", "scales", "quats", "opacity", "rgb", "sem_val")
+    inf = float("inf")
+    clamp = {"opacity": (1e-4, 0.9999), "sem_val": (0.0, inf)}
+    runs = []
+    for fused in (False, True):
+        g = Gaussians(*[getattr(g0, nm).clone() for nm in names], g0.sem_idx)
+        gout = {nm: torch.empty_like(getattr(g, nm)) for nm in names}
+        opt = FusedAdam([(getattr(g, nm), gout[nm], *clamp.get(nm, (-inf, inf))) for nm in names], lr=1e-3)
+        grads_in = {"rgb": torch.empty(P, 3, device=dev), "depth": torch.empty(P, device=dev),
+                    "sil": torch.empty(P, device=dev), "sem_at_label": torch.empty(P, device=dev),
+                    "sem_label": label}
+        for _ in range(2):
+            fr.project(g)
+            fr.bin(g)
+            fr.forward_loss(g, targets, loss_config(), grads=grads_in)
+            fr.backward_tiles(g, grads_in)
+            if fused:
+                fr.backward_gather_adam(g, opt)
+            else:
+                fr.backward_gather(g, gout)
+                opt.step()
+        torch.cuda.synchronize()
+        assert fr.status()[0] == 0
+        runs.append(([getattr(g, nm).clone() for nm in names], [m.clone() for m in opt.m], [v.clone() for v in opt.v]))
+    (pa, ma, va), (pb, mb, vb) = runs
+    for nm, x, y in zip(names, pa, pb):
+        assert torch.equal(x, y), nm
+    for nm, x, y in zip(names + names, ma + va, mb + vb):
+        assert torch.equal(x, y), nm
+    assert not torch.equal(pa[0], g0.means)  # the step did move the means
