@@ -140,10 +140,16 @@ __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ k
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * TILE;
-#pragma unroll 4
+    uint32_t kr[ITEMS];
+#pragma unroll
     for (int r = 0; r < ITEMS; r++) {
         const uint32_t i = base + r * 256 + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & ((1u << dbits) - 1u)], 1u);
+        kr[r] = i < n ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) {
+        const uint32_t i = base + r * 256 + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(kr[r] >> shift) & ((1u << dbits) - 1u)], 1u);
     }
     __syncthreads();
     const uint32_t bins = 1u << dbits;
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ k
     }
 }
 
-// Stable scatter of one 8-bit digit.  Items are taken in index order, 256
+// Stable scatter of one digit of at most 8 bits.  Items are taken in index order, 256
 // per round; within a wave the rank among equal digits comes from eight
 // ballots, across the four waves from per-digit wave counts in LDS.
 // SCANNED: hist holds the exclusive scan over (digit, block).  Otherwise it
@@ -195,11 +201,26 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t base = blockIdx.x * TILE;
+    // With few workgroups (the small-tile variant), every round's items are
+    // loaded up front, so the rounds (each ends at a barrier) do not each
+    // wait out a global load.  With many, the registers that would take
+    // cost more occupancy than the loads cost time.
+    constexpr bool kPre = !SCANNED;
+    uint32_t kr[kPre ? ITEMS : 1], vr[kPre ? ITEMS : 1];
+    if constexpr (kPre) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; r++) {
+            const uint32_t i = base + r * 256 + tid;
+            kr[r] = i < n ? kin[i] : 0u;
+            vr[r] = i < n ? (vin ? vin[i] : i) : 0u;
+        }
+    }
+#pragma unroll
     for (int r = 0; r < ITEMS; r++) {
         const uint32_t i = base + r * 256 + tid;
         const bool valid = i < n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const uint32_t val = valid ? (vin ? vin[i] : i) : 0u;
+        const uint32_t key = kPre ? kr[r] : (valid ? kin[i] : 0u);
+        const uint32_t val = kPre ? vr[r] : (valid ? (vin ? vin[i] : i) : 0u);
         const uint32_t d = (key >> shift) & mask;
         uint64_t match = __ballot(valid);
 #pragma unroll
@@ -255,18 +276,22 @@ int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* v
         if (few) {
             if (dbits == 8) {
                 radix_hist<true, kRadixItemsSmall, 8><<<nblk_small, 256, 0, st>>>(ki, cs, sh, 8, hist);
-                radix_scatter<false, kRadixItemsSmall, 8><<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist);
+                radix_scatter<false, kRadixItemsSmall, 8>
+                    <<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist);
             } else {
                 radix_hist<true, kRadixItemsSmall, 0><<<nblk_small, 256, 0, st>>>(ki, cs, sh, dbits, hist);
-                radix_scatter<false, kRadixItemsSmall, 0><<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits,
-                                                                                   hist);
+                radix_scatter<false, kRadixItemsSmall, 0>
+                    <<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist);
             }
         } else {
             if (dbits == 8) radix_hist<false, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, cs, sh, 8, hist);
             else radix_hist<false, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, cs, sh, dbits, hist);
             scan_exclusive(hist, hist, hs, bins * nblk_max, partial, nullptr, 0, nullptr, st);
-            if (dbits == 8) radix_scatter<true, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist);
-            else radix_scatter<true, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist);
+            if (dbits == 8)
+                radix_scatter<true, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist);
+            else
+                radix_scatter<true, kRadixItems, 0>
+                    <<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist);
         }
         uint32_t* t;
         t = ki; ki = ko; ko = t;
