@@ -148,7 +148,8 @@ typedef struct {
     size_t sorted_rec;      /* 3 x float4 [V*n]: compositing record of each visible pair, front to back */
     size_t sorted_keys;     /* uint32 [key_capacity]: global tile id, sorted */
     size_t sorted_vals;     /* uint32 [key_capacity]: emission index of each sorted key */
-    size_t sorted_gauss;    /* uint32 [key_capacity]: front-to-back index of each sorted key */
+    size_t key_owner;       /* uint32 [key_capacity]: front-to-back index of the pair that emitted key e
+                               (sorted key s belongs to pair key_owner[sorted_vals[s]]) */
     size_t ranges;          /* uint32 [num_tiles][2]: [start, end) per global tile */
     size_t tile_offsets;    /* uint32 [V*n]: first emission index of each visible pair */
     int64_t num_tiles;      /* sum over views of tiles_x * tiles_y */

@@ -110,7 +110,6 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     P->vals1 = take(4 * caps);
     P->owner = take(4 * caps);
     P->heads = take(4 * (caps / kKeyChunk + 2));
-    P->sgp = take(4 * caps);
     P->ranges = take(8 * (size_t)tiles);
     const uint32_t big = (uint32_t)std::max<int64_t>(vn, cap);
     const size_t hist_words = radix_hist_words(big);
@@ -289,7 +288,7 @@ sgr_status sgr_workspace_layout(int64_t n, const sgr_camera* cams, int32_t num_v
     out->order = P.order;
     out->sorted_keys = P.sorted_keys;
     out->sorted_vals = P.sorted_vals;
-    out->sorted_gauss = P.sgp;
+    out->key_owner = P.owner;
     out->ranges = P.ranges;
     out->tile_offsets = P.toff;
     out->num_tiles = P.num_tiles;

@@ -415,19 +415,15 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
     }
 }
 
-// [start, end) of every non-empty tile, and the front-to-back index of each
-// sorted key.
-__global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ skeys,
-                                                   const uint32_t* __restrict__ svals,
-                                                   const uint32_t* __restrict__ owner, uint32_t* __restrict__ sgp,
-                                                   uint2* __restrict__ ranges, const uint32_t* __restrict__ counters,
-                                                   uint32_t cap) {
+// [start, end) of every non-empty tile.  (The compositing kernels find the
+// pair of sorted key s as owner[svals[s]], inside their staging prefetch.)
+__global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ skeys, uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ counters, uint32_t cap) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const uint32_t K = min(counters[kKeysLo], cap);
     if (counters[kStatus] & SGR_ECAPACITY) return;
     if (s >= K) return;
     const uint32_t key = skeys[s];
-    sgp[s] = owner[svals[s]];
     if (s == 0 || skeys[s - 1] != key) ranges[key].x = s;
     if (s == K - 1 || skeys[s + 1] != key) ranges[key].y = s + 1;
 }
@@ -519,9 +515,8 @@ sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t 
                                   (uint32_t*)(ws + P.vals1), true, device_count(counters + kKeysLo, (uint32_t)P.cap),
                                   (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits);
     if (passes != P.tile_passes) return SGR_EUNSUPPORTED;
-    tile_ranges<<<(unsigned)div_up(P.cap, 256), 256, 0, st>>>(
-        (const uint32_t*)(ws + P.sorted_keys), (const uint32_t*)(ws + P.sorted_vals), (const uint32_t*)(ws + P.owner),
-        (uint32_t*)(ws + P.sgp), (uint2*)(ws + P.ranges), counters, (uint32_t)P.cap);
+    tile_ranges<<<(unsigned)div_up(P.cap, 256), 256, 0, st>>>((const uint32_t*)(ws + P.sorted_keys),
+                                                              (uint2*)(ws + P.ranges), counters, (uint32_t)P.cap);
     if (d_num_keys) publish_num_keys<<<1, 1, 0, st>>>(counters, d_num_keys);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }

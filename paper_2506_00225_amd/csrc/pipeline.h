@@ -33,7 +33,7 @@ struct Plan {
     bool ranked = false;
     size_t srk = 0;
     size_t sorig = 0;  // original list index of each stored top-k position [vis][kpad] (bytes)
-    size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, sgp = 0, ranges = 0, heads = 0;
+    size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, ranges = 0, heads = 0;
     size_t sorted_keys = 0, sorted_vals = 0;
     size_t hist = 0, partial = 0;
     size_t pix_T = 0, pix_last = 0;

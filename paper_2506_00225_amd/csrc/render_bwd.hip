@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
     };
     auto fetch = [&](uint32_t f0, int fn) {
         if (rl >= fn) return;
-        const uint32_t g = a.sgp[f0 + rl];
+        const uint32_t e = b.svals[f0 + rl], g = a.owner[e];  // emission index, pair
         if (role == 0) {
             const float4* rp = (const float4*)(a.srec + g);
             put4(0, rp[0]);
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
             const float4* rp = (const float4*)(a.srec + g);
             put4(0, rp[2]);
             put4(4, a.scol[g]);
-            stg[8] = b.svals[f0 + rl];
+            stg[8] = e;
         } else if constexpr (RANKED) {
             // wave 2: the class words and the rank -> position nibbles; wave 3: the mask
             const uint32_t* rk = a.srk + (size_t)g * kRankWords;

@@ -113,7 +113,7 @@ struct TileArgs {
     int64_t num_tiles;
     int k, kpad, C;
     const uint2* ranges;
-    const uint32_t* sgp;
+    const uint32_t *svals, *owner;  // the pair of sorted key s: owner[svals[s]]
     const Proj* srec;
     const float4* scol;
     const float* ssv;

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void render_fwd_dense_kernel(DenseArgs d) {
         if (__builtin_amdgcn_readfirstlane(__syncthreads_count(done)) == kBlock) break;
         const int nb = (int)min((uint32_t)kDenseBatch, end - b0);
         if (tid < nb) {
-            const uint32_t g = a.sgp[b0 + tid];
+            const uint32_t g = a.owner[a.svals[b0 + tid]];
             const Proj p = a.srec[g];
             s_r0[tid] = p.r0;
             s_r1[tid] = p.r1;

@@ -130,7 +130,7 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
     auto fetch = [&](uint32_t f0, int fn) {
         if (tid < kFwdBatch) {
             if (tid < fn) {
-                const uint32_t g = a.sgp[f0 + tid];
+                const uint32_t g = a.owner[a.svals[f0 + tid]];
                 const float4* rp = (const float4*)(a.srec + g);
                 const float4 r[4] = {rp[0], rp[1], rp[2], a.scol[g]};
 #pragma unroll
@@ -142,7 +142,7 @@ __device__ __forceinline__ void composite_tile(const TileArgs& a, int gt, float*
                 }
             }
         } else if (SEM != 0 && tid - kFwdBatch < fn) {
-            const uint32_t g = a.sgp[f0 + tid - kFwdBatch];
+            const uint32_t g = a.owner[a.svals[f0 + tid - kFwdBatch]];
             const float* sv = a.ssv + (size_t)g * k;
             if constexpr (KT > 0 && (KT & 3) == 0) {
 #pragma unroll
@@ -928,7 +928,8 @@ TileArgs make_tile_args(const Plan& P, char* ws) {
     a.kpad = P.kpad;
     a.C = P.C;
     a.ranges = (const uint2*)(ws + P.ranges);
-    a.sgp = (const uint32_t*)(ws + P.sgp);
+    a.svals = (const uint32_t*)(ws + P.sorted_vals);
+    a.owner = (const uint32_t*)(ws + P.owner);
     a.srec = (const Proj*)(ws + P.srec);
     a.scol = (const float4*)(ws + P.scol);
     a.ssv = (const float*)(ws + P.ssv);

@@ -39,7 +39,8 @@ def gpu_keys(fr):
     K = int(c[5])
     nvis = int(c[1])
     gt = ws_u32(fr, lay.sorted_keys, K).astype(np.int64)
-    sgp = ws_u32(fr, lay.sorted_gauss, K).astype(np.int64)
+    svals = ws_u32(fr, lay.sorted_vals, K).astype(np.int64)
+    sgp = ws_u32(fr, lay.key_owner, K).astype(np.int64)[svals]
     order = ws_u32(fr, lay.order, nvis).astype(np.int64)
     zb = ws_u32(fr, lay.proj_zbits, lay.vn).astype(np.int64)
     lin = order[sgp]

@@ -70,7 +70,7 @@ def test_workspace_size_valid_and_layout(L):
     assert lay.num_pixels == 64 * 48 + 160 * 120
     assert lay.vn == 2000
     offs = [lay.views, lay.proj_count, lay.proj_zbits, lay.sorted_rec, lay.order, lay.sorted_keys, lay.sorted_vals,
-            lay.sorted_gauss, lay.ranges, lay.tile_offsets]
+            lay.key_owner, lay.ranges, lay.tile_offsets]
     assert all(o % 256 == 0 and 0 < o < size for o in offs)
 
 
