@@ -615,6 +615,57 @@ def cpu_baseline(sc, rows=None, min_s=10.0):
                       f", all {sc.n} Gaussians projected each time; {B} blends in {t:.2f} s"}
 
 
+def oracle_legs(out):
+    """The FP64 oracle (as it stands) on the other workloads, on the host
+    threads, beside the GPU figures of the same legs: the 64x64 forward
+    (repeated to about 1 s), the 200k forward + backward of the full
+    keyframe, one 1024x1280 keyframe of the 3M scene forward + backward,
+    and the first 8 of the 64 candidate views scored (forward + entropy)."""
+    from oracle import oracle as O
+    from paper_2506_00225_amd import scenes
+    cfg = O.config_array()
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    res = {}
+
+    def grads_for(cam, C, seed):
+        rng = np.random.default_rng(seed)
+        h, w = cam.height, cam.width
+        return {"rgb": rng.standard_normal((h, w, 3)), "depth": rng.standard_normal((h, w)),
+                "sil": rng.standard_normal((h, w)), "sem": rng.standard_normal((h, w, C))}
+
+    sc = scenes.tiny_scene()
+    reps, t = 0, 0.0
+    while reps < 200 and (reps == 0 or t < 1.0):
+        t0 = time.perf_counter()
+        _, mp = O.forward(O.scene_arrays(sc), sc.cameras[0], cfg, sc.num_classes)
+        t += time.perf_counter() - t0
+        reps += 1
+    B = int(mp["n_contrib"].sum())
+    res["forward_64x64_2k"] = {"ms": round(t / reps * 1e3, 3), "blends": B, "sample": f"{reps} forward passes"}
+    for name, sc, cam in (("fwd_bwd_200k_1200x680", scenes.room_scene(n=200_000, targets=False), None),
+                          ("large_3m_8x1024x1280", scenes.large_scene(), None)):
+        cam = sc.cameras[0]
+        gr = grads_for(cam, sc.num_classes, 1)
+        t0 = time.perf_counter()
+        pr, mp = O.forward(O.scene_arrays(sc), cam, cfg, sc.num_classes)
+        O.backward(O.scene_arrays(sc), cam, cfg, sc.num_classes, gr, proj=pr)
+        t = time.perf_counter() - t0
+        B = int(mp["n_contrib"].sum())
+        res[name] = {"ms": round(t * 1e3, 1), "blends": B, "blends_per_s": round(B / t, 1),
+                     "sample": f"forward + backward of one {cam.width}x{cam.height} keyframe, all {sc.n} Gaussians"}
+        del mp, gr
+    sc = scenes.candidate_scene(n=500_000, nviews=64)
+    t0 = time.perf_counter()
+    for cam in sc.cameras[:8]:
+        _, mp = O.forward(O.scene_arrays(sc), cam, cfg, sc.num_classes)
+        O.score(mp, sc.num_classes)
+    t = time.perf_counter() - t0
+    res["score_64_views"] = {"views_per_s": round(8 / t, 2), "sample": "the first 8 of the 64 candidate views"}
+    for k_, v in res.items():
+        v["cores"] = threads
+    out["oracle_legs"] = res
+
+
 def cpu_info():
     model = None
     try:
@@ -688,6 +739,9 @@ def main():
         one = cpu_baseline_one_thread(sc.n, rows=68)
         if one is not None:
             cpu["one_thread"] = {"value": one["value"], "unit": one["unit"], "sample": one["sample"]}
+        if not args.no_configs:
+            log("oracle on the other workloads")
+            oracle_legs(out)
     dom, roof = roofline(out)
     value = out["blends"] / (out["step_ms"] * 1e-3)
     line = {
@@ -713,7 +767,7 @@ def main():
     for key in ("views_per_s_batched", "views_per_s_graph", "views_per_s_plain", "score_batched_ms", "score_graph_ms",
                 "score_graph_equal", "score_plain_ms",
                 "score_max_mean_entropy_diff", "score_n_empty_equal", "score_views", "plan", "dense_vs_sparse",
-                "configs"):
+                "configs", "oracle_legs"):
         if key in out:
             line[key] = out[key]
     tuned = {k: out[k]["chosen"] for k in ("autotune_mapping", "autotune_score") if k in out and "chosen" in out[k]}
