@@ -406,7 +406,7 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
                 const float Tf = T * rom;  // transmittance in front of this Gaussian
                 const float w = act ? alpha * Tf : 0.f;  // blend weight; 0 where this pixel does not blend
                 float e = col.x * gC0 + col.y * gC1 + col.z * gC2 + col.w * gD + gS;
-                if (b.semgeo) e += es;
+                if (!RANKED && b.semgeo) e += es;  // (the ranked kernel runs only with semgeo off)
                 const float dalpha = Tf * e - R * rom;
                 if (act) {
                     T = Tf;
