@@ -144,14 +144,16 @@ typedef struct {
     size_t views;           /* per-view device table */
     size_t proj_count;      /* uint32 [V*n]: tiles touched per (view, Gaussian); 0 = culled */
     size_t proj_zbits;      /* uint32 [V*n]: bits of fp32 camera-space z */
-    size_t order;           /* uint32 [V*n]: (view*n + id) of each visible pair, front to back */
-    size_t sorted_rec;      /* 3 x float4 [V*n]: compositing record of each visible pair, front to back */
+    size_t pair_rec;        /* 3 x float4 [V*n]: compositing record of each visible pair; records are
+                               numbered in (view, Gaussian id) order */
+    size_t pair_lin;        /* uint32 [V*n]: (view*n + id) of each record */
+    size_t order;           /* uint32 [V*n]: record of each visible pair, front to back (depth rank) */
     size_t sorted_keys;     /* uint32 [key_capacity]: global tile id, sorted */
     size_t sorted_vals;     /* uint32 [key_capacity]: emission index of each sorted key */
-    size_t key_owner;       /* uint32 [key_capacity]: front-to-back index of the pair that emitted key e
-                               (sorted key s belongs to pair key_owner[sorted_vals[s]]) */
+    size_t key_owner;       /* uint32 [key_capacity]: record of the pair that emitted key e
+                               (sorted key s belongs to record key_owner[sorted_vals[s]]) */
     size_t ranges;          /* uint32 [num_tiles][2]: [start, end) per global tile */
-    size_t tile_offsets;    /* uint32 [V*n]: first emission index of each visible pair */
+    size_t tile_offsets;    /* uint32 [V*n]: first emission index of each visible pair, by depth rank */
     int64_t num_tiles;      /* sum over views of tiles_x * tiles_y */
     int64_t num_pixels;     /* sum over views of W * H */
     int64_t vn;             /* V * n */
@@ -173,7 +175,8 @@ sgr_status sgr_workspace_layout(int64_t n, const sgr_camera *cams, int32_t num_v
  * lowpass*I, Sigma3 = Rq diag(s^2) Rq^T; the pixel rectangle is the exact
  * axis-aligned box of {o exp(-Q/2) >= alpha_min}, Q = d^T Sigma2^-1 d,
  * computed in double precision.  Visible pairs are then sorted by (fp32 z
- * bits, Gaussian id) per view and their records gathered in that order.
+ * bits, Gaussian id) per view (their records are built in (view, Gaussian
+ * id) order, and the sort orders record numbers).
  */
 sgr_status sgr_project(const sgr_gaussians *g, const sgr_camera *cams, int32_t num_views, const sgr_config *cfg,
                        int64_t key_capacity, void *workspace, size_t workspace_bytes, void *stream);

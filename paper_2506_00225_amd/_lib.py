@@ -86,8 +86,8 @@ class sgr_sampling(ctypes.Structure):
 
 class sgr_layout(ctypes.Structure):
     _fields_ = [(name, ctypes.c_size_t) for name in (
-        "total_bytes", "counters", "views", "proj_count", "proj_zbits", "order", "sorted_rec", "sorted_keys",
-        "sorted_vals", "key_owner", "ranges", "tile_offsets")] + [
+        "total_bytes", "counters", "views", "proj_count", "proj_zbits", "pair_rec", "pair_lin", "order",
+        "sorted_keys", "sorted_vals", "key_owner", "ranges", "tile_offsets")] + [
         ("num_tiles", ctypes.c_int64), ("num_pixels", ctypes.c_int64), ("vn", ctypes.c_int64)]
 
 

@@ -95,6 +95,7 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     P->vis_k1 = take(4 * vns);
     P->vis_v1 = take(4 * vns);
     P->order = P->vis_v0;  // the 4-pass depth sort ends in the *0 buffers
+    P->pair_lin = take(4 * vns);
     P->srec = take(sizeof(Proj) * vns);
     P->scol = take(16 * vns);
     P->ssv = take(4 * (size_t)P->k * vns);
@@ -103,6 +104,7 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     P->ranked = P->k == 16 && P->C <= 128;
     if (P->ranked) P->srk = take(4 * (size_t)kRankWords * vns);
     P->tcount = take(4 * vns);
+    P->tcount_rec = take(4 * vns);
     P->toff = take(4 * vns);
     P->keys0 = take(4 * caps);
     P->vals0 = take(4 * caps);
@@ -284,7 +286,8 @@ sgr_status sgr_workspace_layout(int64_t n, const sgr_camera* cams, int32_t num_v
     out->views = P.views;
     out->proj_count = P.count;
     out->proj_zbits = P.zbits;
-    out->sorted_rec = P.srec;
+    out->pair_rec = P.srec;
+    out->pair_lin = P.pair_lin;
     out->order = P.order;
     out->sorted_keys = P.sorted_keys;
     out->sorted_vals = P.sorted_vals;

@@ -1,4 +1,5 @@
-// Projection (EWA splat), visibility compaction, depth-ordered gather,
+// Projection (EWA splat), visibility compaction with the compositing records,
+// the depth sort of the records,
 // per-tile key emission and tile ranges.
 #include "pipeline.h"
 #include "sort.h"
@@ -144,79 +145,29 @@ __global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
     a.zbits[lin] = zb;
 }
 
-// --------------------------------------------------------------- compaction
-
-// Writes (depth key, view*n + id) of every visible pair in index order.
-// partial[b] holds block b's count of visible pairs; each workgroup adds up
-// those before it, and the last one writes the total to *total.
-__global__ __launch_bounds__(256) void compact_visible(const uint32_t* __restrict__ count,
-                                                       const uint32_t* __restrict__ zbits, int64_t vn,
-                                                       const uint32_t* __restrict__ partial,
-                                                       uint32_t* __restrict__ out_key, uint32_t* __restrict__ out_val,
-                                                       uint32_t* __restrict__ total) {
-    __shared__ uint32_t wsum[4];
-    __shared__ uint32_t s_before;
-    {
-        uint32_t before = 0;
-        for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) before += partial[b];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
-        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = before;
-        __syncthreads();
-        if (threadIdx.x == 0) s_before = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        __syncthreads();
-    }
-    const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanItems;
-    uint32_t f[kScanItems], s = 0;
-#pragma unroll
-    for (int r = 0; r < kScanItems; r++) {
-        const int64_t i = base + r;
-        f[r] = (i < vn && count[i] != 0u) ? 1u : 0u;
-        s += f[r];
-    }
-    // block exclusive scan
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t x = s;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    uint32_t pre = s_before + x - s;
-    for (int j = 0; j < w; j++) pre += wsum[j];
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) *total = pre + s;  // every visible pair
-#pragma unroll
-    for (int r = 0; r < kScanItems; r++) {
-        if (f[r]) {
-            const int64_t i = base + r;
-            out_key[pre] = zbits[i];
-            out_val[pre] = (uint32_t)i;
-            pre++;
-        }
-    }
-}
-
 // --------------------------------------------------------------- gather
 
-// Gathers the records of visible pairs in front-to-back order g.  Bit 31 of
-// the record's view word flags a Gaussian whose top-k list repeats a class
-// (the LDS-accumulator forward then adds its values one at a time).  The
-// top-k values and classes are stored grouped by accumulator block
-// (grouped_pos); the projection backward undoes the grouping.
+// Record g of the visible pair lin (= view * n + id), built in two halves
+// (build_topk, build_geom).  Bit 31 of the
+// record's view word flags a Gaussian whose top-k list repeats a class (the
+// LDS-accumulator forward then adds its values one at a time).  The top-k
+// values and classes are stored grouped by accumulator block (class /
+// kRegBlock; list order within a block); the projection backward undoes the
+// grouping.  rv and rb are this thread's LDS rows (GATHER_ROW_* below): the
+// stored list is scattered there and read back in order.
+template <int KM>
+struct GatherRow {
+    static constexpr int kVals = KM + 1;               // floats per row (odd: no bank conflicts)
+    static constexpr int kBytes = ((KM + 3) & ~3) + 4;  // class / list-index bytes per row
+};
+
+// The top-k half of record g: stored values, classes, list indices and the
+// class-rank table.  Returns whether the list repeats a class.
 template <int KT>
-__global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
-    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t nv = a.counters[kNumVisible];
-    if (g >= nv) return;
-    const uint32_t lin = a.order[g];
+__device__ __forceinline__ bool build_topk(const GatherArgs& a, uint32_t g, uint32_t lin, float* rv, uint8_t* rc,
+                                           uint8_t* ro) {
     const int v = (int)(lin / (uint64_t)a.n);
     const int64_t i = (int64_t)lin - (int64_t)v * a.n;
-    Proj p;
-    uint32_t zb;
-    project_pair(a.proj, a.proj.views[v], v, i, &zb, &p);
-    a.scol[g] = make_float4(a.rgb[3 * i], a.rgb[3 * i + 1], a.rgb[3 * i + 2], p.r2.z);
     const int k = KT > 0 ? KT : a.k;
     const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
     constexpr int KM = KT > 0 ? KT : kMaxK;
@@ -250,7 +201,8 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
         }
     }
     bool bad = false, dup = false;
-    uint32_t cls[KM], blk[KM];
+    uint32_t cls[KM];
+    uint64_t cnt = 0;  // entries per accumulator block, one byte per block (at most 8 blocks, 32 entries)
 #pragma unroll
     for (int m = 0; m < KM; m++) {
         cls[m] = 0u;
@@ -260,68 +212,61 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
                 bad = true;
                 cls[m] = 0u;
             }
+            cnt += 1ull << (8 * (cls[m] / kRegBlock));
         }
-        blk[m] = cls[m] / kRegBlock;
     }
 #pragma unroll
     for (int m = 0; m < KM; m++)
 #pragma unroll
         for (int q = 0; q < KM; q++)
             if (q < m && m < k) dup |= cls[q] == cls[m];
-    // store grouped by accumulator block
-    float vout[KM];
-    uint32_t cout[KM], oout[KM];
+    // stored position of entry m: the entries of lower blocks (an exclusive
+    // prefix of the byte counts: the multiply adds every lower byte into
+    // each byte, and no byte exceeds 32), then the block's earlier entries
+    uint64_t run = cnt * 0x0101010101010100ull;
+    uint32_t pos[KM];
+    uint32_t* rcw = (uint32_t*)rc;
+    uint32_t* row = (uint32_t*)ro;
 #pragma unroll
-    for (int p = 0; p < KM; p++) {
-        vout[p] = 0.f;
-        cout[p] = 0u;
-        oout[p] = 0u;
-    }
+    for (int w = 0; w < KWM; w++)
+        if (w < kw) { rcw[w] = 0u; row[w] = 0u; }  // padding bytes past k stay 0
 #pragma unroll
     for (int m = 0; m < KM; m++) {
-        const int pos = m < k ? grouped_pos<KM>(blk, k, m) : -1;
-#pragma unroll
-        for (int p = 0; p < KM; p++)
-            if (p == pos) {
-                vout[p] = vin[m];
-                cout[p] = cls[m];
-                oout[p] = (uint32_t)m;
-            }
+        if (m < k) {
+            const uint32_t sh = 8u * (cls[m] / kRegBlock);
+            pos[m] = (uint32_t)(run >> sh) & 0xffu;
+            run += 1ull << sh;
+            rv[pos[m]] = vin[m];
+            rc[pos[m]] = (uint8_t)cls[m];
+            ro[pos[m]] = (uint8_t)m;
+        }
     }
     float* dv = a.ssv + (size_t)g * k;
     if constexpr (KT > 0 && (KT & 3) == 0) {
 #pragma unroll
-        for (int m = 0; m < KT; m += 4) *(float4*)(dv + m) = make_float4(vout[m], vout[m + 1], vout[m + 2], vout[m + 3]);
+        for (int m = 0; m < KT; m += 4) *(float4*)(dv + m) = make_float4(rv[m], rv[m + 1], rv[m + 2], rv[m + 3]);
     } else {
-        for (int m = 0; m < k; m++) dv[m] = vout[m];
+        for (int m = 0; m < k; m++) dv[m] = rv[m];
     }
+    // classes in stored order, and the list index each stored position came
+    // from (the projection backward writes the top-k value gradients back in
+    // list order)
     uint32_t* di = (uint32_t*)(a.ssi + (size_t)g * a.kpad);
-#pragma unroll
-    for (int w = 0; w < KWM; w++) {
-        uint32_t word = 0;
-#pragma unroll
-        for (int b = 0; b < 4; b++)
-            if (4 * w + b < KM) word |= cout[4 * w + b] << (8 * b);
-        if (w < kw) di[w] = word;
-    }
-    // the list index each stored position came from (the projection
-    // backward writes the top-k value gradients back in list order)
     uint32_t* dorig = (uint32_t*)(a.sorig + (size_t)g * a.kpad);
 #pragma unroll
-    for (int w = 0; w < KWM; w++) {
-        uint32_t word = 0;
-#pragma unroll
-        for (int b = 0; b < 4; b++)
-            if (4 * w + b < KM) word |= oout[4 * w + b] << (8 * b);
-        if (w < kw) dorig[w] = word;
-    }
+    for (int w = 0; w < KWM; w++)
+        if (w < kw) {
+            di[w] = rcw[w];
+            dorig[w] = row[w];
+        }
     if constexpr (KT == 16) {
         if (a.srk) {
-            // class-rank table of the stored list (classes < 128 here)
+            // class-rank table of the stored list (classes < 128 here): the
+            // class mask, and for each rank the stored position of its class
             uint32_t mk[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int q = 0; q < 16; q++) {
-                const uint32_t c = cout[q] & 127u;
+            for (int m = 0; m < 16; m++) {
+                const uint32_t c = cls[m] & 127u;
 #pragma unroll
                 for (int w = 0; w < 4; w++) mk[w] |= (c >> 5) == (uint32_t)w ? 1u << (c & 31u) : 0u;
             }
@@ -329,12 +274,12 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
                            n2 = n1 + __builtin_popcount(mk[2]);
             uint64_t perm = 0;
 #pragma unroll
-            for (int q = 0; q < 16; q++) {
-                const uint32_t c = cout[q] & 127u, w = c >> 5;
+            for (int m = 0; m < 16; m++) {
+                const uint32_t c = cls[m] & 127u, w = c >> 5;
                 const uint32_t base = w == 0 ? 0u : (w == 1 ? n0 : (w == 2 ? n1 : n2));
                 const uint32_t mw = w == 0 ? mk[0] : (w == 1 ? mk[1] : (w == 2 ? mk[2] : mk[3]));
                 const uint32_t rank = base + __builtin_popcount(mw & ((1u << (c & 31u)) - 1u));
-                perm |= dup ? 0ull : (uint64_t)q << (4 * (rank & 15u));
+                perm |= dup ? 0ull : (uint64_t)pos[m] << (4 * (rank & 15u));
             }
             uint4* dst = (uint4*)(a.srk + (size_t)g * kRankWords);
             dst[0] = make_uint4(mk[0], mk[1], mk[2], mk[3]);
@@ -342,29 +287,119 @@ __global__ __launch_bounds__(256) void gather_sorted(GatherArgs a) {
         }
     }
     if (bad) atomicOr(&a.counters[kStatus], Plan::kBadIndex);
+    return dup;
+}
+
+// The geometric half of record g: the projection (the compositing record,
+// colour and depth) and the pair's tile count and depth key.
+__device__ __forceinline__ void build_geom(const GatherArgs& a, uint32_t g, uint32_t lin, bool dup) {
+    const int v = (int)(lin / (uint64_t)a.n);
+    const int64_t i = (int64_t)lin - (int64_t)v * a.n;
+    Proj p;
+    uint32_t zb;
+    project_pair(a.proj, a.proj.views[v], v, i, &zb, &p);
+    a.zkeys[g] = zb;
+    a.pair_lin[g] = lin;
+    a.scol[g] = make_float4(a.rgb[3 * i], a.rgb[3 * i + 1], a.rgb[3 * i + 2], p.r2.z);
     p.r2.w = __uint_as_float(__float_as_uint(p.r2.w) | (dup ? 0x80000000u : 0u));
     a.srec[g] = p;
     a.tcount[g] = a.count[lin];
     a.gp_of_lin[lin] = g;
 }
 
+// Compaction of the visible pairs with their records, in (view, Gaussian id)
+// order: a workgroup takes kScanTile consecutive pairs, lists the visible
+// ones in LDS, and builds their records with every lane busy.  Records are
+// numbered in that order (partial[b]: visible pairs of block b; each
+// workgroup adds up those before it), so the parameter reads run forward
+// through memory; the depth sort then orders record numbers.  The last
+// workgroup writes the visible count.
+constexpr int kGatherThreads = 256;
+constexpr int kGatherItems = kScanTile / kGatherThreads;
+
+template <int KT>
+__global__ __launch_bounds__(kGatherThreads, KT > 0 ? 4 : 1) void compact_gather(GatherArgs a) {
+    constexpr int NW = kGatherThreads / 64;
+    __shared__ uint32_t wsum[NW];
+    __shared__ uint32_t s_before, s_nloc;
+    __shared__ uint32_t s_lin[kScanTile];
+    constexpr int KM = KT > 0 ? KT : kMaxK;
+    using Row = GatherRow<KM>;
+    __shared__ float s_rv[kGatherThreads * Row::kVals];
+    __shared__ __align__(4) uint8_t s_rc[kGatherThreads * Row::kBytes];
+    __shared__ __align__(4) uint8_t s_ro[kGatherThreads * Row::kBytes];
+    __shared__ uint8_t s_dup[kScanTile];
+    const int64_t vn = a.proj.vn;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    {
+        uint32_t before = 0;
+        for (uint32_t b = tid; b < blockIdx.x; b += kGatherThreads) before += a.partial[b];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
+        if (lane == 0) wsum[w] = before;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t t = 0;
+            for (int j = 0; j < NW; j++) t += wsum[j];
+            s_before = t;
+        }
+        __syncthreads();
+    }
+    const int64_t base = blockIdx.x * (int64_t)kScanTile + tid * kGatherItems;
+    uint32_t f[kGatherItems], s = 0;
+#pragma unroll
+    for (int r = 0; r < kGatherItems; r++) {
+        const int64_t i = base + r;
+        f[r] = (i < vn && a.count[i] != 0u) ? 1u : 0u;
+        s += f[r];
+    }
+    // block exclusive scan of the flags
+    uint32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t pre = x - s;
+    for (int j = 0; j < w; j++) pre += wsum[j];
+    if (tid == kGatherThreads - 1) {
+        s_nloc = pre + s;
+        if (blockIdx.x == gridDim.x - 1) a.counters[kNumVisible] = s_before + pre + s;  // every visible pair
+    }
+#pragma unroll
+    for (int r = 0; r < kGatherItems; r++)
+        if (f[r]) s_lin[pre++] = (uint32_t)(base + r);
+    __syncthreads();
+    const uint32_t nloc = s_nloc, before = s_before;
+    // two passes over this thread's records (the same ones in both), each
+    // with fewer live registers than one pass that did both halves
+    for (uint32_t j = tid; j < nloc; j += kGatherThreads)
+        s_dup[j] = build_topk<KT>(a, before + j, s_lin[j], s_rv + tid * Row::kVals, s_rc + tid * Row::kBytes,
+                                  s_ro + tid * Row::kBytes) ? 1 : 0;
+    for (uint32_t j = tid; j < nloc; j += kGatherThreads) build_geom(a, before + j, s_lin[j], s_dup[j] != 0);
+}
+
 // --------------------------------------------------------------- keys
 
-// Keys are emitted in chunks of kKeyChunk consecutive keys, one chunk per
-// workgroup, so a pair near the camera that covers thousands of tiles is
-// spread over many workgroups.  The scan of the pairs' key counts records,
-// for every chunk, the visible pair that owns its first key (pair g owns keys
-// [toff[g], toff[g] + tcount[g])) in heads.
+// Keys are emitted in depth order, in chunks of kKeyChunk consecutive keys,
+// one chunk per workgroup, so a pair near the camera that covers thousands
+// of tiles is spread over many workgroups.  The scan of the pairs' key counts
+// records, for every chunk, the depth rank of the pair that owns its first
+// key (the pair at depth rank r, record order[r], owns keys [toff[r], toff[r]
+// + tcount[r])) in heads.
 
 // Workgroup q emits keys [q C, q C + C) (C = kKeyChunk): the pairs that own
-// them, heads[q] onwards, go to LDS (offsets and tile rectangle), and each
-// key finds its owner by binary search there.  A pair owns at least one key,
-// so at most C + 1 pairs meet a chunk; longer runs (pairs with none) are
-// taken in windows of that size.
+// them, heads[q] onwards, go to LDS (offsets, tile rectangle and record),
+// and each key finds its owner by binary search there.  A pair owns at least
+// one key, so at most C + 1 pairs meet a chunk; longer runs (pairs with none)
+// are taken in windows of that size.  owner[e] is the record of key e's
+// pair.
 __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
     constexpr int W = kKeyChunk + 1;
     __shared__ uint32_t off[W + 1];
-    __shared__ int32_t info[W][3];  // first global tile of the rect, rect width in tiles, view width in tiles
+    __shared__ int32_t info[W][4];  // first global tile of the rect, rect width in tiles, view width in tiles, record
     const uint32_t nv = a.counters[kNumVisible];
     const uint64_t K = min((uint64_t)a.counters[kKeysLo], (uint64_t)a.cap);
     const uint64_t e0 = (uint64_t)blockIdx.x * kKeyChunk;
@@ -378,8 +413,8 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
         // window of pairs [w0, w0 + nw)
         const uint32_t nw = min((uint32_t)W, wend - w0);
         for (uint32_t i = threadIdx.x; i < nw; i += 256) {
-            const uint32_t g = w0 + i;
-            off[i] = a.toff[g];
+            const uint32_t r = w0 + i, g = a.order[r];
+            off[i] = a.toff[r];
             const float4 r2 = a.srec[g].r2;
             const uint32_t rx = __float_as_uint(r2.x), ry = __float_as_uint(r2.y);
             const int v = __float_as_int(r2.w) & 0x7fffffff;
@@ -389,7 +424,8 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
             info[i][0] = vw.tile_off + ty0 * vw.tiles_x + tx0;
             info[i][1] = tx1 - tx0 + 1;
             info[i][2] = vw.tiles_x;
-            if (i == nw - 1) off[nw] = a.toff[g] + a.tcount[g];
+            info[i][3] = (int32_t)g;
+            if (i == nw - 1) off[nw] = a.toff[r] + a.tcount[r];
         }
         __syncthreads();
         // keys of this chunk owned by the window's pairs
@@ -405,7 +441,7 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
             const uint32_t wdt = (uint32_t)info[lo][1];
             const uint32_t gt = (uint32_t)info[lo][0] + (local / wdt) * (uint32_t)info[lo][2] + local % wdt;
             a.keys[e] = gt;
-            a.owner[e] = w0 + lo;
+            a.owner[e] = (uint32_t)info[lo][3];
         }
         // the same for every thread: taken as a scalar, so the loop exit is uniform
         const int more = __builtin_amdgcn_readfirstlane((uint64_t)off[nw] < e1 && w0 + nw < wend ? 1 : 0);
@@ -466,31 +502,34 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
     pa.gp_of_lin = (uint32_t*)(ws + P.gp_of_lin);
     if (P.vn == 0) return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
     project_kernel<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(pa);
-    // compaction of visible pairs, then the depth sort
+    // compaction of visible pairs with their records, then the depth sort
+    // of record numbers
     uint32_t* partial = (uint32_t*)(ws + P.partial);
-    {
-        const uint32_t nblk = (uint32_t)div_up(P.vn, kScanTile);
-        scan_flag_sums(pa.count, (uint32_t)P.vn, partial, st);
-        compact_visible<<<nblk, 256, 0, st>>>(pa.count, pa.zbits, P.vn, partial, (uint32_t*)(ws + P.vis_k0),
-                                              (uint32_t*)(ws + P.vis_v0), counters + kNumVisible);
-    }
-    const int passes = radix_sort((uint32_t*)(ws + P.vis_k0), (uint32_t*)(ws + P.vis_v0), (uint32_t*)(ws + P.vis_k1),
-                                  (uint32_t*)(ws + P.vis_v1), false, device_count(counters + kNumVisible, 0),
-                                  (uint32_t)P.vn, 32, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits);
-    // 32 bits in 4 (8-bit digits) or 6 (6-bit digits) passes: the result is
-    // back in the *0 buffers (P.order)
-    if (passes & 1) return SGR_EUNSUPPORTED;
     GatherArgs ga;
-    ga.order = (const uint32_t*)(ws + P.order); ga.proj = pa; ga.count = pa.count;
+    ga.partial = partial; ga.proj = pa; ga.count = pa.count;
     ga.rgb = g->rgb; ga.sem_val = g->sem_val; ga.sem_idx = g->sem_idx;
     ga.n = P.n; ga.k = P.k; ga.kpad = P.kpad; ga.C = P.C; ga.counters = counters;
     ga.srec = (Proj*)(ws + P.srec); ga.scol = (float4*)(ws + P.scol); ga.ssv = (float*)(ws + P.ssv);
     ga.ssi = (uint8_t*)(ws + P.ssi); ga.srk = P.ranked ? (uint32_t*)(ws + P.srk) : nullptr;
-    ga.sorig = (uint8_t*)(ws + P.sorig); ga.tcount = (uint32_t*)(ws + P.tcount); ga.gp_of_lin = pa.gp_of_lin;
-    const unsigned ggrid = (unsigned)div_up(P.vn, 256);
-    if (P.k == 16) gather_sorted<16><<<ggrid, 256, 0, st>>>(ga);
-    else if (P.k == 3) gather_sorted<3><<<ggrid, 256, 0, st>>>(ga);
-    else gather_sorted<0><<<ggrid, 256, 0, st>>>(ga);
+    ga.sorig = (uint8_t*)(ws + P.sorig); ga.tcount = (uint32_t*)(ws + P.tcount_rec); ga.gp_of_lin = pa.gp_of_lin;
+    ga.pair_lin = (uint32_t*)(ws + P.pair_lin); ga.zkeys = (uint32_t*)(ws + P.vis_k0);
+    {
+        const uint32_t nblk = (uint32_t)div_up(P.vn, kScanTile);
+        scan_flag_sums(pa.count, (uint32_t)P.vn, partial, st);
+        if (P.k == 16) compact_gather<16><<<nblk, kGatherThreads, 0, st>>>(ga);
+        else if (P.k == 3) compact_gather<3><<<nblk, kGatherThreads, 0, st>>>(ga);
+        else compact_gather<0><<<nblk, kGatherThreads, 0, st>>>(ga);
+    }
+    // (fp32 depth bits, record) pairs; records are numbered in id order, so
+    // a stable sort on the bits alone gives the (depth, id) order.  32 bits
+    // in 4 (8-bit digits) or 6 (6-bit digits) passes: the record numbers end
+    // in the *0 buffers (P.order).  The last pass also writes each pair's
+    // tile count by depth rank.
+    const int passes = radix_sort((uint32_t*)(ws + P.vis_k0), (uint32_t*)(ws + P.vis_v0), (uint32_t*)(ws + P.vis_k1),
+                                  (uint32_t*)(ws + P.vis_v1), true, device_count(counters + kNumVisible, 0),
+                                  (uint32_t)P.vn, 32, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits,
+                                  ga.tcount, (uint32_t*)(ws + P.tcount));
+    if (passes & 1) return SGR_EUNSUPPORTED;
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
 }
 
@@ -499,14 +538,15 @@ sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t 
     uint32_t* partial = (uint32_t*)(ws + P.partial);
     uint32_t* tcount = (uint32_t*)(ws + P.tcount);
     uint32_t* toff = (uint32_t*)(ws + P.toff);
-    // per-pair key offsets; the total is the key count K.  The scan also
-    // records, for every chunk of kKeyChunk keys, the pair that owns its
-    // first key.
+    const uint32_t* order = (const uint32_t*)(ws + P.order);
+    // key offsets of the pairs in depth order; the total is the key count K.
+    // The scan also records, for every chunk of kKeyChunk keys, the depth
+    // rank of the pair that owns its first key.
     scan_exclusive(tcount, toff, device_count(counters + kNumVisible, 0), (uint32_t)P.vn, partial,
                    counters + kKeysLo, (uint32_t)P.cap, counters + kStatus, st, (uint32_t*)(ws + P.heads),
                    (uint32_t)kKeyChunk);
     KeyArgs ka;
-    ka.toff = toff; ka.tcount = tcount; ka.srec = (const Proj*)(ws + P.srec); ka.views = (const ViewDev*)(ws + P.views);
+    ka.toff = toff; ka.tcount = tcount; ka.order = order; ka.srec = (const Proj*)(ws + P.srec); ka.views = (const ViewDev*)(ws + P.views);
     ka.counters = counters; ka.cap = P.cap;
     ka.keys = (uint32_t*)(ws + P.keys0); ka.owner = (uint32_t*)(ws + P.owner);
     ka.heads = (uint32_t*)(ws + P.heads);

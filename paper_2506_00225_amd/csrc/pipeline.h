@@ -26,8 +26,13 @@ struct Plan {
     // byte offsets
     size_t counters = 0, views = 0;
     size_t count = 0, zbits = 0, gp_of_lin = 0;
-    size_t vis_k0 = 0, vis_v0 = 0, vis_k1 = 0, vis_v1 = 0, order = 0;
-    size_t srec = 0, scol = 0, ssv = 0, ssi = 0, tcount = 0, toff = 0;
+    // Records of visible pairs are kept in (view, Gaussian id) order, the
+    // order the compaction finds them in; order[r] is the record of the pair
+    // at depth rank r (front to back, per view), toff is indexed by depth
+    // rank, tcount (tiles touched) both by depth rank and (tcount_rec) by
+    // record, and every record array by record.
+    size_t vis_k0 = 0, vis_v0 = 0, vis_k1 = 0, vis_v1 = 0, order = 0, pair_lin = 0;
+    size_t srec = 0, scol = 0, ssv = 0, ssi = 0, tcount = 0, tcount_rec = 0, toff = 0;
     // class-rank table of each visible pair (kRankWords words), kept when the
     // top-k lists have 16 entries over at most 128 classes
     bool ranked = false;
@@ -71,7 +76,7 @@ struct ProjectArgs {
 };
 
 struct GatherArgs {
-    const uint32_t* order;
+    const uint32_t* partial;  // visible pairs per block of kScanTile (view, Gaussian) pairs
     ProjectArgs proj;
     const uint32_t* count;
     const float *rgb, *sem_val;
@@ -85,11 +90,14 @@ struct GatherArgs {
     uint8_t* ssi;
     uint32_t* srk;  // class-rank table [vis][kRankWords], or nullptr
     uint8_t* sorig; // original list index of each stored position [vis][kpad]
-    uint32_t *tcount, *gp_of_lin;
+    uint32_t *tcount, *gp_of_lin;  // tcount by record
+    uint32_t* pair_lin;  // view * n + id of each record
+    uint32_t* zkeys;     // fp32 depth bits of each record: the depth sort's keys
 };
 
 struct KeyArgs {
-    const uint32_t *toff, *tcount;
+    const uint32_t *toff, *tcount;  // by depth rank
+    const uint32_t* order;          // record of each depth rank
     const Proj* srec;
     const ViewDev* views;
     const uint32_t* counters;

@@ -559,22 +559,26 @@ __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ sl
                                                     const uint8_t* __restrict__ touched,
                                                     const uint32_t* __restrict__ toff,
                                                     const uint32_t* __restrict__ tcount,
+                                                    const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ counters, int nv_rt,
                                                     float* __restrict__ g2d) {
     constexpr int NVMAX = 10 + (KT > 0 ? KT : kMaxK);
     const int NV = KT > 0 ? 10 + KT : nv_rt;
     const uint32_t nvis = counters[kNumVisible];
     const bool ok = !(counters[kStatus] & SGR_ECAPACITY);
-    // Pairs are in depth order, so the nearest ones (the longest segments)
-    // are adjacent; striding pairs across workgroups spreads them over the
-    // machine instead of queueing them in one wave.
-    const uint32_t g = threadIdx.x * gridDim.x + blockIdx.x;
+    // Pairs are taken by depth rank r (their keys are the emission range
+    // [toff[r], toff[r] + tcount[r])), so the nearest ones (the
+    // longest segments) are adjacent; striding ranks across workgroups
+    // spreads them over the machine instead of queueing them in one wave.
+    // The sums go to the pair's record g = order[r].
+    const uint32_t r = threadIdx.x * gridDim.x + blockIdx.x;
     const int lane = threadIdx.x & 63;
-    const bool valid = g < nvis;
-    uint32_t e0 = 0, e1 = 0;
+    const bool valid = r < nvis;
+    uint32_t e0 = 0, e1 = 0, g = 0;
+    if (valid) g = order[r];
     if (valid && ok) {
-        e0 = toff[g];
-        e1 = e0 + tcount[g];
+        e0 = toff[r];
+        e1 = e0 + tcount[r];
     }
     const bool longseg = e1 - e0 > kShortSeg;
     if (valid && !longseg) {
@@ -899,9 +903,10 @@ sgr_status launch_backward_gather(const Plan& P, const sgr_gaussians* g, const s
         const uint32_t* toff = (const uint32_t*)(ws + P.toff);
         const uint32_t* tcount = (const uint32_t*)(ws + P.tcount);
         float* g2d = (float*)(ws + P.g2d);
-        if (P.k == 16) gather_slots<16><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, counters, nvals, g2d);
-        else if (P.k == 3) gather_slots<3><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, counters, nvals, g2d);
-        else gather_slots<0><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, counters, nvals, g2d);
+        const uint32_t* order = (const uint32_t*)(ws + P.order);
+        if (P.k == 16) gather_slots<16><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, order, counters, nvals, g2d);
+        else if (P.k == 3) gather_slots<3><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, order, counters, nvals, g2d);
+        else gather_slots<0><<<ggrid, 256, 0, st>>>(slots, touched, toff, tcount, order, counters, nvals, g2d);
     }
     ProjBwdArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opacity = g->opacity;

@@ -12,7 +12,7 @@ constexpr int kDenseBatch = 64;  // entries per staged batch: one culling ballot
 
 struct DenseArgs {
     TileArgs t;
-    const uint32_t* order;  // front-to-back visible pair -> view * n + Gaussian
+    const uint32_t* pair_lin;  // record of a visible pair -> view * n + Gaussian
     int64_t n;
     const float* dense;     // [n][C]
 };
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void render_fwd_dense_kernel(DenseArgs d) {
             s_r1[tid] = p.r1;
             s_r2[tid] = p.r2;
             s_col[tid] = a.scol[g];
-            const uint32_t lin = d.order[g];
+            const uint32_t lin = d.pair_lin[g];
             s_gid[tid] = (uint32_t)(lin - (uint64_t)(lin / d.n) * d.n);
         }
         __syncthreads();
@@ -147,7 +147,7 @@ sgr_status launch_forward_dense(const Plan& P, const float* dense, const sgr_map
     for (int v = 0; v < P.V; v++)
         mp[v] = MapPtrs{out[v].rgb, out[v].depth, out[v].sil, out[v].sem, out[v].t_final, out[v].n_contrib};
     set_view_table(d.t.maps, mp, ws + P.map_table, st);
-    d.order = (const uint32_t*)(ws + P.order);
+    d.pair_lin = (const uint32_t*)(ws + P.pair_lin);
     d.n = P.n;
     d.dense = dense;
     const size_t lds = dense_lds_bytes(P.C);

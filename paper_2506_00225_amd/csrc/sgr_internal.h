@@ -28,17 +28,8 @@ constexpr int kRankWords = 8;
 
 // Top-k entries are stored grouped by accumulator block (class / 32), in
 // their original order inside a block, so a compositing kernel can walk a
-// Gaussian's classes one register vector at a time.  grouped_pos gives the
-// stored position of entry m; blk[] holds class / 32 of every entry.
-template <int KM>
-__device__ __forceinline__ int grouped_pos(const uint32_t (&blk)[KM], int k, int m) {
-    int p = 0;
-#pragma unroll
-    for (int q = 0; q < KM; q++)
-        if (q < k) p += (blk[q] < blk[m] || (blk[q] == blk[m] && q < m)) ? 1 : 0;
-    return p;
-}
-
+// Gaussian's classes one register vector at a time (the records are built
+// in build_record).
 // counters[] slots at the start of the workspace
 enum Counter : int {
     kStatus = 0,      // bit 1: capacity exceeded

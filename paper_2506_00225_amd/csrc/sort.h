@@ -37,9 +37,10 @@ inline CountSpec device_count(const uint32_t* d, uint32_t cap) { return CountSpe
 // goes to *total_out (if set); total > cap sets SGR_ECAPACITY in *status.
 // With heads set, heads[q] receives the item whose run [out[i], out[i] +
 // in[i]) holds position q * chunk, for every such position below cap.
+// With perm set, item i is in[perm[i]] (out is still indexed by i).
 void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
                     uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st,
-                    uint32_t* heads = nullptr, uint32_t chunk = 0);
+                    uint32_t* heads = nullptr, uint32_t chunk = 0, const uint32_t* perm = nullptr);
 
 // Block sums of (in[i] != 0) over in[0..n): partial[b] is the number of
 // non-zero items in block b (blocks of kScanTile).
@@ -54,10 +55,11 @@ inline int radix_passes(int bits, int max_digit) { return (bits + max_digit - 1)
 // between the a and b buffers.  Returns the pass count
 // (radix_passes(bits, max_digit)): the result is in the a buffers when it is
 // even, else in b.  vals_identity: the a values are not read; value i is
-// taken to be i.
+// taken to be i.  With carry_dst set, carry_dst[i] = carry_src[sorted value
+// i] (written by the last pass).
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
                CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st,
-               int max_digit = 8);
+               int max_digit = 8, const uint32_t* carry_src = nullptr, uint32_t* carry_dst = nullptr);
 
 inline size_t radix_hist_words(uint32_t max_n) {
     return 256u * (size_t)std::max(div_up(max_n, kRadixTile), div_up(max_n, kRadixTileSmall));

@@ -37,7 +37,8 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* wsum, uin
 
 template <bool FLAG>
 __global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restrict__ in, CountSpec cs,
-                                                       uint32_t* __restrict__ partial) {
+                                                       uint32_t* __restrict__ partial,
+                                                       const uint32_t* __restrict__ perm) {
     __shared__ uint32_t wsum[4];
     const uint32_t n = count_of(cs);
     const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restric
     for (int r = 0; r < kScanItems; r++) {
         const uint32_t i = base + r * 256 + threadIdx.x;
         if (i < n) {
-            const uint32_t x = in[i];
+            const uint32_t x = in[perm ? perm[i] : i];
             s += FLAG ? (x != 0u) : x;
         }
     }
@@ -63,12 +64,12 @@ __global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restric
 // block writes the total (and the saturating capacity check).  With `heads`
 // set, the scan is of per-item run lengths, and for every chunk of `chunk`
 // positions below `cap` the item whose run holds the chunk's first position
-// is recorded in heads[chunk index].
+// is recorded in heads[chunk index].  With perm set, item i is in[perm[i]].
 __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec cs,
                                                   const uint32_t* __restrict__ partial, uint32_t* out,
                                                   uint32_t* __restrict__ total_out, uint32_t cap,
                                                   uint32_t* __restrict__ status, uint32_t* __restrict__ heads,
-                                                  uint32_t chunk) {
+                                                  uint32_t chunk, const uint32_t* __restrict__ perm) {
     __shared__ uint32_t wsum[4];
     const uint32_t n = count_of(cs);
     const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec 
 #pragma unroll
     for (int r = 0; r < kScanItems; r++) {
         const uint32_t i = base + r;
-        v[r] = i < n ? in[i] : 0u;
+        v[r] = i < n ? in[perm ? perm[i] : i] : 0u;
         s += v[r];
     }
     uint32_t tot;
@@ -115,11 +116,11 @@ __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec 
 
 void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
                     uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st, uint32_t* heads,
-                    uint32_t chunk) {
+                    uint32_t chunk, const uint32_t* perm) {
     const uint32_t nblk_max = (uint32_t)div_up(max_n, kScanTile);
     if (nblk_max == 0) return;
-    scan_block_sums<false><<<nblk_max, 256, 0, st>>>(in, cs, partial);
-    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out, total_out, cap, status, heads, chunk);
+    scan_block_sums<false><<<nblk_max, 256, 0, st>>>(in, cs, partial, perm);
+    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out, total_out, cap, status, heads, chunk, perm);
 }
 
 // ------------------------------------------------------------------ radix
@@ -166,13 +167,15 @@ __global__ __launch_bounds__(256) void radix_hist(const uint32_t* __restrict__ k
 // holds the raw counts, block-major, and each workgroup forms its own starting offsets:
 // the counts of its digit in earlier blocks plus, over all blocks, the counts
 // of smaller digits (used when there are few blocks; it saves three scan
-// launches per pass).
+// launches per pass).  With cdst set, cdst[out position] = csrc[value]
+// (a value-indexed array carried into sorted order).
 template <bool SCANNED, int ITEMS, int DBITS>
 __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict__ kin,
                                                      const uint32_t* __restrict__ vin,
                                                      uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                      CountSpec cs, int shift, int dbits_rt,
-                                                     const uint32_t* __restrict__ hist) {
+                                                     const uint32_t* __restrict__ hist,
+                                                     const uint32_t* __restrict__ csrc, uint32_t* __restrict__ cdst) {
     const int dbits = DBITS > 0 ? DBITS : dbits_rt;
     constexpr uint32_t TILE = 256u * ITEMS;
     __shared__ uint32_t run[256];
@@ -239,6 +242,7 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
             for (int j = 0; j < w; j++) off += wc[j][d];
             kout[off] = key;
             vout[off] = val;
+            if (cdst) cdst[off] = csrc[val];
         }
         __syncthreads();
         run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
@@ -250,12 +254,12 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
 void scan_flag_sums(const uint32_t* in, uint32_t n, uint32_t* partial, hipStream_t st) {
     const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
     if (nblk == 0) return;
-    scan_block_sums<true><<<nblk, 256, 0, st>>>(in, host_count(n), partial);
+    scan_block_sums<true><<<nblk, 256, 0, st>>>(in, host_count(n), partial, nullptr);
 }
 
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
                CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st,
-               int max_digit) {
+               int max_digit, const uint32_t* carry_src, uint32_t* carry_dst) {
     const uint32_t nblk_max = (uint32_t)div_up(max_n, kRadixTile);
     if (nblk_max == 0) return 0;
     // few: small tiles (more workgroups for a small sort) and offsets formed in the scatter
@@ -273,25 +277,28 @@ int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* v
     for (int p = 0; p < passes; p++) {
         const uint32_t* vin = (p == 0 && vals_identity) ? nullptr : vi;
         const int sh = dbits * p;
+        const bool lastp = p == passes - 1;
+        const uint32_t* cs_ = lastp ? carry_src : nullptr;
+        uint32_t* cd_ = lastp ? carry_dst : nullptr;
         if (few) {
             if (dbits == 8) {
                 radix_hist<true, kRadixItemsSmall, 8><<<nblk_small, 256, 0, st>>>(ki, cs, sh, 8, hist);
                 radix_scatter<false, kRadixItemsSmall, 8>
-                    <<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist);
+                    <<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist, cs_, cd_);
             } else {
                 radix_hist<true, kRadixItemsSmall, 0><<<nblk_small, 256, 0, st>>>(ki, cs, sh, dbits, hist);
                 radix_scatter<false, kRadixItemsSmall, 0>
-                    <<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist);
+                    <<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist, cs_, cd_);
             }
         } else {
             if (dbits == 8) radix_hist<false, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, cs, sh, 8, hist);
             else radix_hist<false, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, cs, sh, dbits, hist);
             scan_exclusive(hist, hist, hs, bins * nblk_max, partial, nullptr, 0, nullptr, st);
             if (dbits == 8)
-                radix_scatter<true, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist);
+                radix_scatter<true, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist, cs_, cd_);
             else
                 radix_scatter<true, kRadixItems, 0>
-                    <<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist);
+                    <<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist, cs_, cd_);
         }
         uint32_t* t;
         t = ki; ki = ko; ko = t;

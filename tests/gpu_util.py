@@ -40,10 +40,10 @@ def gpu_keys(fr):
     nvis = int(c[1])
     gt = ws_u32(fr, lay.sorted_keys, K).astype(np.int64)
     svals = ws_u32(fr, lay.sorted_vals, K).astype(np.int64)
-    sgp = ws_u32(fr, lay.key_owner, K).astype(np.int64)[svals]
-    order = ws_u32(fr, lay.order, nvis).astype(np.int64)
+    rec = ws_u32(fr, lay.key_owner, K).astype(np.int64)[svals]
+    pair_lin = ws_u32(fr, lay.pair_lin, nvis).astype(np.int64)
     zb = ws_u32(fr, lay.proj_zbits, lay.vn).astype(np.int64)
-    lin = order[sgp]
+    lin = pair_lin[rec]
     view = lin // fr.n
     gid = lin % fr.n
     tile_off = np.cumsum([0] + [((c_.width + 15) // 16) * ((c_.height + 15) // 16) for c_ in fr.cam_list])
@@ -55,17 +55,17 @@ def gpu_keys(fr):
 
 def gpu_proj(fr):
     """Projected records of view 0 (indexed by Gaussian id): visible, rect,
-    zbits, tile count, mean2d, conic; taken from the front-to-back records."""
+    zbits, tile count, mean2d, conic; taken from the pairs' records."""
     lay = fr.layout
     n = fr.n
     cnt = ws_u32(fr, lay.proj_count, n)
     zb = ws_u32(fr, lay.proj_zbits, n)
     nvis = int(counters(fr)[1])
-    order = ws_u32(fr, lay.order, nvis).astype(np.int64)
-    srec = fr.ws[lay.sorted_rec:lay.sorted_rec + 48 * nvis].view(torch.float32).cpu().numpy().reshape(nvis, 12)
+    pair_lin = ws_u32(fr, lay.pair_lin, nvis).astype(np.int64)
+    prec = fr.ws[lay.pair_rec:lay.pair_rec + 48 * nvis].view(torch.float32).cpu().numpy().reshape(nvis, 12)
     rec = np.zeros((n, 12), np.float32)
-    mask = order < n  # view 0 only
-    rec[order[mask]] = srec[mask]
+    mask = pair_lin < n  # view 0 only
+    rec[pair_lin[mask]] = prec[mask]
     ri = rec.view(np.int32)
     ru = rec.view(np.uint32)
     # the record holds 0.5 - fraction of the mean (fp32)

@@ -69,8 +69,8 @@ def test_workspace_size_valid_and_layout(L):
     assert lay.num_tiles == 4 * 3 + 10 * 8
     assert lay.num_pixels == 64 * 48 + 160 * 120
     assert lay.vn == 2000
-    offs = [lay.views, lay.proj_count, lay.proj_zbits, lay.sorted_rec, lay.order, lay.sorted_keys, lay.sorted_vals,
-            lay.key_owner, lay.ranges, lay.tile_offsets]
+    offs = [lay.views, lay.proj_count, lay.proj_zbits, lay.pair_rec, lay.pair_lin, lay.order, lay.sorted_keys,
+            lay.sorted_vals, lay.key_owner, lay.ranges, lay.tile_offsets]
     assert all(o % 256 == 0 and 0 < o < size for o in offs)
 
 
