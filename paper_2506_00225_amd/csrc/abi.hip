@@ -117,6 +117,7 @@ sgr_status make_plan(int64_t n, const sgr_camera* cams, int32_t V, const sgr_con
     const size_t hist_words = radix_hist_words(big);
     P->hist = take(4 * hist_words);
     P->partial = take(4 * scan_partial_words(std::max<size_t>(big, hist_words)));
+    P->block_vis = take(4 * (size_t)div_up((int64_t)vns, 256));
     P->pix_T = take(4 * (size_t)pixels);
     P->pix_last = take(4 * (size_t)pixels);
     P->slots = take(4 * (size_t)NV * caps);

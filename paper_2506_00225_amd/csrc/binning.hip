@@ -133,16 +133,31 @@ __device__ __forceinline__ uint32_t project_pair(const ProjectArgs& a, const Vie
 }
 
 // One thread per (view, Gaussian): tile count and depth key only; the
-// compositing record is recomputed later for the visible pairs alone.
-__global__ __launch_bounds__(256) void project_kernel(ProjectArgs a) {
+// compositing record is recomputed later for the visible pairs alone.  Each
+// workgroup also counts its visible pairs (block_vis), which is all the
+// compaction needs for its prefix sums.
+__global__ __launch_bounds__(256, 6) void project_kernel(ProjectArgs a, ViewChunk ch) {
     const int64_t lin = blockIdx.x * 256ll + threadIdx.x;
-    if (lin >= a.vn) return;
-    const int v = (int)(lin / a.n);
-    const int64_t i = lin - (int64_t)v * a.n;
-    a.gp_of_lin[lin] = kInvalid;
-    uint32_t zb;
-    a.count[lin] = project_pair(a, a.views[v], v, i, &zb, nullptr);
-    a.zbits[lin] = zb;
+    if (a.init) {
+        const int64_t nclear = a.num_tiles > kNumCounters ? a.num_tiles : kNumCounters;
+        for (int64_t z = lin; z < nclear; z += (int64_t)gridDim.x * 256) {
+            if (z < kNumCounters) a.counters[z] = 0;
+            if (z < a.num_tiles) a.ranges[z] = make_uint2(0u, 0u);
+        }
+        if (blockIdx.x == 0 && threadIdx.x < ch.count) a.views_out[ch.first + threadIdx.x] = ch.v[threadIdx.x];
+    }
+    uint32_t cnt = 0;
+    if (lin < a.vn) {
+        const int v = (int)(lin / a.n);
+        const int64_t i = lin - (int64_t)v * a.n;
+        a.gp_of_lin[lin] = kInvalid;
+        uint32_t zb;
+        cnt = project_pair(a, a.init ? ch.v[v] : a.views[v], v, i, &zb, nullptr);
+        a.count[lin] = cnt;
+        a.zbits[lin] = zb;
+    }
+    const int nvis = __syncthreads_count(cnt != 0u);
+    if (threadIdx.x == 0) a.block_vis[blockIdx.x] = (uint32_t)nvis;
 }
 
 // --------------------------------------------------------------- gather
@@ -310,8 +325,9 @@ __device__ __forceinline__ void build_geom(const GatherArgs& a, uint32_t g, uint
 // Compaction of the visible pairs with their records, in (view, Gaussian id)
 // order: a workgroup takes kScanTile consecutive pairs, lists the visible
 // ones in LDS, and builds their records with every lane busy.  Records are
-// numbered in that order (partial[b]: visible pairs of block b; each
-// workgroup adds up those before it), so the parameter reads run forward
+// numbered in that order (partial[b]: visible pairs of the projection's
+// block b of 256 pairs; each workgroup adds up those before its own), so
+// the parameter reads run forward
 // through memory; the depth sort then orders record numbers.  The last
 // workgroup writes the visible count.
 constexpr int kGatherThreads = 256;
@@ -332,8 +348,11 @@ __global__ __launch_bounds__(kGatherThreads, KT > 0 ? 4 : 1) void compact_gather
     const int64_t vn = a.proj.vn;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     {
+        // visible pairs before this workgroup's block: the projection's
+        // counts of the 256-pair blocks before it
         uint32_t before = 0;
-        for (uint32_t b = tid; b < blockIdx.x; b += kGatherThreads) before += a.partial[b];
+        const uint32_t nb = blockIdx.x * (kScanTile / 256);
+        for (uint32_t b = tid; b < nb; b += kGatherThreads) before += a.partial[b];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
         if (lane == 0) wsum[w] = before;
@@ -397,14 +416,18 @@ __global__ __launch_bounds__(kGatherThreads, KT > 0 ? 4 : 1) void compact_gather
 // are taken in windows of that size.  owner[e] is the record of key e's
 // pair.
 __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
+    static_assert(kKeyChunk == kRadixTile, "a chunk of keys is a block of the tile sort");
     constexpr int W = kKeyChunk + 1;
     __shared__ uint32_t off[W + 1];
+    __shared__ uint32_t s_hist[256];  // counts of the sort's first digit among this chunk's keys
     __shared__ int32_t info[W][4];  // first global tile of the rect, rect width in tiles, view width in tiles, record
     const uint32_t nv = a.counters[kNumVisible];
     const uint64_t K = min((uint64_t)a.counters[kKeysLo], (uint64_t)a.cap);
     const uint64_t e0 = (uint64_t)blockIdx.x * kKeyChunk;
     if (e0 >= K || nv == 0) return;
     const uint64_t e1 = min(e0 + kKeyChunk, K);
+    const uint32_t dmask = a.hist_bins - 1u;
+    for (uint32_t d = threadIdx.x; d < a.hist_bins; d += 256) s_hist[d] = 0u;  // (read after the loop's barriers)
     uint32_t w0 = a.heads[blockIdx.x];
     // the pairs that own this chunk's keys end with the owner of the next
     // chunk's first key (recorded when that chunk exists)
@@ -442,6 +465,7 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
             const uint32_t gt = (uint32_t)info[lo][0] + (local / wdt) * (uint32_t)info[lo][2] + local % wdt;
             a.keys[e] = gt;
             a.owner[e] = (uint32_t)info[lo][3];
+            atomicAdd(&s_hist[gt & dmask], 1u);
         }
         // the same for every thread: taken as a scalar, so the loop exit is uniform
         const int more = __builtin_amdgcn_readfirstlane((uint64_t)off[nw] < e1 && w0 + nw < wend ? 1 : 0);
@@ -449,6 +473,10 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
         if (!more) break;
         w0 += nw;
     }
+    // this block's first-digit counts (the loop ended at a barrier)
+    const uint32_t nblk = (uint32_t)div_up((int64_t)K, kRadixTile);
+    for (uint32_t d = threadIdx.x; d < a.hist_bins; d += 256)
+        a.hist0[a.hist_block_major ? blockIdx.x * a.hist_bins + d : d * nblk + blockIdx.x] = s_hist[d];
 }
 
 // [start, end) of every non-empty tile.  (The compositing kernels find the
@@ -487,26 +515,34 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
         for (int j = 0; j < ch.count; j++) ch.v[j] = P.view_table[first + j];
         return ch;
     };
-    {
+    // With one chunk of views and host poses (and some pair to project), the
+    // projection launch initialises the frame itself; otherwise a separate
+    // launch does, and further chunks and device poses follow it.
+    const bool fold = P.V <= kViewChunk && !d_poses && P.vn > 0;
+    if (!fold) {
         const int64_t nthreads = std::max<int64_t>(P.num_tiles, kNumCounters);
         init_frame<<<(unsigned)div_up(nthreads, 256), 256, 0, st>>>(counters, (uint2*)(ws + P.ranges), P.num_tiles,
                                                                     chunk(0), views);
+        for (int first = kViewChunk; first < P.V; first += kViewChunk)
+            upload_views<<<1, kViewChunk, 0, st>>>(chunk(first), views);
+        if (d_poses) set_view_poses<<<(unsigned)div_up(P.V, 256), 256, 0, st>>>(views, d_poses, P.V);
     }
-    for (int first = kViewChunk; first < P.V; first += kViewChunk) upload_views<<<1, kViewChunk, 0, st>>>(chunk(first), views);
-    if (d_poses) set_view_poses<<<(unsigned)div_up(P.V, 256), 256, 0, st>>>(views, d_poses, P.V);
     ProjectArgs pa;
     pa.means = g->means; pa.scales = g->scales; pa.quats = g->quats; pa.opacity = g->opacity;
     pa.views = views; pa.n = P.n; pa.vn = P.vn;
     pa.alpha_min = P.cfg.alpha_min; pa.z_near = P.cfg.z_near; pa.lowpass = P.cfg.lowpass;
     pa.count = (uint32_t*)(ws + P.count); pa.zbits = (uint32_t*)(ws + P.zbits);
     pa.gp_of_lin = (uint32_t*)(ws + P.gp_of_lin);
+    pa.block_vis = (uint32_t*)(ws + P.block_vis);
+    pa.init = fold ? 1 : 0;
+    pa.counters = counters; pa.ranges = (uint2*)(ws + P.ranges); pa.num_tiles = P.num_tiles; pa.views_out = views;
     if (P.vn == 0) return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
-    project_kernel<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(pa);
+    project_kernel<<<(unsigned)div_up(P.vn, 256), 256, 0, st>>>(pa, chunk(0));
     // compaction of visible pairs with their records, then the depth sort
     // of record numbers
     uint32_t* partial = (uint32_t*)(ws + P.partial);
     GatherArgs ga;
-    ga.partial = partial; ga.proj = pa; ga.count = pa.count;
+    ga.partial = pa.block_vis; ga.proj = pa; ga.count = pa.count;
     ga.rgb = g->rgb; ga.sem_val = g->sem_val; ga.sem_idx = g->sem_idx;
     ga.n = P.n; ga.k = P.k; ga.kpad = P.kpad; ga.C = P.C; ga.counters = counters;
     ga.srec = (Proj*)(ws + P.srec); ga.scol = (float4*)(ws + P.scol); ga.ssv = (float*)(ws + P.ssv);
@@ -515,7 +551,6 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
     ga.pair_lin = (uint32_t*)(ws + P.pair_lin); ga.zkeys = (uint32_t*)(ws + P.vis_k0);
     {
         const uint32_t nblk = (uint32_t)div_up(P.vn, kScanTile);
-        scan_flag_sums(pa.count, (uint32_t)P.vn, partial, st);
         if (P.k == 16) compact_gather<16><<<nblk, kGatherThreads, 0, st>>>(ga);
         else if (P.k == 3) compact_gather<3><<<nblk, kGatherThreads, 0, st>>>(ga);
         else compact_gather<0><<<nblk, kGatherThreads, 0, st>>>(ga);
@@ -550,10 +585,16 @@ sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t 
     ka.counters = counters; ka.cap = P.cap;
     ka.keys = (uint32_t*)(ws + P.keys0); ka.owner = (uint32_t*)(ws + P.owner);
     ka.heads = (uint32_t*)(ws + P.heads);
+    const RadixFirstPass fp = radix_first_pass((uint32_t)P.cap, P.tile_bits, P.radix_bits);
+    ka.hist0 = (uint32_t*)(ws + P.hist);
+    ka.hist_bins = fp.bins;
+    ka.hist_block_major = fp.block_major;
     if (P.vn > 0) emit_keys<<<(unsigned)div_up(P.cap, kKeyChunk), 256, 0, st>>>(ka);
+    // (with no pair to project there are no keys: the sort's blocks are empty)
     const int passes = radix_sort((uint32_t*)(ws + P.keys0), (uint32_t*)(ws + P.vals0), (uint32_t*)(ws + P.keys1),
                                   (uint32_t*)(ws + P.vals1), true, device_count(counters + kKeysLo, (uint32_t)P.cap),
-                                  (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits);
+                                  (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits,
+                                  nullptr, nullptr, P.vn > 0);
     if (passes != P.tile_passes) return SGR_EUNSUPPORTED;
     tile_ranges<<<(unsigned)div_up(P.cap, 256), 256, 0, st>>>((const uint32_t*)(ws + P.sorted_keys),
                                                               (uint2*)(ws + P.ranges), counters, (uint32_t)P.cap);

@@ -41,6 +41,7 @@ struct Plan {
     size_t keys0 = 0, vals0 = 0, keys1 = 0, vals1 = 0, owner = 0, ranges = 0, heads = 0;
     size_t sorted_keys = 0, sorted_vals = 0;
     size_t hist = 0, partial = 0;
+    size_t block_vis = 0;  // visible pairs per block of 256 (view, Gaussian) pairs
     size_t pix_T = 0, pix_last = 0;
     size_t slots = 0, touched = 0, g2d = 0;
     size_t tile_part = 0;
@@ -73,10 +74,20 @@ struct ProjectArgs {
     int64_t n, vn;
     float alpha_min, z_near, lowpass;
     uint32_t *count, *zbits, *gp_of_lin;
+    uint32_t* block_vis;  // visible pairs of each block of 256 pairs (the compaction's prefix)
+    // With init set, the projection launch also initialises the frame: it
+    // clears the counters and the tile ranges and stores the view table (one
+    // chunk of at most kViewChunk views, passed as a kernel argument, which
+    // the projection reads instead of the table it is storing).
+    int init;
+    uint32_t* counters;
+    uint2* ranges;
+    int64_t num_tiles;
+    ViewDev* views_out;
 };
 
 struct GatherArgs {
-    const uint32_t* partial;  // visible pairs per block of kScanTile (view, Gaussian) pairs
+    const uint32_t* partial;  // visible pairs per block of 256 (view, Gaussian) pairs (ProjectArgs::block_vis)
     ProjectArgs proj;
     const uint32_t* count;
     const float *rgb, *sem_val;
@@ -104,6 +115,11 @@ struct KeyArgs {
     int64_t cap;
     uint32_t *keys, *owner;
     uint32_t* heads;  // [cap / kKeyChunk + 1]: owner of each chunk's first key
+    // the tile sort's first-pass counts (radix_first_pass layout), written
+    // here so the sort needs no histogram launch for that pass
+    uint32_t* hist0;
+    uint32_t hist_bins;
+    int hist_block_major;
 };
 
 constexpr int kKeyChunk = 2048;  // keys emitted per workgroup

@@ -9,7 +9,7 @@ namespace sgr {
 
 constexpr int kScanItems = 8;
 constexpr int kScanTile = 256 * kScanItems;
-constexpr int kRadixItems = 16;
+constexpr int kRadixItems = 8;
 constexpr int kRadixTile = 256 * kRadixItems;
 // Small sorts (up to kRadixFewBlocks tiles of kRadixTileSmall items) use
 // smaller tiles, for more workgroups, and each scatter workgroup forms its
@@ -42,10 +42,6 @@ void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t ma
                     uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st,
                     uint32_t* heads = nullptr, uint32_t chunk = 0, const uint32_t* perm = nullptr);
 
-// Block sums of (in[i] != 0) over in[0..n): partial[b] is the number of
-// non-zero items in block b (blocks of kScanTile).
-void scan_flag_sums(const uint32_t* in, uint32_t n, uint32_t* partial, hipStream_t st);
-
 // Passes of a radix sort of `bits` key bits with digits of at most
 // max_digit (<= 8) bits.
 inline int radix_passes(int bits, int max_digit) { return (bits + max_digit - 1) / max_digit; }
@@ -56,10 +52,29 @@ inline int radix_passes(int bits, int max_digit) { return (bits + max_digit - 1)
 // (radix_passes(bits, max_digit)): the result is in the a buffers when it is
 // even, else in b.  vals_identity: the a values are not read; value i is
 // taken to be i.  With carry_dst set, carry_dst[i] = carry_src[sorted value
-// i] (written by the last pass).
+// i] (written by the last pass).  With hist0_ready, the producer of the keys
+// has already written the first pass's counts into hist (the layout of
+// radix_first_pass), and that pass's histogram launch is skipped.
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
                CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st,
-               int max_digit = 8, const uint32_t* carry_src = nullptr, uint32_t* carry_dst = nullptr);
+               int max_digit = 8, const uint32_t* carry_src = nullptr, uint32_t* carry_dst = nullptr,
+               bool hist0_ready = false);
+
+// The first pass's counts as radix_sort expects them, for a producer that
+// writes them itself: per block of kRadixTile keys (the key count clamped to
+// the sort's, as CountSpec gives it), the counts of key & (bins - 1);
+// block-major (hist[b * bins + d]) when the sort takes few blocks, else
+// digit-major (hist[d * nblk + b], nblk the blocks of the clamped count).
+static_assert(kRadixTile == kRadixTileSmall, "both radix paths cut the keys into the same blocks");
+struct RadixFirstPass {
+    uint32_t bins;
+    int block_major;
+};
+inline RadixFirstPass radix_first_pass(uint32_t max_n, int bits, int max_digit) {
+    const int passes = radix_passes(bits, max_digit);
+    const int dbits = passes > 0 ? (bits + passes - 1) / passes : 8;
+    return RadixFirstPass{1u << dbits, div_up(max_n, kRadixTileSmall) <= (int64_t)kRadixFewBlocks ? 1 : 0};
+}
 
 inline size_t radix_hist_words(uint32_t max_n) {
     return 256u * (size_t)std::max(div_up(max_n, kRadixTile), div_up(max_n, kRadixTileSmall));

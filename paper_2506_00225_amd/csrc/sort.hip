@@ -251,15 +251,9 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
     }
 }
 
-void scan_flag_sums(const uint32_t* in, uint32_t n, uint32_t* partial, hipStream_t st) {
-    const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
-    if (nblk == 0) return;
-    scan_block_sums<true><<<nblk, 256, 0, st>>>(in, host_count(n), partial, nullptr);
-}
-
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
                CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st,
-               int max_digit, const uint32_t* carry_src, uint32_t* carry_dst) {
+               int max_digit, const uint32_t* carry_src, uint32_t* carry_dst, bool hist0_ready) {
     const uint32_t nblk_max = (uint32_t)div_up(max_n, kRadixTile);
     if (nblk_max == 0) return 0;
     // few: small tiles (more workgroups for a small sort) and offsets formed in the scatter
@@ -280,19 +274,23 @@ int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* v
         const bool lastp = p == passes - 1;
         const uint32_t* cs_ = lastp ? carry_src : nullptr;
         uint32_t* cd_ = lastp ? carry_dst : nullptr;
+        const bool counted = p == 0 && hist0_ready;  // the producer wrote this pass's counts
         if (few) {
             if (dbits == 8) {
-                radix_hist<true, kRadixItemsSmall, 8><<<nblk_small, 256, 0, st>>>(ki, cs, sh, 8, hist);
+                if (!counted) radix_hist<true, kRadixItemsSmall, 8><<<nblk_small, 256, 0, st>>>(ki, cs, sh, 8, hist);
                 radix_scatter<false, kRadixItemsSmall, 8>
                     <<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist, cs_, cd_);
             } else {
-                radix_hist<true, kRadixItemsSmall, 0><<<nblk_small, 256, 0, st>>>(ki, cs, sh, dbits, hist);
+                if (!counted)
+                    radix_hist<true, kRadixItemsSmall, 0><<<nblk_small, 256, 0, st>>>(ki, cs, sh, dbits, hist);
                 radix_scatter<false, kRadixItemsSmall, 0>
                     <<<nblk_small, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist, cs_, cd_);
             }
         } else {
-            if (dbits == 8) radix_hist<false, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, cs, sh, 8, hist);
-            else radix_hist<false, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, cs, sh, dbits, hist);
+            if (!counted) {
+                if (dbits == 8) radix_hist<false, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, cs, sh, 8, hist);
+                else radix_hist<false, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, cs, sh, dbits, hist);
+            }
             scan_exclusive(hist, hist, hs, bins * nblk_max, partial, nullptr, 0, nullptr, st);
             if (dbits == 8)
                 radix_scatter<true, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist, cs_, cd_);
