@@ -331,6 +331,7 @@ __device__ __forceinline__ void build_geom(const GatherArgs& a, uint32_t g, uint
 // through memory; the depth sort then orders record numbers.  The last
 // workgroup writes the visible count.
 constexpr int kGatherThreads = 256;
+constexpr uint32_t kGatherSumBlocks = 512;  // above this many workgroups the block counts are scanned first
 constexpr int kGatherItems = kScanTile / kGatherThreads;
 
 template <int KT>
@@ -349,10 +350,15 @@ __global__ __launch_bounds__(kGatherThreads, KT > 0 ? 4 : 1) void compact_gather
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     {
         // visible pairs before this workgroup's block: the projection's
-        // counts of the 256-pair blocks before it
+        // counts of the 256-pair blocks before it (summed here when there
+        // are few workgroups, else scanned beforehand)
         uint32_t before = 0;
         const uint32_t nb = blockIdx.x * (kScanTile / 256);
-        for (uint32_t b = tid; b < nb; b += kGatherThreads) before += a.partial[b];
+        if (a.partial_scanned) {
+            if (tid == 0) before = a.partial[nb];
+        } else {
+            for (uint32_t b = tid; b < nb; b += kGatherThreads) before += a.partial[b];
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
         if (lane == 0) wsum[w] = before;
@@ -416,7 +422,8 @@ __global__ __launch_bounds__(kGatherThreads, KT > 0 ? 4 : 1) void compact_gather
 // are taken in windows of that size.  owner[e] is the record of key e's
 // pair.
 __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
-    static_assert(kKeyChunk == kRadixTile, "a chunk of keys is a block of the tile sort");
+    static_assert(kKeyChunk == kRadixTileSmall && kKeyChunk == kRadixTileMid,
+                  "a chunk of keys is a block of the tile sort (when hist0 is set)");
     constexpr int W = kKeyChunk + 1;
     __shared__ uint32_t off[W + 1];
     __shared__ uint32_t s_hist[256];  // counts of the sort's first digit among this chunk's keys
@@ -465,7 +472,7 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
             const uint32_t gt = (uint32_t)info[lo][0] + (local / wdt) * (uint32_t)info[lo][2] + local % wdt;
             a.keys[e] = gt;
             a.owner[e] = (uint32_t)info[lo][3];
-            atomicAdd(&s_hist[gt & dmask], 1u);
+            if (a.hist0) atomicAdd(&s_hist[gt & dmask], 1u);
         }
         // the same for every thread: taken as a scalar, so the loop exit is uniform
         const int more = __builtin_amdgcn_readfirstlane((uint64_t)off[nw] < e1 && w0 + nw < wend ? 1 : 0);
@@ -474,7 +481,8 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
         w0 += nw;
     }
     // this block's first-digit counts (the loop ended at a barrier)
-    const uint32_t nblk = (uint32_t)div_up((int64_t)K, kRadixTile);
+    if (!a.hist0) return;
+    const uint32_t nblk = (uint32_t)div_up((int64_t)K, kKeyChunk);
     for (uint32_t d = threadIdx.x; d < a.hist_bins; d += 256)
         a.hist0[a.hist_block_major ? blockIdx.x * a.hist_bins + d : d * nblk + blockIdx.x] = s_hist[d];
 }
@@ -551,6 +559,15 @@ sgr_status launch_project(const Plan& P, const sgr_gaussians* g, char* ws, hipSt
     ga.pair_lin = (uint32_t*)(ws + P.pair_lin); ga.zkeys = (uint32_t*)(ws + P.vis_k0);
     {
         const uint32_t nblk = (uint32_t)div_up(P.vn, kScanTile);
+        // Each compaction workgroup needs the visible pairs before its block.
+        // With few workgroups each adds up the counts itself; with many (a
+        // batch of views), summing them all would grow with the square of
+        // the count, so an exclusive scan of the counts comes first.
+        ga.partial_scanned = nblk > kGatherSumBlocks ? 1 : 0;
+        if (ga.partial_scanned) {
+            const uint32_t nvb = (uint32_t)div_up(P.vn, 256);
+            scan_exclusive(pa.block_vis, pa.block_vis, host_count(nvb), nvb, partial, nullptr, 0, nullptr, st);
+        }
         if (P.k == 16) compact_gather<16><<<nblk, kGatherThreads, 0, st>>>(ga);
         else if (P.k == 3) compact_gather<3><<<nblk, kGatherThreads, 0, st>>>(ga);
         else compact_gather<0><<<nblk, kGatherThreads, 0, st>>>(ga);
@@ -585,16 +602,19 @@ sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t 
     ka.counters = counters; ka.cap = P.cap;
     ka.keys = (uint32_t*)(ws + P.keys0); ka.owner = (uint32_t*)(ws + P.owner);
     ka.heads = (uint32_t*)(ws + P.heads);
+    // When the tile sort's blocks are the chunks of emission, the emission
+    // counts the first digit of each block (the sort then has no histogram
+    // launch for that pass); larger sorts take longer blocks.
     const RadixFirstPass fp = radix_first_pass((uint32_t)P.cap, P.tile_bits, P.radix_bits);
-    ka.hist0 = (uint32_t*)(ws + P.hist);
+    const bool counted = fp.tile == (uint32_t)kKeyChunk && P.vn > 0;
+    ka.hist0 = counted ? (uint32_t*)(ws + P.hist) : nullptr;
     ka.hist_bins = fp.bins;
     ka.hist_block_major = fp.block_major;
     if (P.vn > 0) emit_keys<<<(unsigned)div_up(P.cap, kKeyChunk), 256, 0, st>>>(ka);
-    // (with no pair to project there are no keys: the sort's blocks are empty)
     const int passes = radix_sort((uint32_t*)(ws + P.keys0), (uint32_t*)(ws + P.vals0), (uint32_t*)(ws + P.keys1),
                                   (uint32_t*)(ws + P.vals1), true, device_count(counters + kKeysLo, (uint32_t)P.cap),
                                   (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits,
-                                  nullptr, nullptr, P.vn > 0);
+                                  nullptr, nullptr, counted);
     if (passes != P.tile_passes) return SGR_EUNSUPPORTED;
     tile_ranges<<<(unsigned)div_up(P.cap, 256), 256, 0, st>>>((const uint32_t*)(ws + P.sorted_keys),
                                                               (uint2*)(ws + P.ranges), counters, (uint32_t)P.cap);

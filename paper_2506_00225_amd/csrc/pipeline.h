@@ -87,7 +87,10 @@ struct ProjectArgs {
 };
 
 struct GatherArgs {
-    const uint32_t* partial;  // visible pairs per block of 256 (view, Gaussian) pairs (ProjectArgs::block_vis)
+    // visible pairs per block of 256 (view, Gaussian) pairs (ProjectArgs::block_vis), or with
+    // partial_scanned their exclusive prefix sums
+    const uint32_t* partial;
+    int partial_scanned;
     ProjectArgs proj;
     const uint32_t* count;
     const float *rgb, *sem_val;

@@ -8,7 +8,7 @@ namespace sgr {
 __device__ __forceinline__ uint32_t count_of(const CountSpec& c) {
     uint32_t n = c.d_n ? *c.d_n : c.host_n;
     if (c.cap && n > c.cap) n = c.cap;
-    if (c.radix_blocks) n = c.radix_blocks * (uint32_t)div_up(n, kRadixTile);
+    if (c.radix_blocks) n = c.radix_blocks * (uint32_t)div_up(n, c.radix_tile);
     return n;
 }
 
@@ -254,7 +254,9 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
 int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, bool vals_identity,
                CountSpec cs, uint32_t max_n, int bits, uint32_t* hist, uint32_t* partial, hipStream_t st,
                int max_digit, const uint32_t* carry_src, uint32_t* carry_dst, bool hist0_ready) {
-    const uint32_t nblk_max = (uint32_t)div_up(max_n, kRadixTile);
+    const uint32_t tile = radix_block_items(max_n);
+    const bool mid = tile == (uint32_t)kRadixTileMid;  // (the small path's tile may be the same size)
+    const uint32_t nblk_max = (uint32_t)div_up(max_n, tile);
     if (nblk_max == 0) return 0;
     // few: small tiles (more workgroups for a small sort) and offsets formed in the scatter
     const uint32_t nblk_small = (uint32_t)div_up(max_n, kRadixTileSmall);
@@ -267,6 +269,7 @@ int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* v
     uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
     CountSpec hs = cs;
     hs.radix_blocks = bins;
+    hs.radix_tile = tile;
     const bool few = nblk_small <= kRadixFewBlocks;
     for (int p = 0; p < passes; p++) {
         const uint32_t* vin = (p == 0 && vals_identity) ? nullptr : vi;
@@ -288,15 +291,30 @@ int radix_sort(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* v
             }
         } else {
             if (!counted) {
-                if (dbits == 8) radix_hist<false, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, cs, sh, 8, hist);
-                else radix_hist<false, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, cs, sh, dbits, hist);
+                if (mid) {
+                    if (dbits == 8) radix_hist<false, kRadixItemsMid, 8><<<nblk_max, 256, 0, st>>>(ki, cs, sh, 8, hist);
+                    else radix_hist<false, kRadixItemsMid, 0><<<nblk_max, 256, 0, st>>>(ki, cs, sh, dbits, hist);
+                } else {
+                    if (dbits == 8) radix_hist<false, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, cs, sh, 8, hist);
+                    else radix_hist<false, kRadixItems, 0><<<nblk_max, 256, 0, st>>>(ki, cs, sh, dbits, hist);
+                }
             }
             scan_exclusive(hist, hist, hs, bins * nblk_max, partial, nullptr, 0, nullptr, st);
-            if (dbits == 8)
-                radix_scatter<true, kRadixItems, 8><<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist, cs_, cd_);
-            else
-                radix_scatter<true, kRadixItems, 0>
-                    <<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist, cs_, cd_);
+            if (mid) {
+                if (dbits == 8)
+                    radix_scatter<true, kRadixItemsMid, 8>
+                        <<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist, cs_, cd_);
+                else
+                    radix_scatter<true, kRadixItemsMid, 0>
+                        <<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist, cs_, cd_);
+            } else {
+                if (dbits == 8)
+                    radix_scatter<true, kRadixItems, 8>
+                        <<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, 8, hist, cs_, cd_);
+                else
+                    radix_scatter<true, kRadixItems, 0>
+                        <<<nblk_max, 256, 0, st>>>(ki, vin, ko, vo, cs, sh, dbits, hist, cs_, cd_);
+            }
         }
         uint32_t* t;
         t = ki; ki = ko; ko = t;
