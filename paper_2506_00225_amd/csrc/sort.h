@@ -50,10 +50,9 @@ inline uint32_t radix_block_items(uint32_t max_n) {
 // goes to *total_out (if set); total > cap sets SGR_ECAPACITY in *status.
 // With heads set, heads[q] receives the item whose run [out[i], out[i] +
 // in[i]) holds position q * chunk, for every such position below cap.
-// With perm set, item i is in[perm[i]] (out is still indexed by i).
 void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
                     uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st,
-                    uint32_t* heads = nullptr, uint32_t chunk = 0, const uint32_t* perm = nullptr);
+                    uint32_t* heads = nullptr, uint32_t chunk = 0);
 
 // Passes of a radix sort of `bits` key bits with digits of at most
 // max_digit (<= 8) bits.

@@ -35,10 +35,8 @@ __device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* wsum, uin
     return pre + x - v;
 }
 
-template <bool FLAG>
 __global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restrict__ in, CountSpec cs,
-                                                       uint32_t* __restrict__ partial,
-                                                       const uint32_t* __restrict__ perm) {
+                                                       uint32_t* __restrict__ partial) {
     __shared__ uint32_t wsum[4];
     const uint32_t n = count_of(cs);
     const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
@@ -48,10 +46,7 @@ __global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restric
 #pragma unroll
     for (int r = 0; r < kScanItems; r++) {
         const uint32_t i = base + r * 256 + threadIdx.x;
-        if (i < n) {
-            const uint32_t x = in[perm ? perm[i] : i];
-            s += FLAG ? (x != 0u) : x;
-        }
+        if (i < n) s += in[i];
     }
     uint32_t tot;
     block_exscan(s, wsum, &tot);
@@ -64,12 +59,12 @@ __global__ __launch_bounds__(256) void scan_block_sums(const uint32_t* __restric
 // block writes the total (and the saturating capacity check).  With `heads`
 // set, the scan is of per-item run lengths, and for every chunk of `chunk`
 // positions below `cap` the item whose run holds the chunk's first position
-// is recorded in heads[chunk index].  With perm set, item i is in[perm[i]].
+// is recorded in heads[chunk index].
 __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec cs,
                                                   const uint32_t* __restrict__ partial, uint32_t* out,
                                                   uint32_t* __restrict__ total_out, uint32_t cap,
                                                   uint32_t* __restrict__ status, uint32_t* __restrict__ heads,
-                                                  uint32_t chunk, const uint32_t* __restrict__ perm) {
+                                                  uint32_t chunk) {
     __shared__ uint32_t wsum[4];
     const uint32_t n = count_of(cs);
     const uint32_t nblk = (uint32_t)div_up(n, kScanTile);
@@ -86,7 +81,7 @@ __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec 
 #pragma unroll
     for (int r = 0; r < kScanItems; r++) {
         const uint32_t i = base + r;
-        v[r] = i < n ? in[perm ? perm[i] : i] : 0u;
+        v[r] = i < n ? in[i] : 0u;
         s += v[r];
     }
     uint32_t tot;
@@ -116,11 +111,11 @@ __global__ __launch_bounds__(256) void scan_apply(const uint32_t* in, CountSpec 
 
 void scan_exclusive(const uint32_t* in, uint32_t* out, CountSpec cs, uint32_t max_n, uint32_t* partial,
                     uint32_t* total_out, uint32_t cap, uint32_t* status, hipStream_t st, uint32_t* heads,
-                    uint32_t chunk, const uint32_t* perm) {
+                    uint32_t chunk) {
     const uint32_t nblk_max = (uint32_t)div_up(max_n, kScanTile);
     if (nblk_max == 0) return;
-    scan_block_sums<false><<<nblk_max, 256, 0, st>>>(in, cs, partial, perm);
-    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out, total_out, cap, status, heads, chunk, perm);
+    scan_block_sums<<<nblk_max, 256, 0, st>>>(in, cs, partial);
+    scan_apply<<<nblk_max, 256, 0, st>>>(in, cs, partial, out, total_out, cap, status, heads, chunk);
 }
 
 // ------------------------------------------------------------------ radix
