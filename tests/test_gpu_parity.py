@@ -83,6 +83,30 @@ def test_multiview_keys_bit_exact():
     assert np.array_equal(rng, wrng)
 
 
+def test_keys_bit_exact_past_the_small_sort_limits():
+    """Eight views of 150k Gaussians (1.2M pairs): past 512 compaction
+    workgroups (the per-block visible counts are scanned rather than summed
+    by each workgroup) and past the small-sort form of the depth sort (its
+    counts scanned, blocks of 2048); keys, order and ranges still equal the
+    oracle's bit for bit."""
+    _say("keys past the small sort limits")
+    sc = scenes.candidate_scene(n=150_000, nviews=8)
+    assert sc.n * len(sc.cameras) > 512 * 2048
+    fr = U.frame_for(sc)
+    g = Gaussians.from_scene(sc)
+    fr.prepare(g)
+    torch.cuda.synchronize()
+    st, nvis, _ = fr.status()
+    assert st == 0
+    cfg = U.oracle_cfg()
+    prs = [O.project(sc.means, sc.scales, sc.quats, sc.opacity, c, cfg) for c in sc.cameras]
+    assert nvis == sum(int(p["visible"].sum()) for p in prs)
+    keys, rng = U.gpu_keys(fr)
+    want, wrng, _ = O.reference_keys(prs, sc.cameras)
+    assert np.array_equal(keys, want)
+    assert np.array_equal(rng, wrng)
+
+
 # ---------------------------------------------------------------- forward
 
 def _forward_case(sc, lowpass=None):
