@@ -63,8 +63,12 @@ inline AdamParams adam_params(float lr, float b1, float b2, float eps, int step)
 }
 __device__ __forceinline__ void adam_update(float g, float& m, float& v, float& p, float lo, float hi,
                                             const AdamParams& h) {
-    m = h.b1 * m + (1.f - h.b1) * g;
-    v = h.b2 * v + (1.f - h.b2) * g * g;
+    // One fixed evaluation: the two fused multiply-adds are written out and
+    // nothing else is contracted, so every kernel that applies the step (the
+    // plain one, the one fused into the gather) gives the same bits.
+#pragma clang fp contract(off)
+    m = fmaf(h.b1, m, (1.f - h.b1) * g);
+    v = fmaf(h.b2, v, ((1.f - h.b2) * g) * g);
     p = fminf(fmaxf(p - h.lr * (m / h.bc1) / (sqrtf(v / h.bc2) + h.eps), lo), hi);
 }
 

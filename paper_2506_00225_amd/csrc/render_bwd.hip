@@ -551,11 +551,19 @@ __global__ __launch_bounds__(kBwdThreads, (KT == 16 || KT == 3) ? (SPARSE ? 6 : 
 // emission order; long segments (a Gaussian near the camera can cover
 // thousands of tiles) are taken one at a time by the whole wave: lane l sums
 // keys l, l+64, ... and the wave reduces in a fixed pattern.  Either way the
-// result does not depend on timing.
+// result does not depend on timing.  Most lanes of the launch are idle (one
+// per possible pair), so the bound of 8 waves per SIMD (at most 64 registers)
+// lets the whole grid be resident at once.
 constexpr uint32_t kShortSeg = 16;
 
+// Bit i set when byte i of x is nonzero.
+__device__ __forceinline__ uint32_t nonzero_nibble(uint32_t x) {
+    const uint32_t t = (((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u;
+    return ((t >> 7) | (t >> 14) | (t >> 21) | (t >> 28)) & 0xfu;
+}
+
 template <int KT>
-__global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ slots,
+__global__ __launch_bounds__(256, KT > 0 ? 8 : 1) void gather_slots(const float* __restrict__ slots,
                                                     const uint8_t* __restrict__ touched,
                                                     const uint32_t* __restrict__ toff,
                                                     const uint32_t* __restrict__ tcount,
@@ -567,9 +575,10 @@ __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ sl
     const uint32_t nvis = counters[kNumVisible];
     const bool ok = !(counters[kStatus] & SGR_ECAPACITY);
     // Pairs are taken by depth rank r (their keys are the emission range
-    // [toff[r], toff[r] + tcount[r])), so the nearest ones (the
-    // longest segments) are adjacent; striding ranks across workgroups
-    // spreads them over the machine instead of queueing them in one wave.
+    // [toff[r], toff[r] + tcount[r])), so the nearest ones (the longest
+    // segments) are adjacent; striding ranks across all the workgroups the
+    // launch could need (one lane per possible pair, most of them idle)
+    // spreads them over the machine instead of queueing them in a few waves.
     // The sums go to the pair's record g = order[r].
     const uint32_t r = threadIdx.x * gridDim.x + blockIdx.x;
     const int lane = threadIdx.x & 63;
@@ -582,12 +591,24 @@ __global__ __launch_bounds__(256) void gather_slots(const float* __restrict__ sl
     }
     const bool longseg = e1 - e0 > kShortSeg;
     if (valid && !longseg) {
+        // the segment's touched flags, at most 16 bytes, from the (at most
+        // five) aligned words that hold them, all loaded before any slot
+        uint32_t mask = 0u;
+        if (e1 > e0) {
+            const uint32_t* tw = reinterpret_cast<const uint32_t*>(touched);
+            const uint32_t w0 = e0 >> 2, wl = (e1 - 1u) >> 2;
+            uint32_t bits = 0u;
+#pragma unroll
+            for (uint32_t j = 0; j < 5; j++)
+                if (w0 + j <= wl) bits |= nonzero_nibble(tw[w0 + j]) << (4 * j);
+            mask = (bits >> (e0 & 3u)) & ((1u << (e1 - e0)) - 1u);
+        }
         float acc[NVMAX];
 #pragma unroll
         for (int q = 0; q < NVMAX; q++) acc[q] = 0.f;
-        for (uint32_t e = e0; e < e1; e++) {
-            if (!touched[e]) continue;
-            const float* sl = slots + (size_t)e * NV;
+        while (mask) {  // the touched slots in emission order
+            const float* sl = slots + (size_t)(e0 + (uint32_t)__builtin_ctz(mask)) * NV;
+            mask &= mask - 1u;
 #pragma unroll
             for (int q = 0; q < NVMAX; q++)
                 if (q < NV) acc[q] += sl[q];
@@ -648,39 +669,60 @@ struct ProjBwdArgs {
 // that tensor, and the block applies the Adam update to the range with
 // coalesced loads of p, m and v, all of a thread's loads issued before its
 // stores.
+constexpr int kAdamChunk = 8;
+
 template <int WM>
 __device__ __forceinline__ void adam_rows(const sgr_adam_segment& sg, const float* st, int64_t i0, int cnt, int w,
                                           const AdamParams& h) {
     const int ws = w | 1;  // odd row stride: the rows were written without bank conflicts
     const int tot = cnt * w;
     const int64_t base = i0 * w;
-    float m[WM], v[WM], p[WM];
+    // at most kAdamChunk elements per thread in flight (24 registers): the
+    // widest rows (the top-k values) would otherwise hold 48
+    constexpr int CH = WM < kAdamChunk ? WM : kAdamChunk;
     __syncthreads();  // the rows are staged, and every thread has read its parameters
 #pragma unroll
-    for (int u = 0; u < WM; u++) {
-        const int e = (int)threadIdx.x + 256 * u;
-        if (e < tot) {
-            m[u] = sg.m[base + e];
-            v[u] = sg.v[base + e];
-            p[u] = sg.p[base + e];
-        }
-    }
+    for (int u0 = 0; u0 < WM; u0 += CH) {
+        float m[CH], v[CH], p[CH];
 #pragma unroll
-    for (int u = 0; u < WM; u++) {
-        const int e = (int)threadIdx.x + 256 * u;
-        if (e < tot) {
-            const int t = e / w, c = e - t * w;
-            adam_update(st[t * ws + c], m[u], v[u], p[u], sg.lo, sg.hi, h);
-            sg.m[base + e] = m[u];
-            sg.v[base + e] = v[u];
-            sg.p[base + e] = p[u];
+        for (int u = 0; u < CH; u++) {
+            const int e = (int)threadIdx.x + 256 * (u0 + u);
+            if (u0 + u < WM && e < tot) {
+                m[u] = sg.m[base + e];
+                v[u] = sg.v[base + e];
+                p[u] = sg.p[base + e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; u++) {
+            const int e = (int)threadIdx.x + 256 * (u0 + u);
+            if (u0 + u < WM && e < tot) {
+                const int t = e / w, c = e - t * w;
+                adam_update(st[t * ws + c], m[u], v[u], p[u], sg.lo, sg.hi, h);
+                sg.m[base + e] = m[u];
+                sg.v[base + e] = v[u];
+                sg.p[base + e] = p[u];
+            }
         }
     }
     __syncthreads();  // before the rows are overwritten
 }
 
+// a0 b0 + a1 b1 + a2 b2 (+ c) as a fixed chain of fused multiply-adds
+__device__ __forceinline__ float fdot3(float a0, float b0, float a1, float b1, float a2, float b2) {
+#pragma clang fp contract(off)
+    return fmaf(a2, b2, fmaf(a1, b1, a0 * b0));
+}
+__device__ __forceinline__ float fdot3c(float a0, float b0, float a1, float b1, float a2, float b2, float c) {
+    return fmaf(a2, b2, fmaf(a1, b1, fmaf(a0, b0, c)));
+}
+
 template <int KT, bool ADAM>
 __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
+    // The fused multiply-adds are written out and nothing else is contracted
+    // (no choice left to the compiler): the kernel with the Adam step and the
+    // one without compute the same gradients bit for bit.
+#pragma clang fp contract(off)
     const int64_t i0 = blockIdx.x * 256ll, i = i0 + threadIdx.x;
     if (!ADAM && i >= a.n) return;
     // with ADAM every thread reaches the block's barriers; one past the end
@@ -694,18 +736,24 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
     const int k = KT > 0 ? KT : a.k;
     const float m0 = a.means[3 * il], m1 = a.means[3 * il + 1], m2 = a.means[3 * il + 2];
     const float q0 = a.quats[4 * il], q1 = a.quats[4 * il + 1], q2 = a.quats[4 * il + 2], q3 = a.quats[4 * il + 3];
-    const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const float qn = sqrtf(fmaf(q3, q3, fmaf(q2, q2, fmaf(q1, q1, q0 * q0))));
     const float qw = q0 / qn, qx = q1 / qn, qy = q2 / qn, qz = q3 / qn;
     float Rq[9];
-    Rq[0] = 1 - 2 * (qy * qy + qz * qz); Rq[1] = 2 * (qx * qy - qw * qz);     Rq[2] = 2 * (qx * qz + qw * qy);
-    Rq[3] = 2 * (qx * qy + qw * qz);     Rq[4] = 1 - 2 * (qx * qx + qz * qz); Rq[5] = 2 * (qy * qz - qw * qx);
-    Rq[6] = 2 * (qx * qz - qw * qy);     Rq[7] = 2 * (qy * qz + qw * qx);     Rq[8] = 1 - 2 * (qx * qx + qy * qy);
+    Rq[0] = fmaf(-2.f, fmaf(qy, qy, qz * qz), 1.f);
+    Rq[1] = 2.f * fmaf(qx, qy, -(qw * qz));
+    Rq[2] = 2.f * fmaf(qx, qz, qw * qy);
+    Rq[3] = 2.f * fmaf(qx, qy, qw * qz);
+    Rq[4] = fmaf(-2.f, fmaf(qx, qx, qz * qz), 1.f);
+    Rq[5] = 2.f * fmaf(qy, qz, -(qw * qx));
+    Rq[6] = 2.f * fmaf(qx, qz, -(qw * qy));
+    Rq[7] = 2.f * fmaf(qy, qz, qw * qx);
+    Rq[8] = fmaf(-2.f, fmaf(qx, qx, qy * qy), 1.f);
     const float s[3] = {a.scales[3 * il], a.scales[3 * il + 1], a.scales[3 * il + 2]};
     float M[9], S3[9];
     for (int r = 0; r < 3; r++)
         for (int c = 0; c < 3; c++) M[3 * r + c] = Rq[3 * r + c] * s[c];
     for (int r = 0; r < 3; r++)
-        for (int c = 0; c < 3; c++) S3[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+        for (int c = 0; c < 3; c++) S3[3 * r + c] = fdot3(M[3 * r], M[3 * c], M[3 * r + 1], M[3 * c + 1], M[3 * r + 2], M[3 * c + 2]);
     float dS3[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int v = 0; v < a.V && ok; v++) {
         const uint32_t g = a.gp_of_lin[(int64_t)v * a.n + i];
@@ -715,37 +763,38 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
         float W[9];
         for (int r = 0; r < 9; r++) W[r] = vw.R[r];
         float p[3];
-        for (int r = 0; r < 3; r++) p[r] = W[3 * r] * m0 + W[3 * r + 1] * m1 + W[3 * r + 2] * m2 + vw.t[r];
+        for (int r = 0; r < 3; r++) p[r] = fdot3c(W[3 * r], m0, W[3 * r + 1], m1, W[3 * r + 2], m2, vw.t[r]);
         const float fx = vw.fx, fy = vw.fy, x = p[0], y = p[1], z = p[2];
         const float J[6] = {fx / z, 0, -fx * x / (z * z), 0, fy / z, -fy * y / (z * z)};
         float T[6];
         for (int r = 0; r < 2; r++)
-            for (int c = 0; c < 3; c++) T[3 * r + c] = J[3 * r] * W[c] + J[3 * r + 1] * W[3 + c] + J[3 * r + 2] * W[6 + c];
+            for (int c = 0; c < 3; c++) T[3 * r + c] = fdot3(J[3 * r], W[c], J[3 * r + 1], W[3 + c], J[3 * r + 2], W[6 + c]);
         float TS3[6];
         for (int r = 0; r < 2; r++)
             for (int c = 0; c < 3; c++)
-                TS3[3 * r + c] = T[3 * r] * S3[c] + T[3 * r + 1] * S3[3 + c] + T[3 * r + 2] * S3[6 + c];
+                TS3[3 * r + c] = fdot3(T[3 * r], S3[c], T[3 * r + 1], S3[3 + c], T[3 * r + 2], S3[6 + c]);
         // the slots carry dL/dSigma2 itself (the low-pass term is a constant)
         const float dS2[4] = {d2[2], 0.5f * d2[3], 0.5f * d2[3], d2[4]};
         for (int r = 0; r < 3; r++)
             for (int c = 0; c < 3; c++)
-                dS3[3 * r + c] += T[r] * (dS2[0] * T[c] + dS2[1] * T[3 + c]) + T[3 + r] * (dS2[2] * T[c] + dS2[3] * T[3 + c]);
+                dS3[3 * r + c] = fmaf(T[3 + r], fmaf(dS2[3], T[3 + c], dS2[2] * T[c]),
+                                      fmaf(T[r], fmaf(dS2[1], T[3 + c], dS2[0] * T[c]), dS3[3 * r + c]));
         float dT[6];
         for (int r = 0; r < 2; r++)
-            for (int c = 0; c < 3; c++) dT[3 * r + c] = 2.0f * (dS2[2 * r] * TS3[c] + dS2[2 * r + 1] * TS3[3 + c]);
+            for (int c = 0; c < 3; c++) dT[3 * r + c] = 2.0f * fmaf(dS2[2 * r + 1], TS3[3 + c], dS2[2 * r] * TS3[c]);
         float dJ[6];
         for (int r = 0; r < 2; r++)
-            for (int c = 0; c < 3; c++) dJ[3 * r + c] = dT[3 * r] * W[3 * c] + dT[3 * r + 1] * W[3 * c + 1] + dT[3 * r + 2] * W[3 * c + 2];
+            for (int c = 0; c < 3; c++) dJ[3 * r + c] = fdot3(dT[3 * r], W[3 * c], dT[3 * r + 1], W[3 * c + 1], dT[3 * r + 2], W[3 * c + 2]);
         const float z2 = z * z, z3 = z2 * z;
         float dp[3];
         dp[0] = dJ[2] * (-fx / z2);
         dp[1] = dJ[5] * (-fy / z2);
-        dp[2] = dJ[0] * (-fx / z2) + dJ[2] * (2.0f * fx * x / z3) + dJ[4] * (-fy / z2) + dJ[5] * (2.0f * fy * y / z3);
+        dp[2] = fmaf(dJ[5], 2.0f * fy * y / z3, fmaf(dJ[4], -fy / z2, fmaf(dJ[2], 2.0f * fx * x / z3, dJ[0] * (-fx / z2))));
         const float gmx = d2[0], gmy = d2[1];
         dp[0] += gmx * fx / z;
         dp[1] += gmy * fy / z;
         dp[2] += -gmx * fx * x / z2 - gmy * fy * y / z2 + d2[9];
-        for (int c = 0; c < 3; c++) gm[c] += W[c] * dp[0] + W[3 + c] * dp[1] + W[6 + c] * dp[2];
+        for (int c = 0; c < 3; c++) gm[c] = fdot3c(W[c], dp[0], W[3 + c], dp[1], W[6 + c], dp[2], gm[c]);
         go += d2[5];
         grgb[0] += d2[6];
         grgb[1] += d2[7];
@@ -754,19 +803,23 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
     // Sigma3 = M M^T, M = Rq diag(s): dM = 2 dS3 M
     float dM[9];
     for (int r = 0; r < 3; r++)
-        for (int c = 0; c < 3; c++) dM[3 * r + c] = 2.0f * (dS3[3 * r] * M[c] + dS3[3 * r + 1] * M[3 + c] + dS3[3 * r + 2] * M[6 + c]);
-    for (int c = 0; c < 3; c++) gs[c] = dM[c] * Rq[c] + dM[3 + c] * Rq[3 + c] + dM[6 + c] * Rq[6 + c];
+        for (int c = 0; c < 3; c++) dM[3 * r + c] = 2.0f * fdot3(dS3[3 * r], M[c], dS3[3 * r + 1], M[3 + c], dS3[3 * r + 2], M[6 + c]);
+    for (int c = 0; c < 3; c++) gs[c] = fdot3(dM[c], Rq[c], dM[3 + c], Rq[3 + c], dM[6 + c], Rq[6 + c]);
     float dR[9];
     for (int r = 0; r < 3; r++)
         for (int c = 0; c < 3; c++) dR[3 * r + c] = dM[3 * r + c] * s[c];
     float dq[4];
-    dq[0] = 2.0f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-    dq[1] = 2.0f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0f * qx * dR[4] - qw * dR[5] + qz * dR[6] + qw * dR[7] - 2.0f * qx * dR[8]);
-    dq[2] = 2.0f * (-2.0f * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] + qz * dR[7] - 2.0f * qy * dR[8]);
-    dq[3] = 2.0f * (-2.0f * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0f * qz * dR[4] + qy * dR[5] + qx * dR[6] + qy * dR[7]);
-    const float dot = dq[0] * qw + dq[1] * qx + dq[2] * qy + dq[3] * qz;
+    // dL/dq of R(q) (the derivative of each rotation entry in q), left to right
+    dq[0] = 2.0f * fmaf(qx, dR[7], fmaf(-qy, dR[6], fmaf(-qx, dR[5], fmaf(qz, dR[3], fmaf(qy, dR[2], -qz * dR[1])))));
+    dq[1] = 2.0f * fmaf(-2.0f * qx, dR[8], fmaf(qw, dR[7], fmaf(qz, dR[6], fmaf(-qw, dR[5],
+                   fmaf(-2.0f * qx, dR[4], fmaf(qy, dR[3], fmaf(qz, dR[2], qy * dR[1])))))));
+    dq[2] = 2.0f * fmaf(-2.0f * qy, dR[8], fmaf(qz, dR[7], fmaf(-qw, dR[6], fmaf(qz, dR[5],
+                   fmaf(qx, dR[3], fmaf(qw, dR[2], fmaf(qx, dR[1], -2.0f * qy * dR[0])))))));
+    dq[3] = 2.0f * fmaf(qy, dR[7], fmaf(qx, dR[6], fmaf(qy, dR[5], fmaf(-2.0f * qz, dR[4],
+                   fmaf(qw, dR[3], fmaf(qx, dR[2], fmaf(-qw, dR[1], -2.0f * qz * dR[0])))))));
+    const float dot = fmaf(dq[3], qz, fmaf(dq[2], qy, fmaf(dq[1], qx, dq[0] * qw)));
     const float qh[4] = {qw, qx, qy, qz};
-    for (int c = 0; c < 4; c++) gq[c] = (dq[c] - qh[c] * dot) / qn;
+    for (int c = 0; c < 4; c++) gq[c] = fmaf(-qh[c], dot, dq[c]) / qn;
     if (!ADAM) {
         if (a.d_means) for (int c = 0; c < 3; c++) a.d_means[3 * i + c] = gm[c];
         if (a.d_scales) for (int c = 0; c < 3; c++) a.d_scales[3 * i + c] = gs[c];
