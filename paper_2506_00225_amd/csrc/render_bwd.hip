@@ -708,6 +708,47 @@ __device__ __forceinline__ void adam_rows(const sgr_adam_segment& sg, const floa
     __syncthreads();  // before the rows are overwritten
 }
 
+// The same update split in two, so a tensor's rows can be loaded before
+// the work that precedes their update: the block's m, v and p rows of one
+// tensor (WM elements per thread), then, once its gradients are staged in
+// st, the update and the stores.
+template <int WM>
+struct AdamRows {
+    float m[WM], v[WM], p[WM];
+};
+template <int WM, int U0 = 0>  // (elements U0 .. U0 + WM - 1 of each thread)
+__device__ __forceinline__ void adam_load(const sgr_adam_segment& sg, int64_t i0, int cnt, int w, AdamRows<WM>& r) {
+    const int tot = cnt * w;
+    const int64_t base = i0 * w;
+#pragma unroll
+    for (int u = 0; u < WM; u++) {
+        const int e = (int)threadIdx.x + 256 * (U0 + u);
+        if (e < tot) {
+            r.m[u] = sg.m[base + e];
+            r.v[u] = sg.v[base + e];
+            r.p[u] = sg.p[base + e];
+        }
+    }
+}
+template <int WM, int U0 = 0>
+__device__ __forceinline__ void adam_apply(const sgr_adam_segment& sg, const float* st, int64_t i0, int cnt, int w,
+                                           const AdamParams& h, AdamRows<WM>& r) {
+    const int ws = w | 1;
+    const int tot = cnt * w;
+    const int64_t base = i0 * w;
+#pragma unroll
+    for (int u = 0; u < WM; u++) {
+        const int e = (int)threadIdx.x + 256 * (U0 + u);
+        if (e < tot) {
+            const int t = e / w, c = e - t * w;
+            adam_update(st[t * ws + c], r.m[u], r.v[u], r.p[u], sg.lo, sg.hi, h);
+            sg.m[base + e] = r.m[u];
+            sg.v[base + e] = r.v[u];
+            sg.p[base + e] = r.p[u];
+        }
+    }
+}
+
 // a0 b0 + a1 b1 + a2 b2 (+ c) as a fixed chain of fused multiply-adds
 __device__ __forceinline__ float fdot3(float a0, float b0, float a1, float b1, float a2, float b2) {
 #pragma clang fp contract(off)
@@ -730,6 +771,15 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
     const bool live = i < a.n;
     const int64_t il = live ? i : a.n - 1;
     const bool ok = live && !(a.counters[kStatus] & SGR_ECAPACITY);
+    const int cnt = (int)min<int64_t>(256, a.n - i0);
+    // the Adam rows of the means and scales are loaded first, under the
+    // chain rule (the parameters it reads are stored only after the block's
+    // next barrier)
+    AdamRows<3> r_means, r_scales;
+    if (ADAM) {
+        adam_load<3>(a.seg[0], i0, cnt, 3, r_means);
+        adam_load<3>(a.seg[1], i0, cnt, 3, r_scales);
+    }
     float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0};
     float go = 0.f, grgb[3] = {0.f, 0.f, 0.f};
     constexpr int KM = KT > 0 ? KT : kMaxK;
@@ -829,24 +879,45 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
     }
     constexpr int kRow = (KM | 1) > 5 ? (KM | 1) : 5;  // widest staged row: quats (4 | 1) or the top-k values
     __shared__ float st[ADAM ? 256 * kRow : 1];
-    const int cnt = (int)min<int64_t>(256, a.n - i0);
     const int tid = threadIdx.x;
     if (ADAM) {
+        // each tensor's update with the next tensors' rows already in flight
+        AdamRows<4> r_quats;
+        AdamRows<1> r_opac;
+        AdamRows<3> r_rgb;
         for (int c = 0; c < 3; c++) st[tid * 3 + c] = gm[c];
-        adam_rows<3>(a.seg[0], st, i0, cnt, 3, a.h);
+        adam_load<4>(a.seg[2], i0, cnt, 4, r_quats);
+        __syncthreads();  // the rows are staged, and every thread has read its parameters
+        adam_apply<3>(a.seg[0], st, i0, cnt, 3, a.h, r_means);
+        __syncthreads();
         for (int c = 0; c < 3; c++) st[tid * 3 + c] = gs[c];
-        adam_rows<3>(a.seg[1], st, i0, cnt, 3, a.h);
+        adam_load<1>(a.seg[3], i0, cnt, 1, r_opac);
+        __syncthreads();
+        adam_apply<3>(a.seg[1], st, i0, cnt, 3, a.h, r_scales);
+        __syncthreads();
         for (int c = 0; c < 4; c++) st[tid * 5 + c] = gq[c];
-        adam_rows<4>(a.seg[2], st, i0, cnt, 4, a.h);
+        adam_load<3>(a.seg[4], i0, cnt, 3, r_rgb);
+        __syncthreads();
+        adam_apply<4>(a.seg[2], st, i0, cnt, 4, a.h, r_quats);
+        __syncthreads();
         st[tid] = go;
-        adam_rows<1>(a.seg[3], st, i0, cnt, 1, a.h);
+        __syncthreads();
+        adam_apply<1>(a.seg[3], st, i0, cnt, 1, a.h, r_opac);
+        __syncthreads();
         for (int c = 0; c < 3; c++) st[tid * 3 + c] = grgb[c];
-        adam_rows<3>(a.seg[4], st, i0, cnt, 3, a.h);
+        __syncthreads();
+        adam_apply<3>(a.seg[4], st, i0, cnt, 3, a.h, r_rgb);
+        __syncthreads();
     }
     if (ADAM || a.d_sem) {
         // the top-k value gradients in stored order, summed over views (after
         // the chain rule, so its registers are free), then written to the list
         // positions they came from (the same for every view of a Gaussian)
+        // with a fixed k the first half of the value rows is loaded first
+        constexpr int SH = KT > 0 ? (KM + 1) / 2 : 1;
+        AdamRows<SH> r_sem0;
+        AdamRows<KM - SH> r_sem1;
+        if (ADAM && KT > 0) adam_load<SH>(a.seg[5], i0, cnt, k, r_sem0);
         float gsem[KM];
 #pragma unroll
         for (int p = 0; p < KM; p++) gsem[p] = 0.f;
@@ -869,7 +940,14 @@ __global__ __launch_bounds__(256) void project_backward_kernel(ProjBwdArgs a) {
             for (int p = 0; p < KM; p++)
                 if (p < k) ds[(so[p >> 2] >> (8 * (p & 3))) & 0xffu] = gsem[p];
         }
-        if (ADAM) adam_rows<KM>(a.seg[5], st, i0, cnt, k, a.h);
+        if (ADAM && KT > 0) {
+            adam_load<KM - SH, SH>(a.seg[5], i0, cnt, k, r_sem1);
+            __syncthreads();
+            adam_apply<SH>(a.seg[5], st, i0, cnt, k, a.h, r_sem0);
+            adam_apply<KM - SH, SH>(a.seg[5], st, i0, cnt, k, a.h, r_sem1);
+        } else if (ADAM) {
+            adam_rows<KM>(a.seg[5], st, i0, cnt, k, a.h);
+        }
     }
 }
 
