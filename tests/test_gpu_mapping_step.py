@@ -156,14 +156,16 @@ def test_large_scene_two_portrait_keyframes():
     print("large scene report", reps, U.compare_grads(got, want, bad, visible=vis), flush=True)
 
 
-def test_gather_with_adam_equals_gather_then_adam():
+@pytest.mark.parametrize("n,k", [(200_000, 16), (60_000, 3), (60_000, 5)])
+def test_gather_with_adam_equals_gather_then_adam(n, k):
     """The gather with the Adam step fused (sgr_render_backward_gather_adam)
     gives, bit for bit, the parameters and moments of the gather followed by
-    sgr_adam_step, over two mapping iterations of a 200k room (the second
-    starts from nonzero moments)."""
+    sgr_adam_step, over two mapping iterations of a room (the second starts
+    from nonzero moments): top-16 lists, and the kernels for 3 entries and
+    for a run-time list length."""
     from paper_2506_00225_amd import FusedAdam
-    _say("gather + Adam fused vs separate, 200k")
-    sc = scenes.room_scene(n=200_000)
+    _say(f"gather + Adam fused vs separate, {n} Gaussians, k={k}")
+    sc = scenes.room_scene(n=n, k=k)
     cam = sc.cameras[0]
     P = cam.width * cam.height
     g0, fr = _bench_frame(sc, [cam])
