@@ -417,7 +417,8 @@ __global__ __launch_bounds__(kGatherThreads, KT > 0 ? 4 : 1) void compact_gather
 
 // Workgroup q emits keys [q C, q C + C) (C = kKeyChunk): the pairs that own
 // them, heads[q] onwards, go to LDS (offsets, tile rectangle and record),
-// and each key finds its owner by binary search there.  A pair owns at least
+// and each key finds its owner there (marks and a max-scan over the chunk's
+// positions, below).  A pair owns at least
 // one key, so at most C + 1 pairs meet a chunk; longer runs (pairs with none)
 // are taken in windows of that size.  owner[e] is the record of key e's
 // pair.
@@ -428,6 +429,8 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
     __shared__ uint32_t off[W + 1];
     __shared__ uint32_t s_hist[256];  // counts of the sort's first digit among this chunk's keys
     __shared__ int32_t info[W][4];  // first global tile of the rect, rect width in tiles, view width in tiles, record
+    __shared__ uint32_t s_own[kKeyChunk];  // owner (window index) of each key of the window's range
+    __shared__ uint32_t s_wmax[4];
     const uint32_t nv = a.counters[kNumVisible];
     const uint64_t K = min((uint64_t)a.counters[kKeysLo], (uint64_t)a.cap);
     const uint64_t e0 = (uint64_t)blockIdx.x * kKeyChunk;
@@ -460,13 +463,45 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
         __syncthreads();
         // keys of this chunk owned by the window's pairs
         const uint64_t k0 = max(e0, (uint64_t)off[0]), k1 = min(e1, (uint64_t)off[nw]);
-        for (uint64_t e = k0 + threadIdx.x; e < k1; e += 256) {
-            // owner: last j with off[j] <= e
-            int lo = 0, hi = (int)nw - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (off[mid] <= e) lo = mid; else hi = mid - 1;
+        const uint32_t nk = (uint32_t)(k1 - k0);  // at most kKeyChunk
+        // owner of key k0 + p (the last pair j with off[j] <= k0 + p): each
+        // pair with keys here marks where its keys start (one pair per
+        // position), then an inclusive max-scan carries the marks forward
+        for (uint32_t q = threadIdx.x; q < kKeyChunk; q += 256) s_own[q] = 0;
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < nw; j += 256) {
+            const uint64_t b = max((uint64_t)off[j], k0);
+            if (b < k1 && off[j + 1] > b) s_own[b - k0] = j;
+        }
+        __syncthreads();
+        {
+            constexpr int PT = kKeyChunk / 256;  // positions per thread, in order
+            uint32_t own[PT], m = 0;
+#pragma unroll
+            for (int u = 0; u < PT; u++) {
+                m = max(m, s_own[threadIdx.x * PT + u]);
+                own[u] = m;
             }
+            // exclusive max over the threads before this one
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            uint32_t x = m;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x = max(x, y);
+            }
+            if (lane == 63) s_wmax[wv] = x;
+            uint32_t before = __shfl_up(x, 1, 64);
+            if (lane == 0) before = 0;
+            __syncthreads();
+            for (int w = 0; w < wv; w++) before = max(before, s_wmax[w]);
+#pragma unroll
+            for (int u = 0; u < PT; u++) s_own[threadIdx.x * PT + u] = max(own[u], before);
+        }
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < nk; p += 256) {
+            const uint64_t e = k0 + p;
+            const int lo = (int)s_own[p];
             const uint32_t local = (uint32_t)(e - off[lo]);
             const uint32_t wdt = (uint32_t)info[lo][1];
             const uint32_t gt = (uint32_t)info[lo][0] + (local / wdt) * (uint32_t)info[lo][2] + local % wdt;
