@@ -526,13 +526,30 @@ __global__ __launch_bounds__(256) void emit_keys(KeyArgs a) {
 // pair of sorted key s as owner[svals[s]], inside their staging prefetch.)
 __global__ __launch_bounds__(256) void tile_ranges(const uint32_t* __restrict__ skeys, uint2* __restrict__ ranges,
                                                    const uint32_t* __restrict__ counters, uint32_t cap) {
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    // four consecutive keys per thread (one 16-byte load; the sorted keys
+    // are 16-byte aligned), with the keys either side of them
+    const uint32_t s0 = (blockIdx.x * 256u + threadIdx.x) * 4u;
     const uint32_t K = min(counters[kKeysLo], cap);
     if (counters[kStatus] & SGR_ECAPACITY) return;
-    if (s >= K) return;
-    const uint32_t key = skeys[s];
-    if (s == 0 || skeys[s - 1] != key) ranges[key].x = s;
-    if (s == K - 1 || skeys[s + 1] != key) ranges[key].y = s + 1;
+    if (s0 >= K) return;
+    uint32_t k[6];
+    if (s0 + 4u <= K) {
+        const uint4 q = *reinterpret_cast<const uint4*>(skeys + s0);
+        k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+    } else {
+#pragma unroll
+        for (uint32_t u = 0; u < 4u; u++) k[1 + u] = s0 + u < K ? skeys[s0 + u] : 0u;
+    }
+    k[0] = s0 > 0u ? skeys[s0 - 1u] : 0u;
+    k[5] = s0 + 4u < K ? skeys[s0 + 4u] : 0u;
+#pragma unroll
+    for (uint32_t u = 0; u < 4u; u++) {
+        const uint32_t s = s0 + u;
+        if (s >= K) break;
+        const uint32_t key = k[1 + u];
+        if (s == 0u || k[u] != key) ranges[key].x = s;
+        if (s == K - 1u || k[2 + u] != key) ranges[key].y = s + 1u;
+    }
 }
 
 // --------------------------------------------------------------- launchers
@@ -651,7 +668,7 @@ sgr_status launch_bin(const Plan& P, char* ws, int64_t* d_num_keys, hipStream_t 
                                   (uint32_t)P.cap, P.tile_bits, (uint32_t*)(ws + P.hist), partial, st, P.radix_bits,
                                   nullptr, nullptr, counted);
     if (passes != P.tile_passes) return SGR_EUNSUPPORTED;
-    tile_ranges<<<(unsigned)div_up(P.cap, 256), 256, 0, st>>>((const uint32_t*)(ws + P.sorted_keys),
+    tile_ranges<<<(unsigned)div_up(P.cap, 1024), 256, 0, st>>>((const uint32_t*)(ws + P.sorted_keys),
                                                               (uint2*)(ws + P.ranges), counters, (uint32_t)P.cap);
     if (d_num_keys) publish_num_keys<<<1, 1, 0, st>>>(counters, d_num_keys);
     return hipGetLastError() == hipSuccess ? SGR_OK : SGR_EHIP;
