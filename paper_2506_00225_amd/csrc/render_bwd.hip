@@ -667,8 +667,9 @@ struct ProjBwdArgs {
 // With ADAM the gradients are not written: each block stages its 256
 // Gaussians' gradients of one parameter tensor in LDS, a contiguous range of
 // that tensor, and the block applies the Adam update to the range with
-// coalesced loads of p, m and v, all of a thread's loads issued before its
-// stores.
+// coalesced loads of p, m and v.  Those rows are loaded one or two tensors
+// ahead of their update (the means' and scales' under the chain rule), so
+// their latency overlaps the work before it.
 constexpr int kAdamChunk = 8;
 
 template <int WM>
