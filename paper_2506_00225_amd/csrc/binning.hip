@@ -40,11 +40,32 @@ __global__ void publish_num_keys(const uint32_t* counters, int64_t* d_num_keys) 
 // FP64 reference and no contraction into FMA, so the tile keys agree bit for
 // bit; the compositing record is then rounded to fp32.  Returns the number
 // of tiles the pixel rectangle touches (0: culled).
-__device__ __forceinline__ uint32_t project_pair(const ProjectArgs& a, const ViewDev& vw, int v, int64_t i,
+// Where the projection takes Gaussian i's parameters from: the arrays, read
+// where each is first used (so a pair behind the camera reads only its
+// mean), or values loaded beforehand.
+struct ParamsAt {
+    const ProjectArgs& a;
+    int64_t i;
+    __device__ float mean(int r) const { return a.means[3 * i + r]; }
+    __device__ float quat(int r) const { return a.quats[4 * i + r]; }
+    __device__ float scale(int r) const { return a.scales[3 * i + r]; }
+    __device__ float opacity() const { return a.opacity[i]; }
+};
+struct GeomIn {
+    float m[3], q[4], s[3], o, rgb[3];
+    uint32_t count;
+    __device__ float mean(int r) const { return m[r]; }
+    __device__ float quat(int r) const { return q[r]; }
+    __device__ float scale(int r) const { return s[r]; }
+    __device__ float opacity() const { return o; }
+};
+
+template <typename In>
+__device__ __forceinline__ uint32_t project_pair(const ProjectArgs& a, const ViewDev& vw, int v, const In& in,
                                                  uint32_t* zbits, Proj* rec) {
 #pragma clang fp contract(off)
     uint32_t count = 0;
-    const double m0 = a.means[3 * i], m1 = a.means[3 * i + 1], m2 = a.means[3 * i + 2];
+    const double m0 = in.mean(0), m1 = in.mean(1), m2 = in.mean(2);
     double p[3];
 #pragma unroll
     for (int r = 0; r < 3; r++)
@@ -53,14 +74,14 @@ __device__ __forceinline__ uint32_t project_pair(const ProjectArgs& a, const Vie
     const float zf = (float)p[2];
     *zbits = __float_as_uint(zf);
     if (!(p[2] > (double)a.z_near)) return 0;
-    const double q0 = a.quats[4 * i], q1 = a.quats[4 * i + 1], q2 = a.quats[4 * i + 2], q3 = a.quats[4 * i + 3];
+    const double q0 = in.quat(0), q1 = in.quat(1), q2 = in.quat(2), q3 = in.quat(3);
     const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
     const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
     double Rq[9];
     Rq[0] = 1 - 2 * (y * y + z * z); Rq[1] = 2 * (x * y - w * z);     Rq[2] = 2 * (x * z + w * y);
     Rq[3] = 2 * (x * y + w * z);     Rq[4] = 1 - 2 * (x * x + z * z); Rq[5] = 2 * (y * z - w * x);
     Rq[6] = 2 * (x * z - w * y);     Rq[7] = 2 * (y * z + w * x);     Rq[8] = 1 - 2 * (x * x + y * y);
-    const double s[3] = {(double)a.scales[3 * i], (double)a.scales[3 * i + 1], (double)a.scales[3 * i + 2]};
+    const double s[3] = {(double)in.scale(0), (double)in.scale(1), (double)in.scale(2)};
     double S3[9];
 #pragma unroll
     for (int r = 0; r < 3; r++)
@@ -100,7 +121,7 @@ __device__ __forceinline__ uint32_t project_pair(const ProjectArgs& a, const Vie
     S2[3] += lp;
     const double sxx = S2[0], sxy = 0.5 * (S2[1] + S2[2]), syy = S2[3];
     const double det = sxx * syy - sxy * sxy;
-    const double o = a.opacity[i];
+    const double o = in.opacity();
     if (!(det > 0 && o >= (double)a.alpha_min)) return 0;
     const double mx = fx * p[0] / zz + (double)vw.cx, my = fy * p[1] / zz + (double)vw.cy;
     const double qmax = 2.0 * log(o / (double)a.alpha_min);
@@ -152,7 +173,7 @@ __global__ __launch_bounds__(256, 6) void project_kernel(ProjectArgs a, ViewChun
         const int64_t i = lin - (int64_t)v * a.n;
         a.gp_of_lin[lin] = kInvalid;
         uint32_t zb;
-        cnt = project_pair(a, a.init ? ch.v[v] : a.views[v], v, i, &zb, nullptr);
+        cnt = project_pair(a, a.init ? ch.v[v] : a.views[v], v, ParamsAt{a, i}, &zb, nullptr);
         a.count[lin] = cnt;
         a.zbits[lin] = zb;
     }
@@ -176,20 +197,22 @@ struct GatherRow {
     static constexpr int kBytes = ((KM + 3) & ~3) + 4;  // class / list-index bytes per row
 };
 
-// The top-k half of record g: stored values, classes, list indices and the
-// class-rank table.  Returns whether the list repeats a class.
+// The values and class indices (four per word) of pair lin's top-k list.
 template <int KT>
-__device__ __forceinline__ bool build_topk(const GatherArgs& a, uint32_t g, uint32_t lin, float* rv, uint8_t* rc,
-                                           uint8_t* ro) {
+struct TopkIn {
+    static constexpr int KM = KT > 0 ? KT : kMaxK;
+    float vin[KM];
+    uint32_t words[(KM + 3) / 4];
+};
+template <int KT>
+__device__ __forceinline__ void load_topk(const GatherArgs& a, uint32_t lin, TopkIn<KT>& t) {
     const int v = (int)(lin / (uint64_t)a.n);
     const int64_t i = (int64_t)lin - (int64_t)v * a.n;
     const int k = KT > 0 ? KT : a.k;
-    const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
     constexpr int KM = KT > 0 ? KT : kMaxK;
     constexpr int KWM = (KM + 3) / 4;
-    // values and class indices (four per word) of the Gaussian's top-k list
     const float* sv = a.sem_val + i * k;
-    float vin[KM];
+    float* vin = t.vin;
     if constexpr (KT > 0 && (KT & 3) == 0) {
 #pragma unroll
         for (int m = 0; m < KT; m += 4) {
@@ -200,7 +223,7 @@ __device__ __forceinline__ bool build_topk(const GatherArgs& a, uint32_t g, uint
 #pragma unroll
         for (int m = 0; m < KM; m++) vin[m] = m < k ? sv[m] : 0.f;
     }
-    uint32_t words[KWM];
+    uint32_t* words = t.words;
     const uint8_t* si = a.sem_idx + i * k;
     if constexpr (KT > 0 && (KT & 3) == 0) {
 #pragma unroll
@@ -215,6 +238,20 @@ __device__ __forceinline__ bool build_topk(const GatherArgs& a, uint32_t g, uint
             words[w] = word;
         }
     }
+}
+
+// The top-k half of record g from its loaded list: stored values, classes,
+// list indices and the class-rank table.  Returns whether the list repeats
+// a class.
+template <int KT>
+__device__ __forceinline__ bool build_topk(const GatherArgs& a, uint32_t g, const TopkIn<KT>& t, float* rv,
+                                           uint8_t* rc, uint8_t* ro) {
+    const int k = KT > 0 ? KT : a.k;
+    const int kw = (KT > 0 ? ((KT + 3) & ~3) : a.kpad) >> 2;
+    constexpr int KM = KT > 0 ? KT : kMaxK;
+    constexpr int KWM = (KM + 3) / 4;
+    const float* vin = t.vin;
+    const uint32_t* words = t.words;
     bool bad = false, dup = false;
     uint32_t cls[KM];
     uint64_t cnt = 0;  // entries per accumulator block, one byte per block (at most 8 blocks, 32 entries)
@@ -305,20 +342,37 @@ __device__ __forceinline__ bool build_topk(const GatherArgs& a, uint32_t g, uint
     return dup;
 }
 
-// The geometric half of record g: the projection (the compositing record,
-// colour and depth) and the pair's tile count and depth key.
-__device__ __forceinline__ void build_geom(const GatherArgs& a, uint32_t g, uint32_t lin, bool dup) {
+// The parameters, colour and tile count of pair lin.
+__device__ __forceinline__ void load_geom(const GatherArgs& a, uint32_t lin, GeomIn& t) {
     const int v = (int)(lin / (uint64_t)a.n);
     const int64_t i = (int64_t)lin - (int64_t)v * a.n;
+    const ProjectArgs& pa = a.proj;
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        t.m[r] = pa.means[3 * i + r];
+        t.s[r] = pa.scales[3 * i + r];
+        t.rgb[r] = a.rgb[3 * i + r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) t.q[r] = pa.quats[4 * i + r];
+    t.o = pa.opacity[i];
+    t.count = a.count[lin];
+}
+
+// The geometric half of record g from its loaded parameters: the
+// projection (the compositing record, colour and depth) and the pair's tile
+// count and depth key.
+__device__ __forceinline__ void build_geom(const GatherArgs& a, uint32_t g, uint32_t lin, bool dup, const GeomIn& t) {
+    const int v = (int)(lin / (uint64_t)a.n);
     Proj p;
     uint32_t zb;
-    project_pair(a.proj, a.proj.views[v], v, i, &zb, &p);
+    project_pair(a.proj, a.proj.views[v], v, t, &zb, &p);
     a.zkeys[g] = zb;
     a.pair_lin[g] = lin;
-    a.scol[g] = make_float4(a.rgb[3 * i], a.rgb[3 * i + 1], a.rgb[3 * i + 2], p.r2.z);
+    a.scol[g] = make_float4(t.rgb[0], t.rgb[1], t.rgb[2], p.r2.z);
     p.r2.w = __uint_as_float(__float_as_uint(p.r2.w) | (dup ? 0x80000000u : 0u));
     a.srec[g] = p;
-    a.tcount[g] = a.count[lin];
+    a.tcount[g] = t.count;
     a.gp_of_lin[lin] = g;
 }
 
@@ -335,7 +389,7 @@ constexpr uint32_t kGatherSumBlocks = 512;  // above this many workgroups the bl
 constexpr int kGatherItems = kScanTile / kGatherThreads;
 
 template <int KT>
-__global__ __launch_bounds__(kGatherThreads, KT > 0 ? 4 : 1) void compact_gather(GatherArgs a) {
+__global__ __launch_bounds__(kGatherThreads, KT > 0 ? 3 : 1) void compact_gather(GatherArgs a) {
     constexpr int NW = kGatherThreads / 64;
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t s_before, s_nloc;
@@ -399,11 +453,27 @@ __global__ __launch_bounds__(kGatherThreads, KT > 0 ? 4 : 1) void compact_gather
     __syncthreads();
     const uint32_t nloc = s_nloc, before = s_before;
     // two passes over this thread's records (the same ones in both), each
-    // with fewer live registers than one pass that did both halves
-    for (uint32_t j = tid; j < nloc; j += kGatherThreads)
-        s_dup[j] = build_topk<KT>(a, before + j, s_lin[j], s_rv + tid * Row::kVals, s_rc + tid * Row::kBytes,
-                                  s_ro + tid * Row::kBytes) ? 1 : 0;
-    for (uint32_t j = tid; j < nloc; j += kGatherThreads) build_geom(a, before + j, s_lin[j], s_dup[j] != 0);
+    // with fewer live registers than one pass that did both halves; each
+    // loads the next record's inputs before it builds the current one
+    {
+        TopkIn<KT> cur, nxt;
+        if ((uint32_t)tid < nloc) load_topk<KT>(a, s_lin[tid], cur);
+        for (uint32_t j = tid; j < nloc; j += kGatherThreads) {
+            if (j + kGatherThreads < nloc) load_topk<KT>(a, s_lin[j + kGatherThreads], nxt);
+            s_dup[j] = build_topk<KT>(a, before + j, cur, s_rv + tid * Row::kVals, s_rc + tid * Row::kBytes,
+                                      s_ro + tid * Row::kBytes) ? 1 : 0;
+            cur = nxt;
+        }
+    }
+    {
+        GeomIn cur, nxt;
+        if ((uint32_t)tid < nloc) load_geom(a, s_lin[tid], cur);
+        for (uint32_t j = tid; j < nloc; j += kGatherThreads) {
+            if (j + kGatherThreads < nloc) load_geom(a, s_lin[j + kGatherThreads], nxt);
+            build_geom(a, before + j, s_lin[j], s_dup[j] != 0, cur);
+            cur = nxt;
+        }
+    }
 }
 
 // --------------------------------------------------------------- keys
