@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kGatherThreads, KT > 0 ? 3 : 1) void compact_gather
     // two passes over this thread's records (the same ones in both), each
     // with fewer live registers than one pass that did both halves; each
     // loads the next record's inputs before it builds the current one
-    {
+    if constexpr (KT > 0) {
         TopkIn<KT> cur, nxt;
         if ((uint32_t)tid < nloc) load_topk<KT>(a, s_lin[tid], cur);
         for (uint32_t j = tid; j < nloc; j += kGatherThreads) {
@@ -463,6 +463,13 @@ __global__ __launch_bounds__(kGatherThreads, KT > 0 ? 3 : 1) void compact_gather
             s_dup[j] = build_topk<KT>(a, before + j, cur, s_rv + tid * Row::kVals, s_rc + tid * Row::kBytes,
                                       s_ro + tid * Row::kBytes) ? 1 : 0;
             cur = nxt;
+        }
+    } else {  // (a run-time list length: lists of up to kMaxK entries, loaded one at a time)
+        for (uint32_t j = tid; j < nloc; j += kGatherThreads) {
+            TopkIn<KT> cur;
+            load_topk<KT>(a, s_lin[j], cur);
+            s_dup[j] = build_topk<KT>(a, before + j, cur, s_rv + tid * Row::kVals, s_rc + tid * Row::kBytes,
+                                      s_ro + tid * Row::kBytes) ? 1 : 0;
         }
     }
     {
