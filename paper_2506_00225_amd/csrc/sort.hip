@@ -199,11 +199,11 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t base = blockIdx.x * TILE;
-    // With few workgroups (the small-tile variant), every round's items are
-    // loaded up front, so the rounds (each ends at a barrier) do not each
-    // wait out a global load.  With many, the registers that would take
-    // cost more occupancy than the loads cost time.
-    constexpr bool kPre = !SCANNED;
+    // Every round's items are loaded up front, so the rounds (each ends at
+    // a barrier) do not each wait out a global load, except with the
+    // longest blocks (16 items a thread), where the registers that would
+    // take cost more occupancy than the loads cost time.
+    constexpr bool kPre = !SCANNED || ITEMS <= 8;
     uint32_t kr[kPre ? ITEMS : 1], vr[kPre ? ITEMS : 1];
     if constexpr (kPre) {
 #pragma unroll
