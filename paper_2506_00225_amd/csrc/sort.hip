@@ -200,25 +200,22 @@ __global__ __launch_bounds__(256) void radix_scatter(const uint32_t* __restrict_
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t base = blockIdx.x * TILE;
     // Every round's items are loaded up front, so the rounds (each ends at
-    // a barrier) do not each wait out a global load, except with the
-    // longest blocks (16 items a thread), where the registers that would
-    // take cost more occupancy than the loads cost time.
-    constexpr bool kPre = !SCANNED || ITEMS <= 8;
-    uint32_t kr[kPre ? ITEMS : 1], vr[kPre ? ITEMS : 1];
-    if constexpr (kPre) {
+    // a barrier) do not each wait out a global load.  (With 16 items a
+    // thread this costs one or two waves per SIMD, and still measured
+    // faster.)
+    uint32_t kr[ITEMS], vr[ITEMS];
 #pragma unroll
-        for (int r = 0; r < ITEMS; r++) {
-            const uint32_t i = base + r * 256 + tid;
-            kr[r] = i < n ? kin[i] : 0u;
-            vr[r] = i < n ? (vin ? vin[i] : i) : 0u;
-        }
+    for (int r = 0; r < ITEMS; r++) {
+        const uint32_t i = base + r * 256 + tid;
+        kr[r] = i < n ? kin[i] : 0u;
+        vr[r] = i < n ? (vin ? vin[i] : i) : 0u;
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; r++) {
         const uint32_t i = base + r * 256 + tid;
         const bool valid = i < n;
-        const uint32_t key = kPre ? kr[r] : (valid ? kin[i] : 0u);
-        const uint32_t val = kPre ? vr[r] : (valid ? (vin ? vin[i] : i) : 0u);
+        const uint32_t key = kr[r];
+        const uint32_t val = vr[r];
         const uint32_t d = (key >> shift) & mask;
         uint64_t match = __ballot(valid);
 #pragma unroll
